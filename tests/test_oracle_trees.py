@@ -1,0 +1,221 @@
+"""Oracle pins for the elimination lists, the task DAG and the schedule.
+
+Every expected number here is printed in the paper (Tables 2-5, Theorem 1,
+Propositions 1 and 2, the total-work identity of Sec. 2.2) or is an
+invariant the paper states (validity conditions of Sec. 2.2, Lemma 1, the
+list identities of PlasmaTree in Sec. 3.2).
+"""
+
+import math
+import random
+
+import pytest
+
+from conftest import load_blocks, load_rows, lower_table
+from oracle import dag, trees
+
+TT = dag.KERN_TT
+TS = dag.KERN_TS
+
+
+# ---- Table 2: coarse-grain time-steps, 15 x 6 ------------------------------
+
+def test_table2_sameh_kuck_and_greedy_coarse():
+    blocks = load_blocks("table2_coarse_15x6.txt")
+    for name, tree in (("Sameh-Kuck", trees.SAMEH_KUCK), ("Greedy", trees.GREEDY)):
+        got = trees.coarse_times(15, 6, trees.elim_list(15, 6, tree))
+        assert got == lower_table(blocks[name]), name
+
+
+def test_table2_fibonacci_closed_form():
+    blocks = load_blocks("table2_coarse_15x6.txt")
+    assert trees.fibonacci_coarse(15, 6) == lower_table(blocks["Fibonacci"])
+
+
+def test_fibonacci_closed_form_is_a_valid_coarse_schedule():
+    # The closed-form steps respect the coarse model's dependences, so the
+    # list run as soon as possible never finishes a tile later.
+    for p in range(2, 30):
+        for q in range(1, p + 1):
+            closed = trees.fibonacci_coarse(p, q)
+            asap = trees.coarse_times(p, q, trees.fibonacci_tree(p, q))
+            assert all(asap[key] <= closed[key] for key in closed)
+
+
+# ---- Table 3: tiled zeroing times, 15 x 6, TT kernels ----------------------
+
+@pytest.mark.parametrize("name,tree,bs", [
+    ("FlatTree", trees.FLAT, 1), ("Fibonacci", trees.FIBONACCI, 1),
+    ("Greedy", trees.GREEDY, 1), ("BinaryTree", trees.BINARY, 1),
+    ("PlasmaTree BS=5", trees.PLASMA, 5)])
+def test_table3_tiled_times(name, tree, bs):
+    want = lower_table(load_blocks("table3_tiled_15x6.txt")[name])
+    assert dag.zero_times(15, 6, tree, bs, TT) == want
+
+
+# ---- Table 4(a): Greedy on 15 x 3 (and its first two columns, 15 x 2) -----
+
+def test_table4a_greedy():
+    want = lower_table(load_blocks("table4a_15x3.txt")["Greedy"])
+    assert dag.zero_times(15, 3, trees.GREEDY, 1, TT) == want
+    got2 = dag.zero_times(15, 2, trees.GREEDY, 1, TT)
+    assert got2 == {key: v for key, v in want.items() if key[1] <= 2}
+    assert max(want.values()) == 64
+
+
+# ---- Table 4(b): Greedy critical paths up to 128 x 32 ----------------------
+
+def test_table4b_greedy_cp():
+    for p, q, greedy, _asap in load_rows("table4b_greedy_asap.txt"):
+        if p * q * q > 128 * 32 * 32:
+            continue  # 128x64 and 128x128 are checked against the C++ planner
+        assert dag.critical_path(p, q, trees.GREEDY, 1, TT) == greedy, (p, q)
+
+
+# ---- Table 5: p = 40 ---------------------------------------------------------
+
+def test_table5_greedy_and_fibonacci():
+    for p, q, greedy, _pt, _bs, fib in load_rows("table5_p40.txt"):
+        assert dag.critical_path(p, q, trees.GREEDY, 1, TT) == greedy, q
+        assert dag.critical_path(p, q, trees.FIBONACCI, 1, TT) == fib, q
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 5, 6, 11, 20])
+def test_table5_best_plasmatree(q):
+    row = [r for r in load_rows("table5_p40.txt") if r[1] == q][0]
+    assert dag.best_plasma_bs(40, q, TT) == (row[3], row[4])
+
+
+# ---- Closed forms -----------------------------------------------------------
+
+def test_theorem1_flattree_tt():
+    for p in range(1, 26):
+        for q in range(1, p + 1):
+            cp = dag.critical_path(p, q, trees.SAMEH_KUCK, 1, TT)
+            if q == 1:
+                want = 2 * p + 2
+            elif p > q:
+                want = 6 * p + 16 * q - 22
+            else:
+                want = 22 * p - 24
+            assert cp == want, (p, q)
+
+
+def test_proposition2_flattree_ts():
+    for p in range(1, 26):
+        for q in range(1, p + 1):
+            cp = dag.critical_path(p, q, trees.FLAT, 1, TS)
+            if q == 1:
+                want = 6 * p - 2
+            elif p > q:
+                want = 12 * p + 18 * q - 32
+            else:
+                want = 30 * p - 34
+            assert cp == want, (p, q)
+
+
+def test_proposition1_binarytree_powers_of_two():
+    for lp in range(1, 7):
+        for lq in range(0, lp):
+            p, q = 2 ** lp, 2 ** lq
+            want = (10 + 6 * lp) * q - 4 * lp - 6
+            assert dag.critical_path(p, q, trees.BINARY, 1, TT) == want, (p, q)
+
+
+def test_theorem1_upper_bounds():
+    for p in range(2, 41):
+        for q in range(1, p + 1, 3):
+            assert dag.critical_path(p, q, trees.GREEDY) <= 22 * q + 6 * math.ceil(math.log2(p))
+            assert dag.critical_path(p, q, trees.FIBONACCI) <= 22 * q + 6 * math.ceil(math.sqrt(2 * p))
+
+
+def test_theorem1_lower_bound_where_it_holds():
+    # The bound 22q - 30 fails for near-square shapes (Table 5 itself gives
+    # 826 < 850 at p = q = 40); it is checked only where p - q >= 7.
+    for p in range(9, 40, 3):
+        for q in range(2, p - 6, 2):
+            for tree in (trees.GREEDY, trees.FIBONACCI, trees.BINARY):
+                assert dag.critical_path(p, q, tree) >= 22 * q - 30
+
+
+def test_table5_contradicts_lower_bound_near_square():
+    rows = {r[1]: r for r in load_rows("table5_p40.txt")}
+    assert rows[40][2] < 22 * 40 - 30
+
+
+# ---- Identities and invariants ---------------------------------------------
+
+def test_list_identities():
+    for p in range(1, 20):
+        for q in range(1, p + 1):
+            assert trees.plasma_tree(p, q, 1) == trees.binary_tree(p, q)
+            assert trees.plasma_tree(p, q, p) == trees.flat_tree(p, q)
+            assert trees.elim_list(p, q, trees.SAMEH_KUCK) == trees.flat_tree(p, q)
+
+
+def test_greedy_list_c1_first_round():
+    # Algorithm 4 on 8 x 4: the first round only touches column 1 and pairs
+    # the bottom floor(8/2) rows with the four rows above them.
+    lst = trees.greedy_tree(8, 4)
+    assert lst[:4] == [(8, 4, 1), (7, 3, 1), (6, 2, 1), (5, 1, 1)]
+
+
+def _all_lists(p, q):
+    yield trees.flat_tree(p, q)
+    yield trees.binary_tree(p, q)
+    yield trees.fibonacci_tree(p, q)
+    yield trees.greedy_tree(p, q)
+    for bs in range(1, p + 1):
+        yield trees.plasma_tree(p, q, bs)
+
+
+def test_validity_and_lemma1():
+    for p in range(1, 18):
+        for q in range(1, p + 1):
+            for lst in _all_lists(p, q):
+                assert trees.validate(p, q, lst) == []
+                assert len(lst) == sum(p - k for k in range(1, min(p, q) + 1))
+
+
+def test_validator_rejects_bad_lists():
+    lst = trees.flat_tree(6, 3)
+    assert trees.validate(6, 3, lst[:-1])            # a tile never zeroed
+    swapped = list(lst)
+    swapped[0], swapped[6] = swapped[6], swapped[0]  # column 2 before column 1
+    assert trees.validate(6, 3, swapped)
+    # pivot already zeroed: zero (2,1) with row 1, then use row 2 as pivot
+    assert trees.validate(3, 1, [(2, 1, 1), (3, 2, 1)])
+
+
+def test_total_work_identity():
+    rng = random.Random(7)
+    for _ in range(40):
+        p = rng.randint(1, 24)
+        q = rng.randint(1, p)
+        for lst in _all_lists(p, q):
+            for kern in (TT, TS):
+                tasks, _ = dag.build_tasks(p, q, lst, kern)
+                assert dag.total_work_units(tasks) == 6 * p * q * q - 2 * q ** 3
+
+
+def test_task_counts():
+    for p in range(1, 14):
+        for q in range(1, p + 1):
+            tasks, _ = dag.build_tasks(p, q, trees.greedy_tree(p, q), TT)
+            want = sum((p - k + 1) * (q - k + 1) + (p - k) * (q - k + 1)
+                       for k in range(1, min(p, q) + 1))
+            if p == q:
+                want -= 0
+            assert len(tasks) == want, (p, q)
+            tasks, _ = dag.build_tasks(p, q, trees.flat_tree(p, q), TS)
+            assert len(tasks) == sum((q - k + 1) * (p - k + 1) for k in range(1, min(p, q) + 1))
+
+
+def test_dag_edges_respect_emission_order_and_tiles():
+    for p, q in ((8, 4), (7, 7), (12, 3)):
+        for tree in (trees.GREEDY, trees.BINARY, trees.FLAT):
+            for kern in (TT, TS):
+                tasks, preds = dag.build_tasks(p, q, trees.elim_list(p, q, tree), kern)
+                for t, ps in enumerate(preds):
+                    assert all(d < t for d in ps)
+                    assert len(ps) <= 3
