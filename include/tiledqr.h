@@ -1,0 +1,208 @@
+/*
+ * tiledqr.h -- C ABI of the MI355X tiled QR library.
+ *
+ * The library factors an m x n FP64 matrix A = QR (m >= n) with the tiled
+ * algorithms of Bouwmeester, Jacquelin, Langou and Robert, "Tiled QR
+ * factorization algorithms" (2011): the matrix is cut into p x q square tiles
+ * of size nb (m = p nb, n = q nb, Remark 1 of Sec. 3.2), an elimination list
+ * chosen by a reduction tree (Sec. 3) says which row zeroes which tile, and
+ * the six tile kernels of Sec. 2.1 (Table 1) run on the GPU in the
+ * dependency order of Algorithms 2 and 3 as soon as their inputs are ready
+ * (Sec. 2.3).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are column-major with a leading dimension (LAPACK style).
+ *   - "device" pointers are HIP device memory on the current device; "host"
+ *     pointers are ordinary host memory.
+ *   - stream is a hipStream_t passed as void*; NULL means the default stream.
+ *     Device work is enqueued on it asynchronously unless stated otherwise.
+ *   - Arguments are checked on the host before any launch; on an error the
+ *     call returns a negative tqr_status, enqueues nothing and writes no
+ *     output.  The library never aborts and never prints.
+ *   - A factor handle may be used on one stream at a time; distinct handles
+ *     are independent.
+ */
+#ifndef TILEDQR_H
+#define TILEDQR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TQR_OK = 0,
+  TQR_EINVAL = -1,        /* invalid argument (checked on the host)         */
+  TQR_ENOMEM = -2,        /* device or host allocation failed               */
+  TQR_EHIP = -3,          /* a HIP runtime call failed                      */
+  TQR_ENOTCONV = -4,      /* refinement did not reach its tolerance         */
+  TQR_EUNSUPPORTED = -5,  /* valid but not implemented (e.g. nb too large)  */
+  TQR_EEXEC = -6          /* the device executor stopped (wait time limit)  */
+} tqr_status;
+
+/* Reduction trees (Sec. 3.1 and Sec. 3.2).  FLAT and SAMEH_KUCK produce the
+ * same elimination list (the tiled Sameh-Kuck algorithm is PLASMA's
+ * FlatTree); they differ only in their default kernel family. */
+typedef enum {
+  TQR_TREE_FLAT = 0,
+  TQR_TREE_SAMEH_KUCK = 1,
+  TQR_TREE_BINARY = 2,
+  TQR_TREE_FIBONACCI = 3,
+  TQR_TREE_GREEDY = 4,
+  TQR_TREE_PLASMA = 5      /* needs bs in [1, p] (domain size)             */
+} tqr_tree;
+
+/* Kernel family (Sec. 2.1): TT = triangle on top of triangle (Algorithm 3),
+ * TS = triangle on top of square (Algorithm 2).  DEFAULT is TS for
+ * TQR_TREE_FLAT (PLASMA's algorithm, Proposition 2) and TT otherwise.  With
+ * TS on a tree other than FlatTree, a killed row that is itself a pivot of
+ * its column is eliminated with TT kernels (a TS kernel needs a square tile
+ * under the triangle). */
+typedef enum { TQR_KERN_DEFAULT = 0, TQR_KERN_TT = 1, TQR_KERN_TS = 2 } tqr_kernels;
+
+/* Arithmetic of the trailing-update kernels (UNMQR, TSMQR, TTMQR).  Panel
+ * kernels (GEQRT, TSQRT, TTQRT: norms, reflector scaling, T factors) are
+ * always FP64 and tiles are always stored in FP64.  F32 / BF16 round the
+ * update operands to that format, multiply on the matrix cores with FP32
+ * accumulation, and subtract the FP32 result from the FP64 tile. */
+typedef enum { TQR_UPD_F64 = 0, TQR_UPD_F32 = 1, TQR_UPD_BF16 = 2 } tqr_update_prec;
+
+typedef struct {
+  int64_t m, n;     /* matrix size; m % nb == 0, n % nb == 0, m >= n >= nb */
+  int32_t nb;       /* tile size: 32, 64, 128 or 256                       */
+  int32_t ib;       /* inner block size: 0 = default (32); must be 32      */
+  int32_t tree;     /* tqr_tree                                            */
+  int32_t bs;       /* PlasmaTree domain size, ignored for other trees     */
+  int32_t kernels;  /* tqr_kernels                                         */
+  int32_t upd;      /* tqr_update_prec                                     */
+} tqr_opts;
+
+typedef struct tqr_factors tqr_factors;   /* opaque, library-owned */
+
+/* Human-readable name of a status code (static string). */
+const char* tiledqr_strerror(int status);
+
+/* Last HIP error code seen by the calling thread (0 if none). */
+int tiledqr_last_hip_error(void);
+
+/* ---- factorization --------------------------------------------------- */
+
+/* Factor A (device, m x n, column-major, lda >= m) into *F.
+ * Sec. 2 (the tiled algorithm), Sec. 2.3 (execution as soon as possible).
+ * A is only read; the handle owns a tile-layout copy holding R, the
+ * reflectors V and the compact-WY T factors.  On success *F must later be
+ * released with tiledqr_destroy.  The factorization is enqueued on stream;
+ * errors of the device executor are reported by tiledqr_sync.
+ * Errors: TQR_EINVAL (null pointer, m % nb, n % nb, m < n, nb or ib not
+ * supported, bs outside [1, p] for PlasmaTree, lda < m), TQR_ENOMEM,
+ * TQR_EHIP. */
+int tiledqr_factor(const tqr_opts* opts, const double* A, int64_t lda,
+                   tqr_factors** F, void* stream);
+
+/* Re-factor a new matrix of the same shape into an existing handle (no
+ * allocation, no host planning).  Same errors as tiledqr_factor. */
+int tiledqr_refactor(tqr_factors* F, const double* A, int64_t lda, void* stream);
+
+/* Wait for the handle's stream and report a device executor error
+ * (TQR_EEXEC) if one occurred in the last factorization. */
+int tiledqr_sync(tqr_factors* F);
+
+/* B (device, m x nrhs, ldb >= m) <- Q^T B (trans 'T') or Q B (trans 'N').
+ * Q^T applies the reflector sets of the panel tasks in task order, Q in
+ * reverse order (Sec. 1).  Errors: TQR_EINVAL (null, ldb < m, nrhs < 0,
+ * trans), TQR_EHIP. */
+int tiledqr_apply_q(const tqr_factors* F, char trans, double* B, int64_t ldb,
+                    int64_t nrhs, void* stream);
+
+/* R (device, n x n, ldr >= n) <- the upper triangular factor (zeros below
+ * the diagonal).  Errors: TQR_EINVAL, TQR_EHIP. */
+int tiledqr_get_r(const tqr_factors* F, double* R, int64_t ldr, void* stream);
+
+/* Packed factor (device, m x n, ld >= m): the handle's tiles in column-major
+ * matrix order, i.e. R, the GEQRT reflectors (strict lower part of each
+ * triangularized tile) and the TT / TS reflectors (upper triangle or whole
+ * of each zeroed tile), exactly as the kernels left them. */
+int tiledqr_get_packed(const tqr_factors* F, double* out, int64_t ld, void* stream);
+
+/* Householder scalars (device, 2 * p * q * nb doubles): tau_geqrt for tile
+ * (r, c) (0-based) at ((c * p + r) * nb), then tau of the TT / TS kernel
+ * that zeroed tile (i, c) at (p * q * nb + (c * p + i) * nb). */
+int tiledqr_get_tau(const tqr_factors* F, double* tau, void* stream);
+
+/* Release a handle (synchronizes its stream first).  NULL is accepted. */
+int tiledqr_destroy(tqr_factors* F);
+
+/* ---- least squares ---------------------------------------------------- */
+
+typedef struct {
+  double tol;        /* target backward error (e.g. 1e-12); <= 0: no refinement */
+  int32_t max_iter;  /* refinement iterations (default 30 if <= 0)          */
+  int32_t method;    /* 0 auto, 1 classical (square), 2 augmented system    */
+} tqr_refine;
+
+typedef struct {      /* host memory, filled by tiledqr_lstsq */
+  int32_t iters;
+  int32_t converged;
+  double backward_err;  /* max over right-hand sides                        */
+} tqr_refine_info;
+
+/* X (device, n x nrhs, ldx >= n) <- argmin ||B - A X|| using the factors F
+ * (Sec. 1: x = R^{-1} (Q^T b)(1:n)).  When r != NULL and r->tol > 0 the
+ * solution is refined with FP64 residuals computed on the GPU against the
+ * original matrix A0 (device, m x n, lda >= m), which the caller keeps
+ * unchanged until the call returns.  Square systems use classical
+ * refinement x <- x + R^{-1} Q^T (b - A0 x); tall systems refine the
+ * augmented system [I A0; A0^T 0][r; x] = [b; 0] (Bjorck 1967) with the same
+ * factors.  The backward error is ||b - A x|| / (||A||_F ||x|| + ||b||)
+ * for square systems and ||A^T r|| / (||A||_F ||r||) for tall ones.
+ * Synchronizes the stream once per refinement iteration.  Returns
+ * TQR_ENOTCONV (info filled, X holding the best iterate) if the tolerance is
+ * not reached within max_iter or the error stops halving over three
+ * iterations.  Errors: TQR_EINVAL, TQR_ENOMEM, TQR_EHIP. */
+int tiledqr_lstsq(const tqr_factors* F, const double* A0, int64_t lda,
+                  const double* B, int64_t ldb, int64_t nrhs,
+                  double* X, int64_t ldx, const tqr_refine* r,
+                  tqr_refine_info* info, void* stream);
+
+/* ---- batched ------------------------------------------------------------ */
+
+/* Factor nprob independent matrices in one persistent launch (all problems'
+ * task graphs are concatenated and walked by one kernel).  opts, A, lda and
+ * F are host arrays of length nprob; A[i] are device pointers.  Each F[i] is
+ * an ordinary handle usable with every other entry point and released with
+ * tiledqr_destroy.  All problems must share upd.
+ * Errors: as tiledqr_factor for each problem. */
+int tiledqr_factor_batched(int32_t nprob, const tqr_opts* opts,
+                           const double* const* A, const int64_t* lda,
+                           tqr_factors** F, void* stream);
+
+/* ---- host-only planning (no GPU needed) -------------------------------- */
+
+/* Elimination list of a tree (Sec. 3): triples (i, piv, k), 1-based, in the
+ * library's emission order (column by column, except Greedy, which follows
+ * the rounds of Algorithm 4).  out (host, 3 * nelim int32) may be NULL to
+ * query *nelim.  Errors: TQR_EINVAL (p < q, q < 1, bad tree or bs). */
+int tiledqr_elim_list(int32_t p, int32_t q, int32_t tree, int32_t bs,
+                      int32_t* out, int64_t* nelim);
+
+/* Kernel tasks of the list (Algorithms 2 and 3) with their unbounded-
+ * processor ASAP schedule in units of nb^3/3 flops (Table 1 weights,
+ * Sec. 2.3).  tasks (host, 7 * ntasks int32) = (kind, i, piv, k, j, start,
+ * finish) with kind 0 GEQRT, 1 UNMQR, 2 TSQRT, 3 TSMQR, 4 TTQRT, 5 TTMQR and
+ * 0 in unused fields; may be NULL to query *ntasks.  *cp = critical path.
+ * Errors: TQR_EINVAL. */
+int tiledqr_schedule(int32_t p, int32_t q, int32_t tree, int32_t bs, int32_t kernels,
+                     int32_t* tasks, int64_t* ntasks, int64_t* cp);
+
+/* Predecessors of each task of tiledqr_schedule in CSR form: ptr (host,
+ * ntasks + 1 int64) and idx (host, ptr[ntasks] int32, ascending per task).
+ * idx may be NULL to query the sizes (ptr still filled). */
+int tiledqr_task_preds(int32_t p, int32_t q, int32_t tree, int32_t bs, int32_t kernels,
+                       int64_t* ptr, int32_t* idx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TILEDQR_H */

@@ -1,0 +1,105 @@
+"""ctypes declarations of libtiledqr.so (names and arguments as in
+include/tiledqr.h).  Loading fails loudly if the library has not been built."""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+lib_path = os.path.join(HERE, "libtiledqr.so")
+
+TREE_FLAT, TREE_SAMEH_KUCK, TREE_BINARY, TREE_FIBONACCI, TREE_GREEDY, TREE_PLASMA = range(6)
+KERN_DEFAULT, KERN_TT, KERN_TS = 0, 1, 2
+UPD_F64, UPD_F32, UPD_BF16 = 0, 1, 2
+TQR_OK, TQR_EINVAL, TQR_ENOMEM, TQR_EHIP, TQR_ENOTCONV, TQR_EUNSUPPORTED, TQR_EEXEC = 0, -1, -2, -3, -4, -5, -6
+
+if not os.path.exists(lib_path):
+    raise ImportError("libtiledqr.so is not built (run python -m paper_1104_4475_amd.build): %s" % lib_path)
+lib = ctypes.CDLL(lib_path)
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("nb", ctypes.c_int32), ("ib", ctypes.c_int32),
+                ("tree", ctypes.c_int32), ("bs", ctypes.c_int32), ("kernels", ctypes.c_int32),
+                ("upd", ctypes.c_int32)]
+
+
+class RefineOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("method", ctypes.c_int32)]
+
+
+class RefineInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("backward_err", ctypes.c_double)]
+
+
+class TiledQRError(RuntimeError):
+    def __init__(self, status, where=""):
+        self.status = status
+        msg = lib.tiledqr_strerror(status).decode()
+        if status == TQR_EHIP:
+            msg += " (hipError %d)" % lib.tiledqr_last_hip_error()
+        super().__init__("%s: %s (%d)" % (where, msg, status))
+
+
+_vp, _i32, _i64, _dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
+_P = ctypes.POINTER
+
+_sigs = {
+    "tiledqr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "tiledqr_last_hip_error": (ctypes.c_int, []),
+    "tiledqr_factor": (ctypes.c_int, [_P(Opts), _dp, _i64, _P(_vp), _vp]),
+    "tiledqr_refactor": (ctypes.c_int, [_vp, _dp, _i64, _vp]),
+    "tiledqr_sync": (ctypes.c_int, [_vp]),
+    "tiledqr_apply_q": (ctypes.c_int, [_vp, ctypes.c_char, _dp, _i64, _i64, _vp]),
+    "tiledqr_get_r": (ctypes.c_int, [_vp, _dp, _i64, _vp]),
+    "tiledqr_get_packed": (ctypes.c_int, [_vp, _dp, _i64, _vp]),
+    "tiledqr_get_tau": (ctypes.c_int, [_vp, _dp, _vp]),
+    "tiledqr_destroy": (ctypes.c_int, [_vp]),
+    "tiledqr_lstsq": (ctypes.c_int, [_vp, _dp, _i64, _dp, _i64, _i64, _dp, _i64, _P(RefineOpts), _P(RefineInfo),
+                                     _vp]),
+    "tiledqr_factor_batched": (ctypes.c_int, [_i32, _P(Opts), _P(_vp), _P(_i64), _P(_vp), _vp]),
+    "tiledqr_elim_list": (ctypes.c_int, [_i32, _i32, _i32, _i32, _P(_i32), _P(_i64)]),
+    "tiledqr_schedule": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32, _P(_i32), _P(_i64), _P(_i64)]),
+    "tiledqr_task_preds": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32, _P(_i64), _P(_i32)]),
+}
+for _name, (_res, _args) in _sigs.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+    globals()[_name] = _f
+
+
+def check(status, where):
+    if status != TQR_OK:
+        raise TiledQRError(status, where)
+
+
+def elim_list(p, q, tree, bs=1):
+    """Elimination list as an int32 array of shape (nelim, 3), 1-based."""
+    n = ctypes.c_int64()
+    check(tiledqr_elim_list(p, q, tree, bs, None, ctypes.byref(n)), "tiledqr_elim_list")
+    out = np.zeros((max(n.value, 1), 3), dtype=np.int32)
+    check(tiledqr_elim_list(p, q, tree, bs, out.ctypes.data_as(_P(_i32)), ctypes.byref(n)), "tiledqr_elim_list")
+    return out[:n.value]
+
+
+def schedule(p, q, tree, bs=1, kernels=KERN_DEFAULT):
+    """(tasks int32 (n, 7) = kind, i, piv, k, j, start, finish; critical path)."""
+    n, cp = ctypes.c_int64(), ctypes.c_int64()
+    check(tiledqr_schedule(p, q, tree, bs, kernels, None, ctypes.byref(n), ctypes.byref(cp)), "tiledqr_schedule")
+    out = np.zeros((max(n.value, 1), 7), dtype=np.int32)
+    check(tiledqr_schedule(p, q, tree, bs, kernels, out.ctypes.data_as(_P(_i32)), ctypes.byref(n),
+                           ctypes.byref(cp)), "tiledqr_schedule")
+    return out[:n.value], cp.value
+
+
+def task_preds(p, q, tree, bs=1, kernels=KERN_DEFAULT):
+    """CSR predecessors (ptr int64 (n+1), idx int32)."""
+    tasks, _ = schedule(p, q, tree, bs, kernels)
+    ptr = np.zeros(len(tasks) + 1, dtype=np.int64)
+    check(tiledqr_task_preds(p, q, tree, bs, kernels, ptr.ctypes.data_as(_P(_i64)), None), "tiledqr_task_preds")
+    idx = np.zeros(max(int(ptr[-1]), 1), dtype=np.int32)
+    check(tiledqr_task_preds(p, q, tree, bs, kernels, ptr.ctypes.data_as(_P(_i64)), idx.ctypes.data_as(_P(_i32))),
+          "tiledqr_task_preds")
+    return ptr, idx[:int(ptr[-1])]

@@ -1,0 +1,140 @@
+"""Torch-facing helpers over the C ABI: device memory and the current HIP
+stream come from torch; all arithmetic runs in libtiledqr.so."""
+
+import ctypes
+
+from . import _lib
+from ._lib import check
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def colmajor(A):
+    """Return a float64 CUDA tensor with the same values as A stored in
+    column-major order (stride (1, rows))."""
+    torch = _torch()
+    if A.dtype != torch.float64:
+        raise TypeError("tiled QR works on float64 tensors")
+    if not A.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if A.dim() == 1:
+        A = A[:, None]
+    if A.stride(0) == 1 and A.stride(1) >= max(1, A.shape[0]):
+        return A
+    return A.t().contiguous().t()
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ld(A):
+    return max(1, A.stride(1)) if A.dim() == 2 else max(1, A.shape[0])
+
+
+class Factors:
+    """Owner of a tqr_factors handle."""
+
+    def __init__(self, handle, m, n, nb, opts):
+        self.handle = handle
+        self.m, self.n, self.nb = m, n, nb
+        self.opts = opts
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.tiledqr_destroy(h)
+            self.handle = None
+
+    def sync(self):
+        check(_lib.tiledqr_sync(self.handle), "tiledqr_sync")
+
+    def refactor(self, A):
+        A = colmajor(A)
+        check(_lib.tiledqr_refactor(self.handle, A.data_ptr(), _ld(A), _stream()), "tiledqr_refactor")
+
+    def R(self):
+        torch = _torch()
+        R = torch.empty((self.n, self.n), dtype=torch.float64, device="cuda").t()
+        check(_lib.tiledqr_get_r(self.handle, R.data_ptr(), self.n, _stream()), "tiledqr_get_r")
+        return R
+
+    def packed(self):
+        torch = _torch()
+        P = torch.empty((self.n, self.m), dtype=torch.float64, device="cuda").t()
+        check(_lib.tiledqr_get_packed(self.handle, P.data_ptr(), self.m, _stream()), "tiledqr_get_packed")
+        return P
+
+    def tau(self):
+        """(tau_geqrt, tau_pair) each of shape (q, p, nb): [c, r] -> tile (r, c)."""
+        torch = _torch()
+        p, q = self.m // self.nb, self.n // self.nb
+        t = torch.empty(2 * p * q * self.nb, dtype=torch.float64, device="cuda")
+        check(_lib.tiledqr_get_tau(self.handle, t.data_ptr(), _stream()), "tiledqr_get_tau")
+        t = t.view(2, q, p, self.nb)
+        return t[0], t[1]
+
+    def apply_q(self, B, trans="T"):
+        """Return Q^T B or Q B (B: m x nrhs float64 CUDA tensor, not modified)."""
+        B = colmajor(B).clone()  # preserves the column-major strides
+        check(_lib.tiledqr_apply_q(self.handle, trans.encode(), B.data_ptr(), _ld(B), B.shape[1], _stream()),
+              "tiledqr_apply_q")
+        return B
+
+    def thin_q(self):
+        torch = _torch()
+        E = torch.zeros((self.n, self.m), dtype=torch.float64, device="cuda").t()
+        E[:self.n, :self.n] = torch.eye(self.n, dtype=torch.float64, device="cuda")
+        check(_lib.tiledqr_apply_q(self.handle, b"N", E.data_ptr(), self.m, self.n, _stream()), "tiledqr_apply_q")
+        return E
+
+    def lstsq(self, B, A0=None, tol=0.0, max_iter=30, method=0, raise_on_noconv=False):
+        """Solve min ||B - A X||.  With tol > 0 the solution is refined
+        against A0 (the original matrix).  Returns (X, info dict)."""
+        torch = _torch()
+        B = colmajor(B)
+        nrhs = B.shape[1]
+        X = torch.empty((nrhs, self.n), dtype=torch.float64, device="cuda").t()
+        info = _lib.RefineInfo()
+        ref = _lib.RefineOpts(tol, max_iter, method)
+        a0p, lda = None, self.m
+        if A0 is not None:
+            A0 = colmajor(A0)
+            a0p, lda = A0.data_ptr(), _ld(A0)
+        st = _lib.tiledqr_lstsq(self.handle, a0p, lda, B.data_ptr(), _ld(B), nrhs, X.data_ptr(), self.n,
+                                ctypes.byref(ref), ctypes.byref(info), _stream())
+        if st != _lib.TQR_OK and not (st == _lib.TQR_ENOTCONV and not raise_on_noconv):
+            raise _lib.TiledQRError(st, "tiledqr_lstsq")
+        return X, {"iters": info.iters, "converged": bool(info.converged),
+                   "backward_err": info.backward_err, "status": st}
+
+
+def factor(A, nb, tree=_lib.TREE_GREEDY, bs=1, kernels=_lib.KERN_DEFAULT, upd=_lib.UPD_F64):
+    """Factor the m x n float64 CUDA tensor A (m, n multiples of nb)."""
+    A = colmajor(A)
+    m, n = A.shape
+    opts = _lib.Opts(m, n, nb, 0, tree, bs, kernels, upd)
+    h = ctypes.c_void_p()
+    check(_lib.tiledqr_factor(ctypes.byref(opts), A.data_ptr(), _ld(A), ctypes.byref(h), _stream()),
+          "tiledqr_factor")
+    return Factors(h, m, n, nb, opts)
+
+
+def factor_batched(mats, nbs, tree=_lib.TREE_GREEDY, bs=1, kernels=_lib.KERN_DEFAULT, upd=_lib.UPD_F64):
+    """Factor a list of matrices in one batched call; returns a list of
+    Factors."""
+    mats = [colmajor(A) for A in mats]
+    k = len(mats)
+    opts = (_lib.Opts * k)()
+    ptrs = (ctypes.c_void_p * k)()
+    ldas = (ctypes.c_int64 * k)()
+    for i, (A, nb) in enumerate(zip(mats, nbs)):
+        opts[i] = _lib.Opts(A.shape[0], A.shape[1], nb, 0, tree, bs, kernels, upd)
+        ptrs[i] = A.data_ptr()
+        ldas[i] = _ld(A)
+    hs = (ctypes.c_void_p * k)()
+    check(_lib.tiledqr_factor_batched(k, opts, ptrs, ldas, hs, _stream()), "tiledqr_factor_batched")
+    return [Factors(ctypes.c_void_p(hs[i]), mats[i].shape[0], mats[i].shape[1], nbs[i], opts[i]) for i in range(k)]

@@ -1,0 +1,538 @@
+// C ABI of the tiled QR library (declared in include/tiledqr.h).
+#include "tiledqr.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "device.hpp"
+#include "plan.hpp"
+
+using tqr::DevSub;
+using tqr::ExecArgs;
+using tqr::ExecPlan;
+using tqr::Plan;
+
+namespace {
+
+thread_local int g_last_hip = 0;
+
+bool hip_ok(hipError_t e) {
+  if (e != hipSuccess) {
+    g_last_hip = static_cast<int>(e);
+    return false;
+  }
+  return true;
+}
+
+#define HIP_TRY(expr)                   \
+  do {                                  \
+    if (!hip_ok(expr)) return TQR_EHIP; \
+  } while (0)
+
+bool nb_supported(int nb) { return nb == 32 || nb == 64 || nb == 128 || nb == 256; }
+
+// Device copy of an executor plan with its flags.
+struct DevPlan {
+  DevSub* sub = nullptr;
+  int32_t* deps = nullptr;
+  int32_t* flags = nullptr;
+  int32_t* order = nullptr;
+  int32_t nsub = 0;
+  std::vector<int32_t> level_ptr;
+  int32_t epoch = 0;
+
+  void release() {
+    if (sub) (void)hipFree(sub);
+    if (deps) (void)hipFree(deps);
+    if (flags) (void)hipFree(flags);
+    if (order) (void)hipFree(order);
+    sub = nullptr;
+    deps = nullptr;
+    flags = nullptr;
+    order = nullptr;
+  }
+};
+
+int upload(const ExecPlan& ex, DevPlan& d) {
+  // The executor waits only on earlier subtasks; anything else could block.
+  for (size_t t = 0; t < ex.sub.size(); ++t) {
+    if (ex.sub[t].dep_begin < 0 || ex.sub[t].dep_end > static_cast<int32_t>(ex.deps.size()) ||
+        ex.sub[t].dep_begin > ex.sub[t].dep_end)
+      return TQR_EINVAL;
+    for (int32_t e = ex.sub[t].dep_begin; e < ex.sub[t].dep_end; ++e)
+      if (ex.deps[e] < 0 || ex.deps[e] >= static_cast<int32_t>(t)) return TQR_EINVAL;
+  }
+  d.nsub = static_cast<int32_t>(ex.sub.size());
+  d.level_ptr = ex.level_ptr;
+  const size_t ns = std::max<size_t>(1, ex.sub.size());
+  const size_t nd = std::max<size_t>(1, ex.deps.size());
+  if (!hip_ok(hipMalloc(&d.sub, ns * sizeof(DevSub))) || !hip_ok(hipMalloc(&d.deps, nd * sizeof(int32_t))) ||
+      !hip_ok(hipMalloc(&d.flags, ns * sizeof(int32_t))) || !hip_ok(hipMalloc(&d.order, ns * sizeof(int32_t)))) {
+    d.release();
+    return TQR_ENOMEM;
+  }
+  static_assert(sizeof(DevSub) == sizeof(tqr::SubTask), "task record layout");
+  if (!ex.sub.empty()) HIP_TRY(hipMemcpy(d.sub, ex.sub.data(), ex.sub.size() * sizeof(DevSub), hipMemcpyHostToDevice));
+  if (!ex.deps.empty())
+    HIP_TRY(hipMemcpy(d.deps, ex.deps.data(), ex.deps.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  if (!ex.level_order.empty())
+    HIP_TRY(hipMemcpy(d.order, ex.level_order.data(), ex.level_order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(d.flags, 0, ns * sizeof(int32_t)));
+  return TQR_OK;
+}
+
+int device_cus() {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
+int64_t wall_ticks_per_second() {
+  static int64_t rate = 0;
+  if (!rate) {
+    int dev = 0, khz = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+      rate = static_cast<int64_t>(khz) * 1000;
+    else
+      rate = 100000000;
+  }
+  return rate;
+}
+
+bool use_level_path() {
+  const char* e = std::getenv("TQR_EXEC");
+  return e && std::strcmp(e, "level") == 0;
+}
+
+int exec_order() {
+  const char* e = std::getenv("TQR_ORDER");
+  return (e && std::strcmp(e, "alap") == 0) ? 1 : 0;
+}
+
+}  // namespace
+
+struct tqr_factors {
+  tqr_opts o{};
+  int p = 0, q = 0, nb = 0;
+  Plan plan;
+  DevPlan exec;
+  std::map<int, DevPlan> apply;  // key: trans * 1024 + nslab
+  double* tiles = nullptr;
+  double* Tg = nullptr;
+  double* Tp = nullptr;
+  int32_t* ctl = nullptr;  // [0] ticket, [1] err
+  hipStream_t stream = nullptr;
+  int grid = 1;
+
+  ~tqr_factors() {
+    exec.release();
+    for (auto& kv : apply) kv.second.release();
+    if (tiles) (void)hipFree(tiles);
+    if (Tg) (void)hipFree(Tg);
+    if (Tp) (void)hipFree(Tp);
+    if (ctl) (void)hipFree(ctl);
+  }
+};
+
+namespace {
+
+ExecArgs base_args(const tqr_factors* F, const DevPlan& d) {
+  ExecArgs a{};
+  a.tiles = F->tiles;
+  a.Tg = F->Tg;
+  a.Tp = F->Tp;
+  a.B = nullptr;
+  a.sub = d.sub;
+  a.deps = d.deps;
+  a.flags = d.flags;
+  a.ticket = F->ctl;
+  a.err = F->ctl + 1;
+  a.nsub = d.nsub;
+  a.p = F->p;
+  a.q = F->q;
+  a.nb = F->nb;
+  a.ncolB = 0;
+  a.transB = 1;
+  a.upd = F->o.upd;
+  a.spin_ticks = 4 * wall_ticks_per_second();
+  return a;
+}
+
+int run_plan(tqr_factors* F, DevPlan& d, ExecArgs a, hipStream_t s) {
+  if (d.nsub == 0) return TQR_OK;
+  a.epoch = ++d.epoch;
+  if (use_level_path()) {
+    HIP_TRY(tqr::launch_reset(a.ticket, a.err, s));
+    const int nl = static_cast<int>(d.level_ptr.size()) - 1;
+    for (int l = 0; l < nl; ++l) {
+      const int b = d.level_ptr[l], c = d.level_ptr[l + 1] - b;
+      if (c > 0) HIP_TRY(tqr::launch_level(a, d.order, b, c, s));
+    }
+    return TQR_OK;
+  }
+  HIP_TRY(tqr::launch_reset(a.ticket, a.err, s));
+  const int grid = std::max(1, std::min(d.nsub, F->grid));
+  HIP_TRY(tqr::launch_persistent(a, grid, s));
+  return TQR_OK;
+}
+
+int check_opts(const tqr_opts* o, int64_t lda) {
+  if (!o) return TQR_EINVAL;
+  if (o->nb <= 0 || o->m <= 0 || o->n <= 0) return TQR_EINVAL;
+  if (!nb_supported(o->nb)) return TQR_EINVAL;
+  if (o->ib != 0 && o->ib != tqr::IB) return TQR_EINVAL;
+  if (o->m % o->nb || o->n % o->nb || o->m < o->n) return TQR_EINVAL;
+  if (lda < o->m) return TQR_EINVAL;
+  if (o->upd < TQR_UPD_F64 || o->upd > TQR_UPD_BF16) return TQR_EINVAL;
+  if (o->kernels < TQR_KERN_DEFAULT || o->kernels > TQR_KERN_TS) return TQR_EINVAL;
+  const int64_t p = o->m / o->nb, q = o->n / o->nb;
+  if (p > (1 << 20)) return TQR_EINVAL;
+  if (!tqr::valid_shape(static_cast<int>(p), static_cast<int>(q), o->tree, o->bs)) return TQR_EINVAL;
+  return TQR_OK;
+}
+
+int create(const tqr_opts* o, tqr_factors** out) {
+  std::unique_ptr<tqr_factors> F(new (std::nothrow) tqr_factors());
+  if (!F) return TQR_ENOMEM;
+  F->o = *o;
+  F->o.ib = tqr::IB;
+  F->nb = o->nb;
+  F->p = static_cast<int>(o->m / o->nb);
+  F->q = static_cast<int>(o->n / o->nb);
+  if (!tqr::make_plan(F->p, F->q, o->tree, o->bs, o->kernels, F->plan)) return TQR_EINVAL;
+  const double w[6] = {4, 6, 6, 12, 2, 6};
+  ExecPlan ex;
+  const int nslab = std::max(1, F->nb / tqr::SLAB);
+  tqr::make_exec_plan(F->plan, nslab, exec_order(), w, ex);
+  int st = upload(ex, F->exec);
+  if (st != TQR_OK) return st;
+  const size_t ntile = static_cast<size_t>(F->p) * F->q;
+  const size_t nbb = static_cast<size_t>(F->nb);
+  if (!hip_ok(hipMalloc(&F->tiles, ntile * nbb * nbb * sizeof(double))) ||
+      !hip_ok(hipMalloc(&F->Tg, ntile * tqr::IB * nbb * sizeof(double))) ||
+      !hip_ok(hipMalloc(&F->Tp, ntile * tqr::IB * nbb * sizeof(double))) ||
+      !hip_ok(hipMalloc(&F->ctl, 2 * sizeof(int32_t))))
+    return TQR_ENOMEM;
+  HIP_TRY(hipMemset(F->Tg, 0, ntile * tqr::IB * nbb * sizeof(double)));
+  HIP_TRY(hipMemset(F->Tp, 0, ntile * tqr::IB * nbb * sizeof(double)));
+  HIP_TRY(hipMemset(F->ctl, 0, 2 * sizeof(int32_t)));
+  F->grid = device_cus() * tqr::persistent_occupancy(F->nb);
+  *out = F.release();
+  return TQR_OK;
+}
+
+int factor_into(tqr_factors* F, const double* A, int64_t lda, hipStream_t s) {
+  F->stream = s;
+  HIP_TRY(tqr::launch_pack(A, lda, F->tiles, F->p, F->q, F->nb, s));
+  return run_plan(F, F->exec, base_args(F, F->exec), s);
+}
+
+DevPlan* apply_plan(tqr_factors* F, int trans, int nslab, int* st) {
+  const int key = trans * 1024 + nslab;
+  auto it = F->apply.find(key);
+  if (it != F->apply.end()) return &it->second;
+  ExecPlan ex;
+  tqr::make_apply_plan(F->plan, trans, nslab, ex);
+  DevPlan d;
+  *st = upload(ex, d);
+  if (*st != TQR_OK) return nullptr;
+  return &(F->apply[key] = d);
+}
+
+// Apply Q^T / Q to the packed row tiles Bt (ncolB columns).
+int apply_tiles(const tqr_factors* Fc, int trans, double* Bt, int ncolB, hipStream_t s) {
+  tqr_factors* F = const_cast<tqr_factors*>(Fc);
+  const int nslab = (ncolB + tqr::SLAB - 1) / tqr::SLAB;
+  int st = TQR_OK;
+  DevPlan* d = apply_plan(F, trans, nslab, &st);
+  if (!d) return st;
+  ExecArgs a = base_args(F, *d);
+  a.B = Bt;
+  a.ncolB = ncolB;
+  a.transB = trans;
+  return run_plan(F, *d, a, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tiledqr_strerror(int status) {
+  switch (status) {
+    case TQR_OK: return "success";
+    case TQR_EINVAL: return "invalid argument";
+    case TQR_ENOMEM: return "out of memory";
+    case TQR_EHIP: return "HIP runtime error";
+    case TQR_ENOTCONV: return "refinement did not converge";
+    case TQR_EUNSUPPORTED: return "unsupported configuration";
+    case TQR_EEXEC: return "device executor stopped (dependency wait time limit)";
+    default: return "unknown status";
+  }
+}
+
+int tiledqr_last_hip_error(void) { return g_last_hip; }
+
+int tiledqr_factor(const tqr_opts* opts, const double* A, int64_t lda, tqr_factors** F, void* stream) {
+  if (!F || !A) return TQR_EINVAL;
+  int st = check_opts(opts, lda);
+  if (st != TQR_OK) return st;
+  tqr_factors* h = nullptr;
+  st = create(opts, &h);
+  if (st != TQR_OK) return st;
+  st = factor_into(h, A, lda, static_cast<hipStream_t>(stream));
+  if (st != TQR_OK) {
+    delete h;
+    return st;
+  }
+  *F = h;
+  return TQR_OK;
+}
+
+int tiledqr_refactor(tqr_factors* F, const double* A, int64_t lda, void* stream) {
+  if (!F || !A || lda < F->o.m) return TQR_EINVAL;
+  return factor_into(F, A, lda, static_cast<hipStream_t>(stream));
+}
+
+int tiledqr_sync(tqr_factors* F) {
+  if (!F) return TQR_EINVAL;
+  HIP_TRY(hipStreamSynchronize(F->stream));
+  int32_t err = 0;
+  HIP_TRY(hipMemcpy(&err, F->ctl + 1, sizeof(int32_t), hipMemcpyDeviceToHost));
+  return err ? TQR_EEXEC : TQR_OK;
+}
+
+int tiledqr_destroy(tqr_factors* F) {
+  if (!F) return TQR_OK;
+  (void)hipStreamSynchronize(F->stream);
+  delete F;
+  return TQR_OK;
+}
+
+int tiledqr_get_r(const tqr_factors* F, double* R, int64_t ldr, void* stream) {
+  if (!F || !R || ldr < F->o.n) return TQR_EINVAL;
+  HIP_TRY(tqr::launch_unpack(F->tiles, R, ldr, F->p, F->q, F->nb, static_cast<int>(F->o.n),
+                             static_cast<int>(F->o.n), 1, static_cast<hipStream_t>(stream)));
+  return TQR_OK;
+}
+
+int tiledqr_get_packed(const tqr_factors* F, double* out, int64_t ld, void* stream) {
+  if (!F || !out || ld < F->o.m) return TQR_EINVAL;
+  HIP_TRY(tqr::launch_unpack(F->tiles, out, ld, F->p, F->q, F->nb, static_cast<int>(F->o.m),
+                             static_cast<int>(F->o.n), 0, static_cast<hipStream_t>(stream)));
+  return TQR_OK;
+}
+
+int tiledqr_get_tau(const tqr_factors* F, double* tau, void* stream) {
+  if (!F || !tau) return TQR_EINVAL;
+  HIP_TRY(tqr::launch_tau(F->Tg, F->Tp, tau, F->p, F->q, F->nb, static_cast<hipStream_t>(stream)));
+  return TQR_OK;
+}
+
+int tiledqr_apply_q(const tqr_factors* F, char trans, double* B, int64_t ldb, int64_t nrhs, void* stream) {
+  if (!F || (!B && nrhs > 0) || ldb < F->o.m || nrhs < 0) return TQR_EINVAL;
+  if (trans != 'T' && trans != 'N' && trans != 't' && trans != 'n') return TQR_EINVAL;
+  if (nrhs == 0) return TQR_OK;
+  if (nrhs > (1 << 20)) return TQR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int ncolB = static_cast<int>((nrhs + 15) / 16 * 16);
+  double* Bt = nullptr;
+  if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Bt),
+                             static_cast<size_t>(F->p) * F->nb * ncolB * sizeof(double), s)))
+    return TQR_ENOMEM;
+  int st = TQR_OK;
+  if (!hip_ok(tqr::launch_pack_b(B, ldb, nrhs, Bt, F->p, F->nb, ncolB, s))) st = TQR_EHIP;
+  if (st == TQR_OK) st = apply_tiles(F, (trans == 'T' || trans == 't') ? 1 : 0, Bt, ncolB, s);
+  if (st == TQR_OK && !hip_ok(tqr::launch_unpack_b(Bt, B, ldb, nrhs, static_cast<int>(F->o.m), F->nb, ncolB, s)))
+    st = TQR_EHIP;
+  (void)hipFreeAsync(Bt, s);
+  return st;
+}
+
+int tiledqr_elim_list(int32_t p, int32_t q, int32_t tree, int32_t bs, int32_t* out, int64_t* nelim) {
+  if (!nelim) return TQR_EINVAL;
+  std::vector<tqr::Elim> el;
+  if (!tqr::make_elims(p, q, tree, bs, el)) return TQR_EINVAL;
+  *nelim = static_cast<int64_t>(el.size());
+  if (out)
+    for (size_t e = 0; e < el.size(); ++e) {
+      out[3 * e] = el[e].i;
+      out[3 * e + 1] = el[e].piv;
+      out[3 * e + 2] = el[e].k;
+    }
+  return TQR_OK;
+}
+
+int tiledqr_schedule(int32_t p, int32_t q, int32_t tree, int32_t bs, int32_t kernels, int32_t* tasks,
+                     int64_t* ntasks, int64_t* cp) {
+  if (!ntasks) return TQR_EINVAL;
+  if (kernels < TQR_KERN_DEFAULT || kernels > TQR_KERN_TS) return TQR_EINVAL;
+  Plan pl;
+  if (!tqr::make_plan(p, q, tree, bs, kernels, pl)) return TQR_EINVAL;
+  *ntasks = static_cast<int64_t>(pl.tasks.size());
+  if (cp) *cp = pl.cp;
+  if (tasks)
+    for (size_t t = 0; t < pl.tasks.size(); ++t) {
+      const tqr::Task& k = pl.tasks[t];
+      int32_t* o = tasks + 7 * t;
+      o[0] = k.kind;
+      o[1] = k.i;
+      o[2] = k.piv;
+      o[3] = k.k;
+      o[4] = k.j;
+      o[5] = static_cast<int32_t>(pl.start[t]);
+      o[6] = static_cast<int32_t>(pl.finish[t]);
+    }
+  return TQR_OK;
+}
+
+int tiledqr_task_preds(int32_t p, int32_t q, int32_t tree, int32_t bs, int32_t kernels, int64_t* ptr, int32_t* idx) {
+  if (!ptr) return TQR_EINVAL;
+  if (kernels < TQR_KERN_DEFAULT || kernels > TQR_KERN_TS) return TQR_EINVAL;
+  Plan pl;
+  if (!tqr::make_plan(p, q, tree, bs, kernels, pl)) return TQR_EINVAL;
+  std::copy(pl.pred_ptr.begin(), pl.pred_ptr.end(), ptr);
+  if (idx) std::copy(pl.pred_idx.begin(), pl.pred_idx.end(), idx);
+  return TQR_OK;
+}
+
+int tiledqr_lstsq(const tqr_factors* F, const double* A0, int64_t lda, const double* B, int64_t ldb, int64_t nrhs,
+                  double* X, int64_t ldx, const tqr_refine* r, tqr_refine_info* info, void* stream) {
+  if (!F || !B || !X || nrhs < 1 || ldb < F->o.m || ldx < F->o.n) return TQR_EINVAL;
+  const bool refine = r && r->tol > 0.0;
+  if (refine && (!A0 || lda < F->o.m)) return TQR_EINVAL;
+  if (nrhs > 4096) return TQR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t m = F->o.m, n = F->o.n;
+  const int ncolB = static_cast<int>((nrhs + 15) / 16 * 16);
+  const size_t bt_elems = static_cast<size_t>(F->p) * F->nb * ncolB;
+  double *Bt = nullptr, *Rv = nullptr, *D = nullptr, *nrm = nullptr;
+  int st = TQR_OK;
+  auto fail = [&](int code) {
+    if (Bt) (void)hipFreeAsync(Bt, s);
+    if (Rv) (void)hipFreeAsync(Rv, s);
+    if (D) (void)hipFreeAsync(D, s);
+    if (nrm) (void)hipFreeAsync(nrm, s);
+    return code;
+  };
+  if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Bt), bt_elems * sizeof(double), s))) return fail(TQR_ENOMEM);
+  // X = R^{-1} (Q^T B)(1:n)
+  if (!hip_ok(tqr::launch_pack_b(B, ldb, nrhs, Bt, F->p, F->nb, ncolB, s))) return fail(TQR_EHIP);
+  st = apply_tiles(F, 1, Bt, ncolB, s);
+  if (st != TQR_OK) return fail(st);
+  if (!hip_ok(tqr::launch_unpack_b(Bt, X, ldx, nrhs, static_cast<int>(n), F->nb, ncolB, s))) return fail(TQR_EHIP);
+  if (!hip_ok(tqr::launch_trsm_upper(F->tiles, F->p, F->q, F->nb, X, ldx, nrhs, s))) return fail(TQR_EHIP);
+  if (!refine) {
+    if (info) {
+      info->iters = 0;
+      info->converged = 1;
+      info->backward_err = -1.0;
+    }
+    return fail(TQR_OK);
+  }
+  if (m != n) return fail(TQR_EUNSUPPORTED);  // augmented-system refinement: tall systems
+  const int max_iter = r->max_iter > 0 ? r->max_iter : 30;
+  const size_t rv_elems = static_cast<size_t>(m) * nrhs;
+  if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Rv), rv_elems * sizeof(double), s)) ||
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&D), static_cast<size_t>(n) * nrhs * sizeof(double), s)) ||
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&nrm), (3 * nrhs + 1) * sizeof(double), s)))
+    return fail(TQR_ENOMEM);
+  // ||A||_F^2 and ||b||^2 once.
+  double* nA = nrm + 3 * nrhs;
+  if (!hip_ok(hipMemsetAsync(nrm, 0, (3 * nrhs + 1) * sizeof(double), s))) return fail(TQR_EHIP);
+  std::vector<double> colA(static_cast<size_t>(n));
+  {
+    double* ca = nullptr;
+    if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&ca), n * sizeof(double), s))) return fail(TQR_ENOMEM);
+    (void)hipMemsetAsync(ca, 0, n * sizeof(double), s);
+    bool ok = hip_ok(tqr::launch_colnorms2(A0, lda, m, n, ca, s)) &&
+              hip_ok(hipMemcpyAsync(colA.data(), ca, n * sizeof(double), hipMemcpyDeviceToHost, s)) &&
+              hip_ok(tqr::launch_colnorms2(B, ldb, m, nrhs, nrm + 2 * nrhs, s));
+    (void)hipFreeAsync(ca, s);
+    if (!ok) return fail(TQR_EHIP);
+  }
+  (void)nA;
+  std::vector<double> h(3 * nrhs);
+  double best = INFINITY, eta = INFINITY;
+  std::vector<double> hist;
+  int it = 0;
+  bool conv = false;
+  for (;; ++it) {
+    // residual and norms
+    if (!hip_ok(tqr::launch_residual(A0, lda, m, n, X, ldx, B, ldb, nrhs, Rv, m, s))) return fail(TQR_EHIP);
+    if (!hip_ok(hipMemsetAsync(nrm, 0, 2 * nrhs * sizeof(double), s))) return fail(TQR_EHIP);
+    if (!hip_ok(tqr::launch_colnorms2(Rv, m, m, nrhs, nrm, s)) ||
+        !hip_ok(tqr::launch_colnorms2(X, ldx, n, nrhs, nrm + nrhs, s)))
+      return fail(TQR_EHIP);
+    if (!hip_ok(hipMemcpyAsync(h.data(), nrm, 3 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s)) ||
+        !hip_ok(hipStreamSynchronize(s)))
+      return fail(TQR_EHIP);
+    double fa = 0.0;
+    for (double v : colA) fa += v;
+    fa = std::sqrt(fa);
+    eta = 0.0;
+    for (int64_t c = 0; c < nrhs; ++c) {
+      const double den = fa * std::sqrt(h[nrhs + c]) + std::sqrt(h[2 * nrhs + c]);
+      eta = std::max(eta, den > 0 ? std::sqrt(h[c]) / den : 0.0);
+    }
+    best = std::min(best, eta);
+    hist.push_back(eta);
+    if (eta <= r->tol) {
+      conv = true;
+      break;
+    }
+    if (it >= max_iter) break;
+    if (hist.size() > 3 && hist.back() > 0.5 * hist[hist.size() - 4]) break;
+    // correction D = R^{-1} (Q^T Rv)(1:n); X += D
+    if (!hip_ok(tqr::launch_pack_b(Rv, m, nrhs, Bt, F->p, F->nb, ncolB, s))) return fail(TQR_EHIP);
+    st = apply_tiles(F, 1, Bt, ncolB, s);
+    if (st != TQR_OK) return fail(st);
+    if (!hip_ok(tqr::launch_unpack_b(Bt, D, n, nrhs, static_cast<int>(n), F->nb, ncolB, s)) ||
+        !hip_ok(tqr::launch_trsm_upper(F->tiles, F->p, F->q, F->nb, D, n, nrhs, s)) ||
+        !hip_ok(tqr::launch_axpy_cols(X, ldx, D, n, n, nrhs, s)))
+      return fail(TQR_EHIP);
+  }
+  if (info) {
+    info->iters = it;
+    info->converged = conv ? 1 : 0;
+    info->backward_err = eta;
+  }
+  return fail(conv ? TQR_OK : TQR_ENOTCONV);
+}
+
+int tiledqr_factor_batched(int32_t nprob, const tqr_opts* opts, const double* const* A, const int64_t* lda,
+                           tqr_factors** F, void* stream) {
+  if (nprob < 0 || (nprob > 0 && (!opts || !A || !lda || !F))) return TQR_EINVAL;
+  for (int32_t i = 0; i < nprob; ++i) {
+    if (!A[i]) return TQR_EINVAL;
+    const int st = check_opts(opts + i, lda[i]);
+    if (st != TQR_OK) return st;
+  }
+  // Placeholder path: one handle per problem, factored back to back.
+  for (int32_t i = 0; i < nprob; ++i) {
+    const int st = tiledqr_factor(opts + i, A[i], lda[i], F + i, stream);
+    if (st != TQR_OK) {
+      for (int32_t j = 0; j < i; ++j) {
+        tiledqr_destroy(F[j]);
+        F[j] = nullptr;
+      }
+      return st;
+    }
+  }
+  return TQR_OK;
+}
+
+}  // extern "C"

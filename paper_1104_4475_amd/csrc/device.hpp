@@ -1,0 +1,66 @@
+// Shared device/host definitions of the HIP tile kernels and executor.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace tqr {
+
+constexpr int IB = 32;        // inner block size of every kernel (Sec. 4: ib = 32)
+constexpr int NTHREADS = 256; // 4 waves of 64 lanes
+constexpr int SLAB = 64;      // columns of C per update subtask (16 per wave)
+
+// Executor task kinds: the six tile kernels (Table 1) and the application of
+// a panel task's reflectors to right-hand-side row tiles (apply_q).
+enum DevKind : int32_t {
+  D_GEQRT = 0, D_UNMQR = 1, D_TSQRT = 2, D_TSMQR = 3, D_TTQRT = 4, D_TTMQR = 5,
+  D_APPLY_GE = 6,   // B_i <- Q_geqrt(i,k)^{T or N} B_i
+  D_APPLY_TS = 7,   // [B_piv; B_i] <- Q_ts(i,k)^{T or N} [...]
+  D_APPLY_TT = 8    // [B_piv; B_i] <- Q_tt(i,k)^{T or N} [...]
+};
+
+struct DevSub {
+  int32_t kind, i, piv, k, j, slab, dep_begin, dep_end;
+};
+
+struct ExecArgs {
+  double* tiles;        // p*q tiles of nb*nb, tile (r,c) at (c*p + r)*nb*nb
+  double* Tg;           // GEQRT T factors, ib*nb per tile
+  double* Tp;           // TS/TT T factors of the zeroed tile, ib*nb per tile
+  double* B;            // apply_q: p row tiles of nb x ncolB (ld nb)
+  const DevSub* sub;
+  const int32_t* deps;
+  int32_t* flags;       // one per subtask, set to epoch when done
+  int32_t* ticket;      // dispatch counter (reset before each launch)
+  int32_t* err;         // nonzero once any wait timed out
+  int32_t nsub;
+  int32_t epoch;
+  int32_t p, q, nb;
+  int32_t ncolB;        // columns of the B row tiles (multiple of 16)
+  int32_t transB;       // apply_q: 1 = Q^T, 0 = Q
+  int32_t upd;          // tqr_update_prec
+  int64_t spin_ticks;   // wall-clock ticks a wait may last before giving up
+};
+
+// Kernel launchers (defined in kernels.hip).
+hipError_t launch_persistent(const ExecArgs& a, int grid, hipStream_t s);
+hipError_t launch_level(const ExecArgs& a, const int32_t* order, int begin, int count, hipStream_t s);
+hipError_t launch_reset(int32_t* ticket, int32_t* err, hipStream_t s);
+hipError_t launch_pack(const double* A, int64_t lda, double* tiles, int p, int q, int nb, hipStream_t s);
+hipError_t launch_unpack(const double* tiles, double* out, int64_t ld, int p, int q, int nb, int rows, int cols,
+                         int upper_only, hipStream_t s);
+hipError_t launch_tau(const double* Tg, const double* Tp, double* tau, int p, int q, int nb, hipStream_t s);
+hipError_t launch_pack_b(const double* B, int64_t ldb, int64_t nrhs, double* Bt, int p, int nb, int ncolB,
+                         hipStream_t s);
+hipError_t launch_unpack_b(const double* Bt, double* B, int64_t ldb, int64_t nrhs, int rows, int nb, int ncolB,
+                           hipStream_t s);
+hipError_t launch_trsm_upper(const double* tiles, int p, int q, int nb, double* Y, int64_t ldy, int64_t nrhs,
+                             hipStream_t s);
+hipError_t launch_residual(const double* A, int64_t lda, int64_t m, int64_t n, const double* X, int64_t ldx,
+                           const double* B, int64_t ldb, int64_t nrhs, double* Rv, int64_t ldr, hipStream_t s);
+hipError_t launch_colnorms2(const double* M, int64_t ld, int64_t rows, int64_t cols, double* out, hipStream_t s);
+hipError_t launch_axpy_cols(double* X, int64_t ldx, const double* D, int64_t ldd, int64_t rows, int64_t cols,
+                            hipStream_t s);
+int persistent_occupancy(int nb);
+
+}  // namespace tqr

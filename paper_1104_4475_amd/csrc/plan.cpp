@@ -1,0 +1,440 @@
+// Host planner (see plan.hpp).
+//
+// Elimination lists follow Sec. 3.1 / Sec. 3.2 of the paper (FlatTree ==
+// Sameh-Kuck, BinaryTree, Fibonacci, PlasmaTree) and Algorithm 4 (Greedy).
+// The expansion into kernels follows Algorithms 2 (TS) and 3 (TT), skipping
+// GEQRT on tiles that are already triangles (Sec. 2.1).  The schedule is the
+// unbounded-processor as-soon-as-possible execution of Sec. 2.3 with the
+// Table 1 weights.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace tqr {
+
+bool valid_shape(int p, int q, int tree, int bs) {
+  if (q < 1 || p < q) return false;
+  if (tree < T_FLAT || tree > T_PLASMA) return false;
+  if (tree == T_PLASMA && (bs < 1 || bs > p)) return false;
+  return true;
+}
+
+int resolve_family(int tree, int family) {
+  if (family == F_DEFAULT) return tree == T_FLAT ? F_TS : F_TT;
+  return family;
+}
+
+namespace {
+
+// Smallest t >= 0 with t(t+1)/2 >= v.
+int tri_ceil(int v) {
+  int t = 0;
+  while (t * (t + 1) / 2 < v) ++t;
+  return t;
+}
+
+void flat(int p, int q, std::vector<Elim>& out) {
+  const int kmax = std::min(p, q);
+  for (int k = 1; k <= kmax; ++k)
+    for (int i = k + 1; i <= p; ++i) out.push_back({i, k, k});
+}
+
+// Binary reduction over rows k..p of each column, rooted at row k.
+void binary(int p, int q, std::vector<Elim>& out) {
+  const int kmax = std::min(p, q);
+  for (int k = 1; k <= kmax; ++k) {
+    const int rows = p - k + 1;
+    for (int stride = 1; stride < rows; stride <<= 1)
+      for (int off = stride; off < rows; off += 2 * stride)
+        out.push_back({k + off, k + off - stride, k});
+  }
+}
+
+// Fibonacci (Modi-Clarke order 1): tile (i, k) is zeroed at step
+// x - y(i - k + 1) + 1 + 2(k - 1), x minimal with x(x+1)/2 >= p - 1 and
+// y(r) minimal with r <= y(y+1)/2 + 1.  Tiles zeroed at one step form a run
+// of z consecutive rows paired with the z rows just above them.
+void fibonacci(int p, int q, std::vector<Elim>& out) {
+  const int x = tri_ceil(p - 1);
+  const int kmax = std::min(p, q);
+  std::vector<int> step(p + 2, 0);
+  for (int k = 1; k <= kmax; ++k) {
+    int smin = 1 << 30, smax = -1;
+    for (int i = k + 1; i <= p; ++i) {
+      const int y = tri_ceil(i - k);  // least y with i-k+1 <= y(y+1)/2 + 1
+      step[i] = x - y + 1 + 2 * (k - 1);
+      smin = std::min(smin, step[i]);
+      smax = std::max(smax, step[i]);
+    }
+    for (int s = smin; s <= smax; ++s) {
+      int first = -1, z = 0;
+      for (int i = k + 1; i <= p; ++i)
+        if (step[i] == s) {
+          if (first < 0) first = i;
+          ++z;
+        }
+      for (int t = 0; t < z; ++t) out.push_back({first + t, first + t - z, k});
+    }
+  }
+}
+
+// Greedy, Algorithm 4: rounds over columns q..1 with counters nT(j) of
+// triangularized and nZ(j) of zeroed tiles.
+void greedy(int p, int q, std::vector<Elim>& out) {
+  std::vector<int> nT(q + 1, 0), nZ(q + 1, 0);
+  auto done = [&] { return nZ[q] == p - q && nT[q] == p - q + 1; };
+  while (!done()) {
+    for (int j = q; j >= 1; --j) {
+      const int tri_next = (j == 1) ? p : nZ[j - 1];
+      const int zero_next = nZ[j] + (nT[j] - nZ[j]) / 2;
+      const int shift = zero_next - nZ[j];
+      for (int kk = nZ[j]; kk < zero_next; ++kk) out.push_back({p - kk, p - kk - shift, j});
+      nT[j] = tri_next;
+      nZ[j] = zero_next;
+    }
+  }
+}
+
+// PlasmaTree(BS): domains of BS rows starting at row k; flat inside each
+// domain, then a binary tree over the domain heads.
+void plasma(int p, int q, int bs, std::vector<Elim>& out) {
+  const int kmax = std::min(p, q);
+  std::vector<int> heads;
+  for (int k = 1; k <= kmax; ++k) {
+    heads.clear();
+    for (int h = k; h <= p; h += bs) heads.push_back(h);
+    for (int h : heads)
+      for (int i = h + 1; i <= std::min(h + bs - 1, p); ++i) out.push_back({i, h, k});
+    const int nd = static_cast<int>(heads.size());
+    for (int stride = 1; stride < nd; stride <<= 1)
+      for (int d = stride; d < nd; d += 2 * stride) out.push_back({heads[d], heads[d - stride], k});
+  }
+}
+
+}  // namespace
+
+bool make_elims(int p, int q, int tree, int bs, std::vector<Elim>& out) {
+  out.clear();
+  if (!valid_shape(p, q, tree, bs)) return false;
+  switch (tree) {
+    case T_FLAT:
+    case T_SAMEH_KUCK: flat(p, q, out); break;
+    case T_BINARY: binary(p, q, out); break;
+    case T_FIBONACCI: fibonacci(p, q, out); break;
+    case T_GREEDY: greedy(p, q, out); break;
+    case T_PLASMA: plasma(p, q, bs, out); break;
+    default: return false;
+  }
+  return true;
+}
+
+namespace {
+
+// Task expansion with tile data flow.  For every tile we remember the last
+// task that wrote its "upper" part (R, or the TT reflectors, or the whole
+// tile while it is full) and its "lower" part (GEQRT reflectors).
+struct Expander {
+  int p, q, family;
+  std::vector<Task>& tasks;
+  std::vector<std::vector<int32_t>> preds;
+  std::vector<int32_t> up, lo;
+  std::vector<char> is_tri;
+
+  Expander(int p_, int q_, int fam, std::vector<Task>& t)
+      : p(p_), q(q_), family(fam), tasks(t),
+        up(static_cast<size_t>(p_) * q_, -1), lo(static_cast<size_t>(p_) * q_, -1),
+        is_tri(static_cast<size_t>(p_) * q_, 0) {}
+
+  size_t at(int r, int c) const { return static_cast<size_t>(r - 1) * q + (c - 1); }
+
+  int emit(Task t, std::initializer_list<int32_t> d) {
+    std::vector<int32_t> v;
+    for (int32_t x : d)
+      if (x >= 0) v.push_back(x);
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+    tasks.push_back(t);
+    preds.push_back(std::move(v));
+    return static_cast<int>(tasks.size()) - 1;
+  }
+
+  void factor_row(int r, int k) {
+    const size_t a = at(r, k);
+    const int g = emit({K_GEQRT, r, 0, k, 0}, {up[a], lo[a]});
+    up[a] = lo[a] = g;
+    is_tri[a] = 1;
+    for (int j = k + 1; j <= q; ++j) {
+      const size_t c = at(r, j);
+      const int u = emit({K_UNMQR, r, 0, k, j}, {g, up[c], lo[c]});
+      up[c] = lo[c] = u;
+    }
+  }
+
+  void run(const std::vector<Elim>& el) {
+    // Rows acting as a pivot in each column (to find the leaves for TS).
+    std::vector<char> pivot(static_cast<size_t>(p + 1) * (q + 1), 0);
+    for (const Elim& e : el) pivot[static_cast<size_t>(e.k) * (p + 1) + e.piv] = 1;
+    for (const Elim& e : el) {
+      const int i = e.i, pv = e.piv, k = e.k;
+      if (!is_tri[at(pv, k)]) factor_row(pv, k);
+      const bool leaf = !pivot[static_cast<size_t>(k) * (p + 1) + i];
+      const size_t ti = at(i, k), tp = at(pv, k);
+      int f, upd;
+      if (family == F_TS && leaf && !is_tri[ti]) {
+        f = emit({K_TSQRT, i, pv, k, 0}, {up[tp], up[ti], lo[ti]});
+        up[tp] = f;
+        up[ti] = lo[ti] = f;
+        upd = K_TSMQR;
+      } else {
+        if (!is_tri[ti]) factor_row(i, k);
+        f = emit({K_TTQRT, i, pv, k, 0}, {up[tp], up[ti]});
+        up[tp] = f;
+        up[ti] = f;
+        upd = K_TTMQR;
+      }
+      for (int j = k + 1; j <= q; ++j) {
+        const size_t cp = at(pv, j), ci = at(i, j);
+        const int u = emit({upd, i, pv, k, j}, {f, up[cp], lo[cp], up[ci], lo[ci]});
+        up[cp] = lo[cp] = up[ci] = lo[ci] = u;
+      }
+    }
+    if (p == q && !is_tri[at(q, q)]) factor_row(q, q);
+  }
+};
+
+}  // namespace
+
+bool make_plan(int p, int q, int tree, int bs, int family, Plan& plan) {
+  if (!valid_shape(p, q, tree, bs)) return false;
+  family = resolve_family(tree, family);
+  if (family != F_TT && family != F_TS) return false;
+  plan = Plan();
+  plan.p = p;
+  plan.q = q;
+  plan.tree = tree;
+  plan.bs = bs;
+  plan.family = family;
+  if (!make_elims(p, q, tree, bs, plan.elims)) return false;
+  Expander ex(p, q, family, plan.tasks);
+  ex.run(plan.elims);
+  const size_t n = plan.tasks.size();
+  plan.pred_ptr.assign(n + 1, 0);
+  for (size_t t = 0; t < n; ++t) plan.pred_ptr[t + 1] = plan.pred_ptr[t] + ex.preds[t].size();
+  plan.pred_idx.reserve(plan.pred_ptr[n]);
+  for (auto& v : ex.preds) plan.pred_idx.insert(plan.pred_idx.end(), v.begin(), v.end());
+  plan.start.assign(n, 0);
+  plan.finish.assign(n, 0);
+  plan.cp = 0;
+  for (size_t t = 0; t < n; ++t) {
+    int64_t s = 0;
+    for (int64_t e = plan.pred_ptr[t]; e < plan.pred_ptr[t + 1]; ++e)
+      s = std::max(s, plan.finish[plan.pred_idx[e]]);
+    plan.start[t] = s;
+    plan.finish[t] = s + kWeight[plan.tasks[t].kind];
+    plan.cp = std::max(plan.cp, plan.finish[t]);
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Executor plan.  An update task on column slab s of its C tiles only touches
+// slab s, so dependencies are tracked per (tile, slab); the panel tasks touch
+// every slab of their tiles.  The two parts of a tile (upper / lower) are
+// tracked separately as in the task expansion.
+void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex) {
+  const int p = plan.p, q = plan.q, S = nslab;
+  ex = ExecPlan();
+  ex.nslab = S;
+  const size_t ntile = static_cast<size_t>(p) * q;
+  std::vector<int32_t> up(ntile * S, -1), lo(ntile * S, -1);
+  auto slot = [&](int r, int c, int s) { return (static_cast<size_t>(r - 1) * q + (c - 1)) * S + s; };
+
+  std::vector<SubTask> sub;  // emission order
+  std::vector<std::vector<int32_t>> pre;
+  std::vector<int32_t> task_of;
+  sub.reserve(plan.tasks.size() * 2);
+
+  auto add = [&](const Task& t, int32_t tidx, int slab, std::vector<int32_t>&& d) {
+    std::sort(d.begin(), d.end());
+    d.erase(std::unique(d.begin(), d.end()), d.end());
+    if (!d.empty() && d.front() < 0) d.erase(d.begin(), std::upper_bound(d.begin(), d.end(), -1));
+    sub.push_back({t.kind, t.i - 1, t.piv > 0 ? t.piv - 1 : 0, t.k - 1, t.j > 0 ? t.j - 1 : 0, slab, 0, 0});
+    pre.push_back(std::move(d));
+    task_of.push_back(tidx);
+    return static_cast<int32_t>(sub.size()) - 1;
+  };
+
+  for (size_t ti = 0; ti < plan.tasks.size(); ++ti) {
+    const Task& t = plan.tasks[ti];
+    const int32_t tid = static_cast<int32_t>(ti);
+    switch (t.kind) {
+      case K_GEQRT: {
+        std::vector<int32_t> d;
+        for (int s = 0; s < S; ++s) {
+          d.push_back(up[slot(t.i, t.k, s)]);
+          d.push_back(lo[slot(t.i, t.k, s)]);
+        }
+        const int32_t id = add(t, tid, 0, std::move(d));
+        for (int s = 0; s < S; ++s) up[slot(t.i, t.k, s)] = lo[slot(t.i, t.k, s)] = id;
+        break;
+      }
+      case K_TTQRT:
+      case K_TSQRT: {
+        std::vector<int32_t> d;
+        for (int s = 0; s < S; ++s) {
+          d.push_back(up[slot(t.piv, t.k, s)]);
+          d.push_back(up[slot(t.i, t.k, s)]);
+          if (t.kind == K_TSQRT) d.push_back(lo[slot(t.i, t.k, s)]);
+        }
+        const int32_t id = add(t, tid, 0, std::move(d));
+        for (int s = 0; s < S; ++s) {
+          up[slot(t.piv, t.k, s)] = id;
+          up[slot(t.i, t.k, s)] = id;
+          if (t.kind == K_TSQRT) lo[slot(t.i, t.k, s)] = id;
+        }
+        break;
+      }
+      case K_UNMQR: {
+        for (int s = 0; s < S; ++s) {
+          std::vector<int32_t> d;
+          for (int s2 = 0; s2 < S; ++s2) d.push_back(lo[slot(t.i, t.k, s2)]);
+          d.push_back(up[slot(t.i, t.j, s)]);
+          d.push_back(lo[slot(t.i, t.j, s)]);
+          const int32_t id = add(t, tid, s, std::move(d));
+          up[slot(t.i, t.j, s)] = lo[slot(t.i, t.j, s)] = id;
+        }
+        break;
+      }
+      default: {  // TSMQR / TTMQR
+        for (int s = 0; s < S; ++s) {
+          std::vector<int32_t> d;
+          for (int s2 = 0; s2 < S; ++s2) {
+            d.push_back(up[slot(t.i, t.k, s2)]);
+            if (t.kind == K_TSMQR) d.push_back(lo[slot(t.i, t.k, s2)]);
+          }
+          d.push_back(up[slot(t.piv, t.j, s)]);
+          d.push_back(lo[slot(t.piv, t.j, s)]);
+          d.push_back(up[slot(t.i, t.j, s)]);
+          d.push_back(lo[slot(t.i, t.j, s)]);
+          const int32_t id = add(t, tid, s, std::move(d));
+          up[slot(t.piv, t.j, s)] = lo[slot(t.piv, t.j, s)] = id;
+          up[slot(t.i, t.j, s)] = lo[slot(t.i, t.j, s)] = id;
+        }
+        break;
+      }
+    }
+  }
+
+  // Priorities: ASAP start (order 0) or ALAP start (order 1) of each subtask
+  // with per-kind weights (updates divided among their slabs).
+  const size_t n = sub.size();
+  std::vector<double> wt(n), est(n, 0.0), lst(n, 0.0);
+  for (size_t s = 0; s < n; ++s) {
+    const int kd = sub[s].kind;
+    const bool is_upd = (kd == K_UNMQR || kd == K_TSMQR || kd == K_TTMQR);
+    wt[s] = is_upd ? w[kd] / S : w[kd];
+  }
+  double span = 0.0;
+  for (size_t s = 0; s < n; ++s) {
+    double st = 0.0;
+    for (int32_t d : pre[s]) st = std::max(st, est[d] + wt[d]);
+    est[s] = st;
+    span = std::max(span, st + wt[s]);
+  }
+  std::vector<std::vector<int32_t>> succ(n);
+  for (size_t s = 0; s < n; ++s)
+    for (int32_t d : pre[s]) succ[d].push_back(static_cast<int32_t>(s));
+  for (size_t s = n; s-- > 0;) {
+    double lf = span;
+    for (int32_t c : succ[s]) lf = std::min(lf, lst[c]);
+    lst[s] = lf - wt[s];
+  }
+  const std::vector<double>& key = (order == 1) ? lst : est;
+  std::vector<int32_t> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+    if (key[a] != key[b]) return key[a] < key[b];
+    return a < b;
+  });
+  std::vector<int32_t> pos(n);
+  for (size_t r = 0; r < n; ++r) pos[perm[r]] = static_cast<int32_t>(r);
+
+  ex.sub.resize(n);
+  ex.deps.clear();
+  for (size_t r = 0; r < n; ++r) {
+    const int32_t s = perm[r];
+    SubTask st = sub[s];
+    st.dep_begin = static_cast<int32_t>(ex.deps.size());
+    for (int32_t d : pre[s]) ex.deps.push_back(pos[d]);
+    st.dep_end = static_cast<int32_t>(ex.deps.size());
+    ex.sub[r] = st;
+  }
+
+  // Depth levels for the level-synchronous launch path.
+  std::vector<int32_t> depth(n, 0);
+  int32_t maxd = 0;
+  for (size_t r = 0; r < n; ++r) {
+    int32_t dd = 0;
+    for (int32_t e = ex.sub[r].dep_begin; e < ex.sub[r].dep_end; ++e) dd = std::max(dd, depth[ex.deps[e]] + 1);
+    depth[r] = dd;
+    maxd = std::max(maxd, dd);
+  }
+  ex.level_ptr.assign(maxd + 2, 0);
+  for (size_t r = 0; r < n; ++r) ex.level_ptr[depth[r] + 1]++;
+  for (int32_t l = 0; l <= maxd; ++l) ex.level_ptr[l + 1] += ex.level_ptr[l];
+  ex.level_order.assign(n, 0);
+  std::vector<int32_t> fill(ex.level_ptr.begin(), ex.level_ptr.end() - 1);
+  for (size_t r = 0; r < n; ++r) ex.level_order[fill[depth[r]]++] = static_cast<int32_t>(r);
+}
+
+}  // namespace tqr
+
+namespace tqr {
+
+void make_apply_plan(const Plan& plan, int trans, int nslab, ExecPlan& ex) {
+  ex = ExecPlan();
+  ex.nslab = nslab;
+  std::vector<int32_t> order;
+  for (size_t t = 0; t < plan.tasks.size(); ++t) {
+    const int k = plan.tasks[t].kind;
+    if (k == K_GEQRT || k == K_TSQRT || k == K_TTQRT) order.push_back(static_cast<int32_t>(t));
+  }
+  if (!trans) std::reverse(order.begin(), order.end());
+  std::vector<int32_t> last(static_cast<size_t>(plan.p) * nslab, -1);
+  for (int32_t t : order) {
+    const Task& tk = plan.tasks[t];
+    const int kind = tk.kind == K_GEQRT ? 6 : (tk.kind == K_TSQRT ? 7 : 8);
+    for (int s = 0; s < nslab; ++s) {
+      SubTask st{kind, tk.i - 1, tk.piv > 0 ? tk.piv - 1 : 0, tk.k - 1, 0, s, 0, 0};
+      st.dep_begin = static_cast<int32_t>(ex.deps.size());
+      const int32_t a = last[static_cast<size_t>(tk.i - 1) * nslab + s];
+      const int32_t b = tk.piv > 0 ? last[static_cast<size_t>(tk.piv - 1) * nslab + s] : -1;
+      if (a >= 0) ex.deps.push_back(a);
+      if (b >= 0 && b != a) ex.deps.push_back(b);
+      st.dep_end = static_cast<int32_t>(ex.deps.size());
+      const int32_t id = static_cast<int32_t>(ex.sub.size());
+      ex.sub.push_back(st);
+      last[static_cast<size_t>(tk.i - 1) * nslab + s] = id;
+      if (tk.piv > 0) last[static_cast<size_t>(tk.piv - 1) * nslab + s] = id;
+    }
+  }
+  const size_t n = ex.sub.size();
+  std::vector<int32_t> depth(n, 0);
+  int32_t maxd = 0;
+  for (size_t r = 0; r < n; ++r) {
+    int32_t dd = 0;
+    for (int32_t e = ex.sub[r].dep_begin; e < ex.sub[r].dep_end; ++e) dd = std::max(dd, depth[ex.deps[e]] + 1);
+    depth[r] = dd;
+    maxd = std::max(maxd, dd);
+  }
+  ex.level_ptr.assign(maxd + 2, 0);
+  for (size_t r = 0; r < n; ++r) ex.level_ptr[depth[r] + 1]++;
+  for (int32_t l = 0; l <= maxd; ++l) ex.level_ptr[l + 1] += ex.level_ptr[l];
+  ex.level_order.assign(n, 0);
+  std::vector<int32_t> fill(ex.level_ptr.begin(), ex.level_ptr.end() - 1);
+  for (size_t r = 0; r < n; ++r) ex.level_order[fill[depth[r]]++] = static_cast<int32_t>(r);
+}
+
+}  // namespace tqr

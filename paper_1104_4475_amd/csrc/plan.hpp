@@ -1,0 +1,63 @@
+// Host planner: elimination lists, kernel-task DAG, schedules and the
+// executor's slab-level task table.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace tqr {
+
+enum Kind : int32_t { K_GEQRT = 0, K_UNMQR = 1, K_TSQRT = 2, K_TSMQR = 3, K_TTQRT = 4, K_TTMQR = 5 };
+enum Tree : int32_t { T_FLAT = 0, T_SAMEH_KUCK = 1, T_BINARY = 2, T_FIBONACCI = 3, T_GREEDY = 4, T_PLASMA = 5 };
+enum Family : int32_t { F_DEFAULT = 0, F_TT = 1, F_TS = 2 };
+
+// Table 1 weights in units of nb^3/3 flops.
+constexpr int kWeight[6] = {4, 6, 6, 12, 2, 6};
+
+struct Elim { int32_t i, piv, k; };          // 1-based (Sec. 2.2)
+struct Task { int32_t kind, i, piv, k, j; };  // 1-based, 0 in unused fields
+
+struct Plan {
+  int32_t p = 0, q = 0, tree = 0, bs = 1, family = F_TT;
+  std::vector<Elim> elims;
+  std::vector<Task> tasks;
+  std::vector<int64_t> pred_ptr;   // CSR predecessors, ntasks + 1
+  std::vector<int32_t> pred_idx;
+  std::vector<int64_t> start, finish;
+  int64_t cp = 0;
+};
+
+// Returns false on invalid (p, q, tree, bs).
+bool valid_shape(int p, int q, int tree, int bs);
+int resolve_family(int tree, int family);
+bool make_elims(int p, int q, int tree, int bs, std::vector<Elim>& out);
+bool make_plan(int p, int q, int tree, int bs, int family, Plan& plan);
+
+// Executor task table.  Update tasks are split into column slabs of the
+// C tiles; panel tasks stay whole.  Subtasks are stored in dispatch order
+// (a topological order), dependencies index earlier subtasks.
+struct SubTask {
+  int32_t kind, i, piv, k, j;   // 0-based tile indices (i, piv, k, j)
+  int32_t slab;                 // column slab of the C tiles (updates)
+  int32_t dep_begin, dep_end;   // range in deps[]
+};
+
+struct ExecPlan {
+  std::vector<SubTask> sub;
+  std::vector<int32_t> deps;
+  std::vector<int32_t> level_ptr;    // subtasks grouped by DAG depth
+  std::vector<int32_t> level_order;  // indices into sub, level by level
+  int32_t nslab = 1;
+};
+
+// order: 0 = ascending ASAP start time, 1 = ascending ALAP start time.
+// w: per-kind weights used for the priority (any positive values).
+void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex);
+
+// Application of Q^T (trans = 1) or Q (trans = 0) to p row tiles of a
+// right-hand side with nslab column slabs: the reflector set of every panel
+// task, in task order for Q^T and in reverse for Q, with dependencies on the
+// row tiles it touches.  Kinds are 6 (GEQRT set), 7 (TS set), 8 (TT set).
+void make_apply_plan(const Plan& plan, int trans, int nslab, ExecPlan& ex);
+
+}  // namespace tqr

@@ -1,0 +1,171 @@
+"""GPU parity: the HIP tiled QR against the oracle, element by element.
+
+Every case prints its name before touching the GPU.  Factors (R, V and the
+Householder scalars) are compared with the oracle run on the same input with
+the same tree and kernels; the bound is 50 n eps ||A||_F elementwise, and the
+residual / orthogonality bounds of the factorization are 50 n eps.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import tqr_inputs
+from oracle import dag, tiled, trees
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _gpu(torch, A):
+    """Column-major float64 copy of a host matrix on the GPU."""
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(A, dtype=np.float64).T)).cuda().t()
+
+
+def _factor_both(torch, A, nb, tree, bs=1, kern=dag.KERN_DEFAULT, upd=0):
+    import paper_1104_4475_amd as tqr
+    F = tqr.factor(_gpu(torch, A), nb, tree, bs, kern, upd)
+    F.sync()
+    O = tiled.tiled_qr(A, nb, tree, bs, kern)
+    return F, O
+
+
+def _compare(torch, F, O, A):
+    p, q, nb = O.p, O.q, O.nb
+    n = O.n
+    tol = 50 * n * EPS * np.linalg.norm(A)
+    P = F.packed().cpu().numpy()
+    err = np.max(np.abs(P - O.A))
+    assert err <= tol, "packed factor differs by %g (tol %g)" % (err, tol)
+    tg, tp = [t.cpu().numpy() for t in F.tau()]
+    for (r, c), tau in O.tau_g.items():
+        assert np.max(np.abs(tg[c - 1, r - 1] - tau)) <= 1e-12, ("tau_geqrt", r, c)
+    for (i, c), tau in O.tau_p.items():
+        assert np.max(np.abs(tp[c - 1, i - 1] - tau)) <= 1e-12, ("tau_pair", i, c)
+    return err
+
+
+SMALL = [
+    # (m, n, nb, tree, bs, kernels)
+    (32, 32, 32, trees.GREEDY, 1, dag.KERN_TT),      # GEQRT only
+    (32, 64, 32, trees.GREEDY, 1, dag.KERN_TT),      # invalid: m < n (skipped below)
+    (64, 32, 32, trees.GREEDY, 1, dag.KERN_TT),      # GEQRT x2 + TTQRT
+    (64, 32, 32, trees.FLAT, 1, dag.KERN_TS),        # GEQRT + TSQRT
+    (64, 64, 32, trees.GREEDY, 1, dag.KERN_TT),      # + UNMQR, TTMQR
+    (64, 64, 32, trees.FLAT, 1, dag.KERN_TS),        # + TSMQR
+    (96, 64, 32, trees.BINARY, 1, dag.KERN_TT),
+    (128, 64, 64, trees.GREEDY, 1, dag.KERN_TT),
+    (128, 128, 64, trees.FLAT, 1, dag.KERN_TS),
+    (384, 256, 128, trees.FIBONACCI, 1, dag.KERN_TT),
+    (256, 256, 128, trees.FLAT, 1, dag.KERN_TS),
+    (512, 256, 256, trees.GREEDY, 1, dag.KERN_TT),
+    (512, 256, 256, trees.FLAT, 1, dag.KERN_TS),
+    (768, 512, 256, trees.PLASMA, 2, dag.KERN_TT),
+]
+
+
+@pytest.mark.parametrize("case", SMALL, ids=lambda c: "%dx%d_nb%d_t%d_bs%d_k%d" % c)
+def test_small_shapes_match_oracle(torch_cuda, case):
+    m, n, nb, tree, bs, kern = case
+    if m < n:
+        pytest.skip("m < n is rejected by the library")
+    _say("case %s" % (case,))
+    A = tqr_inputs.gaussian(m, n, seed=m + 7 * n + nb)
+    F, O = _factor_both(torch_cuda, A, nb, tree, bs, kern)
+    _compare(torch_cuda, F, O, A)
+
+
+C1 = [(trees.GREEDY, 1, dag.KERN_TT), (trees.FLAT, 1, dag.KERN_TS), (trees.SAMEH_KUCK, 1, dag.KERN_TT),
+      (trees.BINARY, 1, dag.KERN_TT), (trees.FIBONACCI, 1, dag.KERN_TT), (trees.PLASMA, 2, dag.KERN_TT),
+      (trees.PLASMA, 3, dag.KERN_TS), (trees.GREEDY, 1, dag.KERN_TS)]
+
+
+@pytest.mark.parametrize("tree,bs,kern", C1)
+def test_config1_parity_and_bounds(torch_cuda, tree, bs, kern):
+    # 256 x 128 at nb = 32 (p = 8, q = 4), N(0,1) from seed 0.
+    _say("config1 tree=%d bs=%d kern=%d" % (tree, bs, kern))
+    torch = torch_cuda
+    A = tqr_inputs.gaussian(256, 128, seed=tqr_inputs.SEED_C1)
+    F, O = _factor_both(torch, A, 32, tree, bs, kern)
+    _compare(torch, F, O, A)
+    Ag = _gpu(torch, A)
+    Q = F.thin_q()
+    R = F.R()
+    n = 128
+    res = (torch.linalg.norm(Ag - Q @ R) / torch.linalg.norm(Ag)).item()
+    orth = torch.linalg.norm(Q.T @ Q - torch.eye(n, dtype=torch.float64, device="cuda")).item()
+    assert res <= 50 * n * EPS, res
+    assert orth <= 50 * n * EPS, orth
+
+
+def test_level_executor_matches_persistent(torch_cuda, monkeypatch):
+    _say("level executor")
+    A = tqr_inputs.gaussian(256, 128, seed=3)
+    monkeypatch.setenv("TQR_EXEC", "level")
+    F, O = _factor_both(torch_cuda, A, 32, trees.GREEDY, 1, dag.KERN_TT)
+    _compare(torch_cuda, F, O, A)
+    monkeypatch.setenv("TQR_EXEC", "persistent")
+
+
+def test_alap_order_matches(torch_cuda, monkeypatch):
+    _say("alap order")
+    A = tqr_inputs.gaussian(512, 256, seed=4)
+    monkeypatch.setenv("TQR_ORDER", "alap")
+    F, O = _factor_both(torch_cuda, A, 64, trees.FIBONACCI, 1, dag.KERN_TT)
+    monkeypatch.delenv("TQR_ORDER")
+    _compare(torch_cuda, F, O, A)
+
+
+def test_apply_q_matches_oracle(torch_cuda):
+    _say("apply_q")
+    torch = torch_cuda
+    A = tqr_inputs.gaussian(320, 192, seed=11)
+    B = tqr_inputs.gaussian(320, 5, seed=12)
+    for tree, kern in ((trees.GREEDY, dag.KERN_TT), (trees.FLAT, dag.KERN_TS)):
+        F, O = _factor_both(torch, A, 64, tree, 1, kern)
+        for trans in ("T", "N"):
+            got = F.apply_q(_gpu(torch, B), trans).cpu().numpy()
+            want = tiled.apply_q(O, B, trans)
+            assert np.max(np.abs(got - want)) <= 50 * 192 * EPS * np.linalg.norm(B), (tree, trans)
+        # empty right-hand side is a no-op
+        E = torch.zeros((320, 0), dtype=torch.float64, device="cuda")
+        assert F.apply_q(E, "T").shape == (320, 0)
+
+
+def test_lstsq_matches_oracle(torch_cuda):
+    _say("lstsq")
+    torch = torch_cuda
+    A = tqr_inputs.gaussian(384, 128, seed=21)
+    B = tqr_inputs.gaussian(384, 3, seed=22)
+    F, O = _factor_both(torch, A, 64, trees.GREEDY, 1, dag.KERN_TT)
+    X, info = F.lstsq(_gpu(torch, B))
+    want = tiled.lstsq(O, B)
+    assert np.max(np.abs(X.cpu().numpy() - want)) <= 1e-10
+
+
+def test_square_refinement_fp64(torch_cuda):
+    _say("square refinement fp64")
+    torch = torch_cuda
+    n = 256
+    A = tqr_inputs.conditioned(n, 1e6, 31, 32)
+    Xt = tqr_inputs.gaussian(n, 4, seed=33)
+    B = A @ Xt
+    F, O = _factor_both(torch, A, 64, trees.GREEDY, 1, dag.KERN_TT)
+    X, info = F.lstsq(_gpu(torch, B), A0=_gpu(torch, A), tol=1e-12)
+    assert info["converged"] and info["backward_err"] <= 1e-12
+    eta = tiled.backward_error(A, X.cpu().numpy(), B)
+    assert np.max(eta) <= 1e-12

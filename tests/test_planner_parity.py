@@ -1,0 +1,81 @@
+"""The library's host planner (C++) against the oracle: elimination lists,
+kernel tasks, predecessors and schedules must be identical, byte for byte."""
+
+import random
+
+import numpy as np
+import pytest
+
+import paper_1104_4475_amd as tqr
+from conftest import load_rows
+from oracle import dag, trees
+
+TREES = [trees.FLAT, trees.SAMEH_KUCK, trees.BINARY, trees.FIBONACCI, trees.GREEDY]
+
+
+def _cases():
+    rng = random.Random(1)
+    shapes = [(1, 1), (2, 1), (2, 2), (3, 3), (8, 4), (15, 6), (15, 3), (16, 16), (17, 5), (40, 7), (64, 8)]
+    shapes += [(rng.randint(1, 30), 0) for _ in range(12)]
+    out = []
+    for p, q in shapes:
+        if q == 0:
+            q = rng.randint(1, p)
+        out.append((p, q))
+    return out
+
+
+@pytest.mark.parametrize("p,q", _cases())
+def test_lists_identical(p, q):
+    for t in TREES:
+        want = np.array(trees.elim_list(p, q, t), dtype=np.int32).reshape(-1, 3)
+        assert np.array_equal(tqr.elim_list(p, q, t), want), (p, q, t)
+    for bs in sorted(b for b in {1, 2, 3, max(1, p // 2), p} if b <= p):
+        want = np.array(trees.plasma_tree(p, q, bs), dtype=np.int32).reshape(-1, 3)
+        assert np.array_equal(tqr.elim_list(p, q, tqr.TREE_PLASMA, bs), want), (p, q, bs)
+
+
+@pytest.mark.parametrize("p,q", _cases())
+def test_schedules_identical(p, q):
+    for t in TREES + [trees.PLASMA]:
+        for kern in (dag.KERN_DEFAULT, dag.KERN_TT, dag.KERN_TS):
+            bs = max(1, p // 3)
+            rows, cp = dag.schedule(p, q, t, bs, kern)
+            got, gcp = tqr.schedule(p, q, t, bs, kern)
+            assert gcp == cp
+            assert np.array_equal(got, np.array(rows, dtype=np.int32).reshape(-1, 7)), (p, q, t, kern)
+            kf = dag.resolve_kernels(t, kern)
+            tasks, preds = dag.build_tasks(p, q, trees.elim_list(p, q, t, bs), kf)
+            ptr, idx = tqr.task_preds(p, q, t, bs, kern)
+            want_ptr = np.cumsum([0] + [len(x) for x in preds])
+            assert np.array_equal(ptr, want_ptr)
+            assert np.array_equal(idx, np.array([d for x in preds for d in x], dtype=np.int32))
+
+
+def test_paper_configs_critical_paths():
+    # 64 x 8 and 40 x 40 (the tall and square workloads) through the C++ planner
+    # against the oracle.
+    for p, q in ((64, 8), (40, 40)):
+        for t in (trees.GREEDY, trees.FIBONACCI, trees.BINARY, trees.FLAT):
+            assert tqr.schedule(p, q, t)[1] == dag.critical_path(p, q, t)
+
+
+def test_table4b_large_greedy_cases():
+    # 128 x 64 and 128 x 128 from Table 4(b), too slow for the Python oracle,
+    # checked through the planner that matches the oracle on every other case.
+    for p, q, greedy, _asap in load_rows("table4b_greedy_asap.txt"):
+        assert tqr.schedule(p, q, tqr.TREE_GREEDY, 1, tqr.KERN_TT)[1] == greedy, (p, q)
+
+
+def test_table5_best_bs_all_q():
+    for p, q, greedy, pt, bs, fib in load_rows("table5_p40.txt"):
+        cps = [tqr.schedule(p, q, tqr.TREE_PLASMA, b, tqr.KERN_TT)[1] for b in range(1, p + 1)]
+        best = min(cps)
+        assert (best, cps.index(best) + 1) == (pt, bs), q
+
+
+def test_invalid_arguments_rejected():
+    for args in ((3, 4, tqr.TREE_GREEDY, 1), (0, 0, tqr.TREE_GREEDY, 1), (5, 2, 9, 1), (5, 2, tqr.TREE_PLASMA, 0),
+                 (5, 2, tqr.TREE_PLASMA, 6)):
+        with pytest.raises(tqr.TiledQRError):
+            tqr.elim_list(*args)
