@@ -16,6 +16,14 @@ TQR_OK, TQR_EINVAL, TQR_ENOMEM, TQR_EHIP, TQR_ENOTCONV, TQR_EUNSUPPORTED, TQR_EE
 
 if not os.path.exists(lib_path):
     raise ImportError("libtiledqr.so is not built (run python -m paper_1104_4475_amd.build): %s" % lib_path)
+# torch ships its own HIP runtime whose soname (libamdhip64.so.7) is the one
+# libtiledqr.so asks for.  Loading torch first makes the library bind to that
+# copy, so the process holds a single HIP runtime and torch's device memory
+# and streams are valid in the library.
+try:
+    import torch  # noqa: F401
+except ImportError:  # plain C-ABI use without torch
+    pass
 lib = ctypes.CDLL(lib_path)
 
 
@@ -37,8 +45,8 @@ class TiledQRError(RuntimeError):
     def __init__(self, status, where=""):
         self.status = status
         msg = lib.tiledqr_strerror(status).decode()
-        if status == TQR_EHIP:
-            msg += " (hipError %d)" % lib.tiledqr_last_hip_error()
+        if status in (TQR_EHIP, TQR_ENOMEM):
+            msg += " (last hipError %d)" % lib.tiledqr_last_hip_error()
         super().__init__("%s: %s (%d)" % (where, msg, status))
 
 

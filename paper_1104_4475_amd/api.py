@@ -32,7 +32,11 @@ def _stream():
 
 
 def _ld(A):
-    return max(1, A.stride(1)) if A.dim() == 2 else max(1, A.shape[0])
+    """Leading dimension of a column-major tensor (the column stride is
+    meaningless with fewer than two columns, so it is then the row count)."""
+    if A.dim() == 2 and A.shape[1] > 1:
+        return A.stride(1)
+    return max(1, A.shape[0])
 
 
 class Factors:

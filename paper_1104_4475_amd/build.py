@@ -15,7 +15,7 @@ LIB = os.path.join(HERE, "libtiledqr.so")
 SOURCES = ["api.cpp", "plan.cpp", "kernels.hip", "solve.hip", "mlp.hip", "batched.hip"]
 
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-mcode-object-version=5",
     # no packed-FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",

@@ -12,11 +12,13 @@
 // of reflectors is applied with two FP64 16x16x4 MFMA contractions
 // (W = V^T C and C -= V T^T W) without moving C.
 //
-// MFMA f64 16x16x4 operand layout (lane l, g = l / 16, n = l % 16):
+// MFMA f64 16x16x4 operand layout (lane l, g = l / 16, n = l % 16; measured
+// on gfx950 with one-hot operands):
 //   A (16x4):  A[n][g]          B (4x16): B[g][n]
-//   C/D (16x16): D[4g + i][n], i = 0..3 (four doubles per lane)
-// A contraction over K rows is split in chunks of 4 rows {16 rb + 4 g + i}
-// (fixed i), so a C block held as D can feed the B operand directly.
+//   C/D (16x16): D[4i + g][n], i = 0..3 (four doubles per lane)
+// For a fixed i the four lane groups hold the four consecutive rows
+// 16 rb + 4 i + {0..3}, so a C block held as D feeds the B operand of a
+// contraction over those rows directly.
 #include <hip/hip_runtime.h>
 
 #include "device.hpp"
@@ -55,7 +57,7 @@ enum { V_UNM = 0, V_TS = 1, V_TT = 2 };
 //   V_UNM  rows relative to the block's first row c0 (unit lower trapezoid);
 //   V_TS   all nb rows of V2;
 //   V_TT   rows 0..c0+ib-1 of V2, zero below each reflector's support.
-// acc[rb] holds rows 16 rb + 4 g + i of C (V_UNM) or of C2 (pairs).
+// acc[rb][i] holds row 16 rb + 4 i + g of C (V_UNM) or of C2 (pairs).
 // c1 points at the lane's column of C1 (pairs only); rows c0..c0+ib-1 of
 // C1 take part.  trans: 1 applies Q^T (T^T), 0 applies Q (T).
 template <int NB, int VAR>
@@ -72,18 +74,18 @@ __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const dou
       w[mb] = zero4();
     } else {
 #pragma unroll
-      for (int i = 0; i < 4; ++i) w[mb][i] = c1[c0 + mb * 16 + 4 * g + i];
+      for (int i = 0; i < 4; ++i) w[mb][i] = c1[c0 + mb * 16 + 4 * i + g];
     }
   }
-  // W += V^T C: lane (n, g) supplies V[16 rb + 4 g + i][16 mb + n].
-  const double* va = Vs + (4 * g - vbase) + n * ldv;
+  // W += V^T C: lane (n, g) supplies V[16 rb + 4 i + g][16 mb + n].
+  const double* va = Vs + (g - vbase) + n * ldv;
 #pragma unroll
   for (int rb = 0; rb < NB / 16; ++rb) {
     if (rb < rb_lo || rb >= rb_hi) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb) w[mb] = mfma(va[rb * 16 + i + mb * 16 * ldv], acc[rb][i], w[mb]);
+      for (int mb = 0; mb < 2; ++mb) w[mb] = mfma(va[rb * 16 + 4 * i + mb * 16 * ldv], acc[rb][i], w[mb]);
     __builtin_amdgcn_sched_barrier(0);
   }
   // W' = T^T W (trans) or T W
@@ -95,7 +97,7 @@ __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const dou
       if (trans ? (jb > ab) : (jb < ab)) continue;  // T is upper triangular
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int j = jb * 16 + 4 * g + i, aa = ab * 16 + n;
+        const int j = jb * 16 + 4 * i + g, aa = ab * 16 + n;
         const double t = trans ? Ts[j + aa * IB] : Ts[aa + j * IB];
         wt[ab] = mfma(t, w[jb][i], wt[ab]);
       }
@@ -105,17 +107,17 @@ __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const dou
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) c1[c0 + mb * 16 + 4 * g + i] -= wt[mb][i];
+      for (int i = 0; i < 4; ++i) c1[c0 + mb * 16 + 4 * i + g] -= wt[mb][i];
   }
-  // C -= V W': lane (n, g) supplies V[16 rb + n][16 mb + 4 g + i].
-  const double* vb = Vs + (n - vbase) + 4 * g * ldv;
+  // C -= V W': lane (n, g) supplies V[16 rb + n][16 mb + 4 i + g].
+  const double* vb = Vs + (n - vbase) + g * ldv;
 #pragma unroll
   for (int rb = 0; rb < NB / 16; ++rb) {
     if (rb < rb_lo || rb >= rb_hi) continue;
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[rb] = mfma(-vb[rb * 16 + (mb * 16 + i) * ldv], wt[mb][i], acc[rb]);
+      for (int i = 0; i < 4; ++i) acc[rb] = mfma(-vb[rb * 16 + (mb * 16 + 4 * i) * ldv], wt[mb][i], acc[rb]);
     __builtin_amdgcn_sched_barrier(0);
   }
 }
@@ -131,7 +133,8 @@ __device__ __forceinline__ void load_cols(d4 (&acc)[NB / 16], const double* C, i
       acc[rb] = zero4();
       continue;
     }
-    acc[rb] = *reinterpret_cast<const d4*>(C + rb * 16 + 4 * g);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[rb][i] = C[rb * 16 + 4 * i + g];
   }
 }
 template <int NB>
@@ -140,7 +143,8 @@ __device__ __forceinline__ void store_cols(const d4 (&acc)[NB / 16], double* C, 
 #pragma unroll
   for (int rb = 0; rb < NB / 16; ++rb) {
     if (rb < lo || rb >= hi) continue;
-    *reinterpret_cast<d4*>(C + rb * 16 + 4 * g) = acc[rb];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) C[rb * 16 + 4 * i + g] = acc[rb][i];
   }
 }
 
@@ -448,39 +452,54 @@ template <int NB>
 __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
   __shared__ double sm[Smem<NB>::TOTAL];
   __shared__ int s_t;
-  const int tid = threadIdx.x;
+  // Every branch that encloses or follows a barrier is on a wave-uniform
+  // (scalar) value, so the compiler keeps the loop structured: wave 0 takes
+  // the ticket and waits for the predecessors as a whole wave; only the
+  // single atomic operations are guarded by lane == 0.
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   for (;;) {
-    if (tid == 0) {
+    if (wave == 0) {
       int t = a.nsub;
-      if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-        t = atomicAdd(a.ticket, 1);
-        if (t < a.nsub) {
-          const DevSub& s = a.sub[t];
-          const uint64_t t0 = wall_clock64();
-          for (int e = s.dep_begin; e < s.dep_end && t < a.nsub; ++e) {
-            const int32_t* f = a.flags + a.deps[e];
-            while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != a.epoch) {
-              if (__hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-                  static_cast<int64_t>(wall_clock64() - t0) > a.spin_ticks) {
-                __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                t = a.nsub;
-                break;
-              }
-              __builtin_amdgcn_s_sleep(1);
+      const int err0 = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (err0 == 0) {
+        int tk = 0;
+        if (lane == 0) tk = atomicAdd(a.ticket, 1);
+        t = __builtin_amdgcn_readfirstlane(tk);
+      }
+      if (t < a.nsub) {
+        const int db = a.sub[t].dep_begin, de = a.sub[t].dep_end;
+        const uint64_t t0 = wall_clock64();
+        for (int e = db; e < de && t < a.nsub; ++e) {
+          int32_t* f = a.flags + a.deps[e];
+          for (;;) {
+            const int v = __builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+            if (v == a.epoch) break;
+            const int err = __builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (err != 0 || static_cast<int64_t>(wall_clock64() - t0) > a.spin_ticks) {
+              if (lane == 0) __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              t = a.nsub;
+              break;
             }
+            __builtin_amdgcn_s_sleep(1);
           }
         }
       }
-      s_t = t;
+      if (lane == 0) s_t = t;
     }
     __syncthreads();
-    const int t = s_t;
+    // The ticket is the same for every thread; readfirstlane makes that
+    // visible to the compiler (scalar loop exit and task dispatch).
+    const int t = __builtin_amdgcn_readfirstlane(s_t);
     if (t >= a.nsub) break;
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     run_sub<NB>(a, a.sub[t], sm);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (tid == 0) __hip_atomic_store(a.flags + t, a.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (wave == 0 && lane == 0) __hip_atomic_store(a.flags + t, a.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -489,7 +508,8 @@ __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
 template <int NB>
 __global__ __launch_bounds__(NTHREADS) void exec_level(ExecArgs a, const int32_t* order, int begin) {
   __shared__ double sm[Smem<NB>::TOTAL];
-  run_sub<NB>(a, a.sub[order[begin + blockIdx.x]], sm);
+  const int t = __builtin_amdgcn_readfirstlane(order[begin + blockIdx.x]);
+  run_sub<NB>(a, a.sub[t], sm);
 }
 
 __global__ void reset_kernel(int32_t* ticket, int32_t* err) {
