@@ -1,0 +1,183 @@
+#!/usr/bin/env python
+"""Benchmark of the MI355X tiled QR: one JSON line on stdout.
+
+Default workload: the square least-squares problem A x = b with A 10240 x
+10240 (p = q = 40 tiles of nb = 256) built as U diag(s) V^T from seeded Haar
+U, V and log-spaced singular values (condition number kappa), 4 right-hand
+sides b = A x_true.  One step = factorization + least-squares solve with
+iterative refinement to a backward error of 1e-12 (the hot path).  The plain
+FP64 path (factorization + solve) is timed beside it on the same input.
+
+Throughput counts 2 m n^2 - 2 n^3 / 3 flops per factorization (the
+Householder count, Sec. 2.2 of the paper) per step.  Inputs are resident in
+HBM before the timed region.
+
+Usage: python bench.py [--steps K] [--warmup W] [--upd f32|bf16|f64]
+                       [--workload square|tall] [--kappa K] [--tree greedy]
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+METRIC = "tiled-QR GFLOP/s & % MFMA peak: mixed+refined vs FP64 at equal LS accuracy"
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+TREES = {"flat": 0, "sameh-kuck": 1, "binary": 2, "fibonacci": 3, "greedy": 4, "plasma": 5}
+UPD = {"f64": 0, "f32": 1, "bf16": 2}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["square", "tall"], default="square")
+    ap.add_argument("--kappa", type=float, default=1e2)
+    ap.add_argument("--upd", choices=list(UPD), default="f32")
+    ap.add_argument("--tree", choices=list(TREES), default="greedy")
+    ap.add_argument("--bs", type=int, default=1)
+    ap.add_argument("--nb", type=int, default=256)
+    ap.add_argument("--nrhs", type=int, default=4)
+    ap.add_argument("--tol", type=float, default=1e-12)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def flops(m, n):
+    return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
+
+
+def update_flop_fraction(p, q):
+    """Share of the Table 1 work units spent in update kernels (UNMQR, TSMQR,
+    TTMQR) for TT kernels: total 6pq^2 - 2q^3, panel units GEQRT 4 per
+    triangularized tile and TTQRT 2 per zeroed tile."""
+    total = 6 * p * q * q - 2 * q ** 3
+    panel = sum(4 * (p - k + 1) + 2 * (p - k) for k in range(1, q + 1))
+    return (total - panel) / total
+
+
+def cpu_baseline(nb, tree, bs, kappa):
+    """The FP64 oracle (plain NumPy tiled QR) on a bounded sample of the same
+    workload: the conditioned matrix at 2048 x 2048 (p = q = 8 tiles of the
+    same nb), BLAS limited to one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    import tqr_inputs
+    from oracle import tiled
+    n = 2048
+    A = tqr_inputs.conditioned(n, kappa, 102, 103)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        tiled.tiled_qr(A, nb, tree, bs)
+        dt = time.perf_counter() - t0
+    return {"value": flops(n, n) / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle tiled QR of a %dx%d conditioned matrix (kappa %g), nb=%d, same tree, "
+                      "1 BLAS thread, %.1f s" % (n, n, kappa, nb, dt),
+            "seconds": dt, "host_cpus": len(os.sched_getaffinity(0))}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the tiled QR here is a single-GPU library "
+              "(multi-GPU sharding is a design note, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1104_4475_amd as tqr
+    import tqr_inputs
+
+    dev = "cuda"
+    nb, nrhs = args.nb, args.nrhs
+    if args.workload == "square":
+        m = n = 10240
+        A = tqr_inputs.conditioned_device(n, args.kappa, tqr_inputs.SEED_C3, tqr_inputs.SEED_C3 + 1, dev).t()
+        workload = "square LS %dx%d, kappa %g, nb %d, %d rhs" % (m, n, args.kappa, nb, nrhs)
+    else:
+        m, n = 16384, 2048
+        A = tqr_inputs.gaussian_device(m, n, tqr_inputs.SEED_C2, dev).t()
+        workload = "tall %dx%d N(0,1), nb %d, %d rhs" % (m, n, nb, nrhs)
+    g = torch.Generator(device=dev)
+    g.manual_seed(tqr_inputs.SEED_C3_RHS)
+    Xt = torch.randn((nrhs, n), generator=g, dtype=torch.float64, device=dev).t()
+    B = (A @ Xt).t().contiguous().t()
+    torch.cuda.synchronize()
+    tree = TREES[args.tree]
+    p, q = m // nb, n // nb
+    F = flops(m, n)
+
+    def run(upd, refine):
+        Fh = tqr.factor(A, nb, tree, args.bs, tqr.KERN_DEFAULT, UPD[upd])
+        Fh.sync()
+        tol = args.tol if refine else 0.0
+        for _ in range(args.warmup):
+            Fh.refactor(A)
+            X, info = Fh.lstsq(B, A0=A, tol=tol)
+        torch.cuda.synchronize()
+        times, execs, infos = [], [], []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            Fh.refactor(A)
+            X, info = Fh.lstsq(B, A0=A, tol=tol)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            execs.append(Fh.exec_ms())
+            infos.append(info)
+        Fh.sync()
+        r = B - A @ X
+        eta = (torch.linalg.norm(r, dim=0) /
+               (torch.linalg.norm(A) * torch.linalg.norm(X, dim=0) + torch.linalg.norm(B, dim=0))).max().item()
+        return {"ms_per_step": 1e3 * sum(times) / len(times), "exec_ms": sum(execs) / len(execs),
+                "gflops": F / (sum(times) / len(times)) / 1e9, "backward_err": eta,
+                "refine_iters": infos[-1]["iters"], "converged": infos[-1]["converged"], "X": X}
+
+    fp64 = run("f64", refine=False)
+    main_res = fp64 if args.upd == "f64" else run(args.upd, refine=True)
+    fwd = (torch.linalg.norm(main_res["X"] - fp64["X"]) / torch.linalg.norm(fp64["X"])).item()
+
+    # Dominant kernel: the executor (all tile kernels of the factorization).
+    exec_s = main_res["exec_ms"] / 1e3
+    if args.upd == "f64":
+        peak = PEAK_TFLOPS["f64"]
+    else:
+        fu = update_flop_fraction(p, q)
+        peak = 1.0 / (fu / PEAK_TFLOPS[args.upd] + (1.0 - fu) / PEAK_TFLOPS["f64"])
+    achieved = F / exec_s / 1e12
+    line = {
+        "metric": METRIC,
+        "value": round(main_res["gflops"], 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.upd == "f64" else "f64 panels/residuals + %s MFMA updates" % args.upd,
+        "data": "synthetic",
+        "config": {"workload": workload, "tree": args.tree, "bs": args.bs, "nb": nb, "m": m, "n": n,
+                   "upd": args.upd, "refine_tol": args.tol if args.upd != "f64" else None},
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "kernel": "exec_persistent<%d>" % nb, "kernel_ms": round(main_res["exec_ms"], 3)},
+        "fp64": {"gflops": round(fp64["gflops"], 2), "ms_per_step": round(fp64["ms_per_step"], 3),
+                 "exec_ms": round(fp64["exec_ms"], 3), "backward_err": fp64["backward_err"],
+                 "frac_fp64_peak": round(F / (fp64["exec_ms"] / 1e3) / 1e12 / PEAK_TFLOPS["f64"], 4)},
+        "speedup_vs_fp64": round(main_res["gflops"] / fp64["gflops"], 3),
+        "accuracy": {"backward_err": main_res["backward_err"], "refine_iters": main_res["refine_iters"],
+                     "converged": main_res["converged"], "fwd_diff_vs_fp64": fwd},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(nb, tree, args.bs, args.kappa)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

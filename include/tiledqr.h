@@ -130,6 +130,23 @@ int tiledqr_get_packed(const tqr_factors* F, double* out, int64_t ld, void* stre
  * that zeroed tile (i, c) at (p * q * nb + (c * p + i) * nb). */
 int tiledqr_get_tau(const tqr_factors* F, double* tau, void* stream);
 
+/* Duration in milliseconds of the last factorization's executor kernel (the
+ * persistent launch, or all level launches), measured with HIP events
+ * recorded on the handle's stream around the launch.  Synchronizes on the
+ * end event.  Errors: TQR_EINVAL (no factorization yet), TQR_EHIP. */
+int tiledqr_exec_time(tqr_factors* F, float* ms);
+
+/* Tracing of the persistent executor.  With tracing on, every later
+ * factorization records for each executor subtask (in dispatch order) the
+ * wall-clock tick when its workgroup took the ticket, when its predecessors
+ * were complete, when it finished, and the workgroup index.
+ * tiledqr_get_trace writes 10 int64 per subtask to out (host): kind, i, piv,
+ * k, j (0-based tiles), column slab, ticket, ready, end, workgroup; out may
+ * be NULL to query *n; *ticks_per_second (may be NULL) gets the clock rate.
+ * Synchronizes the handle's stream.  Errors: TQR_EINVAL, TQR_ENOMEM, TQR_EHIP. */
+int tiledqr_set_trace(tqr_factors* F, int enable);
+int tiledqr_get_trace(tqr_factors* F, int64_t* out, int64_t* n, double* ticks_per_second);
+
 /* Release a handle (synchronizes its stream first).  NULL is accepted. */
 int tiledqr_destroy(tqr_factors* F);
 

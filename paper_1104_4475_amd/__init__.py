@@ -14,7 +14,8 @@ from ._lib import (  # noqa: F401
     TQR_OK, TQR_EINVAL, TQR_ENOMEM, TQR_EHIP, TQR_ENOTCONV, TQR_EUNSUPPORTED, TQR_EEXEC,
     TiledQRError, lib, lib_path, Opts, RefineOpts, RefineInfo,
     tiledqr_factor, tiledqr_refactor, tiledqr_sync, tiledqr_apply_q, tiledqr_get_r,
-    tiledqr_get_packed, tiledqr_get_tau, tiledqr_destroy, tiledqr_lstsq,
+    tiledqr_get_packed, tiledqr_get_tau, tiledqr_destroy, tiledqr_lstsq, tiledqr_exec_time,
+    tiledqr_set_trace, tiledqr_get_trace,
     tiledqr_factor_batched, tiledqr_elim_list, tiledqr_schedule, tiledqr_task_preds,
     tiledqr_strerror, elim_list, schedule, task_preds,
 )

@@ -64,6 +64,9 @@ _sigs = {
     "tiledqr_get_packed": (ctypes.c_int, [_vp, _dp, _i64, _vp]),
     "tiledqr_get_tau": (ctypes.c_int, [_vp, _dp, _vp]),
     "tiledqr_destroy": (ctypes.c_int, [_vp]),
+    "tiledqr_exec_time": (ctypes.c_int, [_vp, _P(ctypes.c_float)]),
+    "tiledqr_set_trace": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "tiledqr_get_trace": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(ctypes.c_double)]),
     "tiledqr_lstsq": (ctypes.c_int, [_vp, _dp, _i64, _dp, _i64, _i64, _dp, _i64, _P(RefineOpts), _P(RefineInfo),
                                      _vp]),
     "tiledqr_factor_batched": (ctypes.c_int, [_i32, _P(Opts), _P(_vp), _P(_i64), _P(_vp), _vp]),

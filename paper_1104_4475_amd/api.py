@@ -56,6 +56,28 @@ class Factors:
     def sync(self):
         check(_lib.tiledqr_sync(self.handle), "tiledqr_sync")
 
+    def exec_ms(self):
+        """Duration of the last factorization's executor kernel (HIP events)."""
+        ms = ctypes.c_float()
+        check(_lib.tiledqr_exec_time(self.handle, ctypes.byref(ms)), "tiledqr_exec_time")
+        return ms.value
+
+    def set_trace(self, enable=True):
+        check(_lib.tiledqr_set_trace(self.handle, 1 if enable else 0), "tiledqr_set_trace")
+
+    def trace(self):
+        """Per executor subtask (dispatch order): int64 array (n, 10) =
+        kind, i, piv, k, j, slab, ticket, ready, end, workgroup (ticks), and
+        the tick rate in Hz."""
+        import numpy as np
+        n = ctypes.c_int64()
+        rate = ctypes.c_double()
+        check(_lib.tiledqr_get_trace(self.handle, None, ctypes.byref(n), ctypes.byref(rate)), "tiledqr_get_trace")
+        out = np.zeros((max(1, n.value), 10), dtype=np.int64)
+        check(_lib.tiledqr_get_trace(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                     ctypes.byref(n), ctypes.byref(rate)), "tiledqr_get_trace")
+        return out[:n.value], rate.value
+
     def refactor(self, A):
         A = colmajor(A)
         check(_lib.tiledqr_refactor(self.handle, A.data_ptr(), _ld(A), _stream()), "tiledqr_refactor")

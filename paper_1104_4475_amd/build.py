@@ -12,7 +12,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtiledqr.so")
 
-SOURCES = ["api.cpp", "plan.cpp", "kernels.hip", "solve.hip", "mlp.hip", "batched.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "kernels.hip", "layout.hip", "solve.hip", "mlp.hip", "batched.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-mcode-object-version=5",

@@ -137,8 +137,14 @@ struct tqr_factors {
   int32_t* ctl = nullptr;  // [0] ticket, [1] err
   hipStream_t stream = nullptr;
   int grid = 1;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool timed = false;
+  int64_t* trace = nullptr;  // device, 4 per executor subtask
 
   ~tqr_factors() {
+    if (trace) (void)hipFree(trace);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
     exec.release();
     for (auto& kv : apply) kv.second.release();
     if (tiles) (void)hipFree(tiles);
@@ -169,6 +175,9 @@ ExecArgs base_args(const tqr_factors* F, const DevPlan& d) {
   a.transB = 1;
   a.upd = F->o.upd;
   a.spin_ticks = 4 * wall_ticks_per_second();
+  a.trace = (&d == &F->exec) ? F->trace : nullptr;
+  const char* dbg = std::getenv("TQR_DEBUG");
+  a.debug = dbg ? std::atoi(dbg) : 0;
   return a;
 }
 
@@ -185,7 +194,11 @@ int run_plan(tqr_factors* F, DevPlan& d, ExecArgs a, hipStream_t s) {
     return TQR_OK;
   }
   HIP_TRY(tqr::launch_reset(a.ticket, a.err, s));
-  const int grid = std::max(1, std::min(d.nsub, F->grid));
+  int grid = std::max(1, std::min(d.nsub, F->grid));
+  if (const char* g = std::getenv("TQR_GRID")) {
+    const int want = std::atoi(g);
+    if (want > 0) grid = std::min(grid, want);
+  }
   HIP_TRY(tqr::launch_persistent(a, grid, s));
   return TQR_OK;
 }
@@ -198,6 +211,7 @@ int check_opts(const tqr_opts* o, int64_t lda) {
   if (o->m % o->nb || o->n % o->nb || o->m < o->n) return TQR_EINVAL;
   if (lda < o->m) return TQR_EINVAL;
   if (o->upd < TQR_UPD_F64 || o->upd > TQR_UPD_BF16) return TQR_EINVAL;
+  if (o->upd != TQR_UPD_F64) return TQR_EUNSUPPORTED;
   if (o->kernels < TQR_KERN_DEFAULT || o->kernels > TQR_KERN_TS) return TQR_EINVAL;
   const int64_t p = o->m / o->nb, q = o->n / o->nb;
   if (p > (1 << 20)) return TQR_EINVAL;
@@ -238,7 +252,16 @@ int create(const tqr_opts* o, tqr_factors** out) {
 int factor_into(tqr_factors* F, const double* A, int64_t lda, hipStream_t s) {
   F->stream = s;
   HIP_TRY(tqr::launch_pack(A, lda, F->tiles, F->p, F->q, F->nb, s));
-  return run_plan(F, F->exec, base_args(F, F->exec), s);
+  if (!F->ev0) {
+    HIP_TRY(hipEventCreate(&F->ev0));
+    HIP_TRY(hipEventCreate(&F->ev1));
+  }
+  HIP_TRY(hipEventRecord(F->ev0, s));
+  const int st = run_plan(F, F->exec, base_args(F, F->exec), s);
+  if (st != TQR_OK) return st;
+  HIP_TRY(hipEventRecord(F->ev1, s));
+  F->timed = true;
+  return TQR_OK;
 }
 
 DevPlan* apply_plan(tqr_factors* F, int trans, int nslab, int* st) {
@@ -313,6 +336,54 @@ int tiledqr_sync(tqr_factors* F) {
   int32_t err = 0;
   HIP_TRY(hipMemcpy(&err, F->ctl + 1, sizeof(int32_t), hipMemcpyDeviceToHost));
   return err ? TQR_EEXEC : TQR_OK;
+}
+
+int tiledqr_exec_time(tqr_factors* F, float* ms) {
+  if (!F || !ms || !F->timed) return TQR_EINVAL;
+  HIP_TRY(hipEventSynchronize(F->ev1));
+  HIP_TRY(hipEventElapsedTime(ms, F->ev0, F->ev1));
+  return TQR_OK;
+}
+
+int tiledqr_set_trace(tqr_factors* F, int enable) {
+  if (!F) return TQR_EINVAL;
+  if (enable && !F->trace) {
+    const size_t bytes = 4 * sizeof(int64_t) * std::max<int32_t>(1, F->exec.nsub);
+    if (!hip_ok(hipMalloc(&F->trace, bytes))) return TQR_ENOMEM;
+    HIP_TRY(hipMemset(F->trace, 0, bytes));
+  } else if (!enable && F->trace) {
+    HIP_TRY(hipStreamSynchronize(F->stream));
+    HIP_TRY(hipFree(F->trace));
+    F->trace = nullptr;
+  }
+  return TQR_OK;
+}
+
+int tiledqr_get_trace(tqr_factors* F, int64_t* out, int64_t* n, double* ticks_per_second) {
+  if (!F || !n) return TQR_EINVAL;
+  *n = F->exec.nsub;
+  if (ticks_per_second) *ticks_per_second = static_cast<double>(wall_ticks_per_second());
+  if (!out) return TQR_OK;
+  if (!F->trace) return TQR_EINVAL;
+  HIP_TRY(hipStreamSynchronize(F->stream));
+  std::vector<int64_t> t(4 * static_cast<size_t>(F->exec.nsub));
+  std::vector<DevSub> sub(F->exec.nsub);
+  HIP_TRY(hipMemcpy(t.data(), F->trace, t.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(sub.data(), F->exec.sub, sub.size() * sizeof(DevSub), hipMemcpyDeviceToHost));
+  for (int32_t s = 0; s < F->exec.nsub; ++s) {
+    int64_t* o = out + 10 * static_cast<int64_t>(s);
+    o[0] = sub[s].kind;
+    o[1] = sub[s].i;
+    o[2] = sub[s].piv;
+    o[3] = sub[s].k;
+    o[4] = sub[s].j;
+    o[5] = sub[s].slab;
+    o[6] = t[4 * s];
+    o[7] = t[4 * s + 1];
+    o[8] = t[4 * s + 2];
+    o[9] = t[4 * s + 3];
+  }
+  return TQR_OK;
 }
 
 int tiledqr_destroy(tqr_factors* F) {

@@ -7,7 +7,7 @@
 namespace tqr {
 
 constexpr int IB = 32;        // inner block size of every kernel (Sec. 4: ib = 32)
-constexpr int NTHREADS = 256; // 4 waves of 64 lanes
+constexpr int NTHREADS = 512; // 8 waves of 64 lanes (two per SIMD)
 constexpr int SLAB = 64;      // columns of C per update subtask (16 per wave)
 
 // Executor task kinds: the six tile kernels (Table 1) and the application of
@@ -40,6 +40,8 @@ struct ExecArgs {
   int32_t transB;       // apply_q: 1 = Q^T, 0 = Q
   int32_t upd;          // tqr_update_prec
   int64_t spin_ticks;   // wall-clock ticks a wait may last before giving up
+  int64_t* trace;       // optional: per subtask (ticket, ready, end, workgroup)
+  int32_t debug;        // diagnostics: bit 0 = clear the workgroup's LDS before each task
 };
 
 // Kernel launchers (defined in kernels.hip).

@@ -6,11 +6,14 @@
 //   TSQRT  zero a square tile under a triangle (V2 is the whole tile).
 //   TTQRT  zero a triangle under a triangle (V2 upper triangular).
 //   UNMQR / TSMQR / TTMQR  apply those reflectors to tiles further right.
-// One workgroup of 4 waves runs one task.  Update tasks are split into
-// column slabs of 64 (16 columns per wave); a wave keeps its nb x 16 block
-// of C in FP64 MFMA accumulator layout for the whole task, so each ib-block
-// of reflectors is applied with two FP64 16x16x4 MFMA contractions
-// (W = V^T C and C -= V T^T W) without moving C.
+//
+// One workgroup of 8 waves (two per SIMD) runs one task.  Update tasks are
+// split into column slabs of 64.  The slab is shared by four column groups
+// of 16 columns; the two waves of a group split the rows of C by 16-row
+// block parity and keep them in FP64 MFMA accumulator layout for the whole
+// task.  Each ib-block of reflectors is applied with two FP64 16x16x4 MFMA
+// contractions, W = V^T C (partial sums of the two waves added through LDS)
+// and C -= V (T^T W).
 //
 // MFMA f64 16x16x4 operand layout (lane l, g = l / 16, n = l % 16; measured
 // on gfx950 with one-hot operands):
@@ -26,18 +29,50 @@
 namespace tqr {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+constexpr int NWAVES = NTHREADS / 64;
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
+__device__ __forceinline__ d4 zero4() { return d4{0.0, 0.0, 0.0, 0.0}; }
+__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+__device__ __forceinline__ double uniform_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane(static_cast<int>(b));
+  const int hi = __builtin_amdgcn_readfirstlane(static_cast<int>(b >> 32));
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+__device__ __forceinline__ double lane_d(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), src);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), src);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
-__device__ __forceinline__ d4 zero4() { return d4{0.0, 0.0, 0.0, 0.0}; }
+// One DPP move of a double (two 32-bit halves); lanes outside row_mask or
+// reading an invalid source get 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), CTRL, ROW_MASK, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROW_MASK, 0xf, true);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// Sum over the 64 lanes of a wave, returned to every lane: quad swaps and
+// row rotations give each row of 16 its sum, row_bcast:15 / row_bcast:31
+// carry the row sums into the last row, and lane 63 holds the total.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_d<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x124, 0xf>(v);  // row_ror:4
+  v += dpp_d<0x128, 0xf>(v);  // row_ror:8
+  v += dpp_d<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
+  return lane_d(v, 63);
+}
 
 __device__ __forceinline__ double* tile_ptr(const ExecArgs& a, int r, int c) {
   return a.tiles + (static_cast<size_t>(c) * a.p + r) * static_cast<size_t>(a.nb) * a.nb;
@@ -49,44 +84,179 @@ __device__ __forceinline__ double* tp_ptr(const ExecArgs& a, int r, int c) {
   return a.Tp + (static_cast<size_t>(c) * a.p + r) * static_cast<size_t>(IB) * a.nb;
 }
 
+// LDS of one workgroup, in doubles.
+template <int NB>
+struct Smem {
+  static constexpr int LDP = NB + 1;            // odd leading dimension of blocks
+  static constexpr int PS = 0;                  // reflector / panel block (LDP x IB)
+  static constexpr int TS = PS + LDP * IB;      // T block
+  static constexpr int GS = TS + IB * IB;       // Gram matrix V^T V
+  static constexpr int RS = GS + IB * IB;       // triangle block of R1 (pair kernels)
+  static constexpr int TAU = RS + IB * IB;      // tau of the panel
+  static constexpr int VBUF = TAU + IB;         // current reflector, double buffered
+  static constexpr int WX = VBUF + 2 * NB;      // W exchange: [group 4][half 2][8][64]
+  static constexpr int TOTAL = WX + 4 * 2 * 8 * 64;
+};
+
+// ---------------------------------------------------------------------------
+// Block staging between tiles (column-major, leading dimension NB) and LDS.
+// Wave w handles columns w, w + 8, w + 16, w + 24 of the ib-wide block; a
+// lane handles rows lane + 64 u, so each load instruction reads 64
+// consecutive doubles of one column, and all loads are issued before the
+// LDS writes.
+//   ST_FULL       all K rows.
+//   ST_UNIT_LOWER GEQRT reflectors: rows below the diagonal from src, 1 on
+//                 the diagonal, 0 above (the stored R part is not read).
+//   ST_UPPER      TT reflectors: rows 0..c0+m of column m from src, 0 below
+//                 (the GEQRT reflectors below the diagonal are not read).
+enum { ST_FULL = 0, ST_UNIT_LOWER = 1, ST_UPPER = 2 };
+template <int NB, int MODE>
+__device__ __forceinline__ void stage_block(double* Vs, int ldv, const double* src, int K, int c0) {
+  constexpr int RCH = (NB + 63) / 64;
+  const int lane = lane_id(), wave = wave_id();
+  double v[4][RCH];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int m = wave + NWAVES * c;
+#pragma unroll
+    for (int u = 0; u < RCH; ++u) {
+      const int kk = lane + 64 * u;
+      bool use = kk < K;
+      if (MODE == ST_UNIT_LOWER) use = use && kk > m;
+      if (MODE == ST_UPPER) use = use && kk <= c0 + m;
+      const double fill = (MODE == ST_UNIT_LOWER && kk == m) ? 1.0 : 0.0;
+      v[c][u] = use ? src[m * NB + kk] : fill;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int m = wave + NWAVES * c;
+#pragma unroll
+    for (int u = 0; u < RCH; ++u) {
+      const int kk = lane + 64 * u;
+      if (kk < K) Vs[kk + m * ldv] = v[c][u];
+    }
+  }
+}
+
+// LDS block back to the tile; with UPPER_ONLY, rows 0..c0+m of column m.
+template <int NB, bool UPPER_ONLY>
+__device__ __forceinline__ void unstage_block(const double* Vs, int ldv, double* dst, int K, int c0) {
+  constexpr int RCH = (NB + 63) / 64;
+  const int lane = lane_id(), wave = wave_id();
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int m = wave + NWAVES * c;
+#pragma unroll
+    for (int u = 0; u < RCH; ++u) {
+      const int kk = lane + 64 * u;
+      if (kk < K && (!UPPER_ONLY || kk <= c0 + m)) dst[m * NB + kk] = Vs[kk + m * ldv];
+    }
+  }
+}
+
+// ib x ib T block (contiguous) into LDS.
+__device__ __forceinline__ void stage_t(double* Ts, const double* T) {
+  constexpr int PER = IB * IB / NTHREADS;
+  double v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) v[u] = T[threadIdx.x + NTHREADS * u];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) Ts[threadIdx.x + NTHREADS * u] = v[u];
+}
+
+// ---------------------------------------------------------------------------
+// Block update.
 enum { V_UNM = 0, V_TS = 1, V_TT = 2 };
 
-// Apply one ib-block of reflectors (first column c0) to a wave's 16 columns.
-// Vs (leading dimension ldv) holds the block's reflectors explicitly, zeros
-// and unit diagonal included:
+// A wave of column group gw = wave % 4 and row half h = wave / 4 holds the
+// 16-row blocks rb = 2 j + h of its 16 columns: acc[j][i] is row
+// 16 rb + 4 i + g.  Load / store rows of blocks rb in [lo, hi).
+template <int NB>
+__device__ __forceinline__ void load_cols(d4 (&acc)[NB / 32], const double* C, int lo, int hi) {
+  const int lane = lane_id(), g = lane >> 4, h = wave_id() >> 2;
+#pragma unroll
+  for (int j = 0; j < NB / 32; ++j) {
+    const int rb = 2 * j + h;
+    if (rb < lo || rb >= hi) {
+      acc[j] = zero4();
+      continue;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[j][i] = C[rb * 16 + 4 * i + g];
+  }
+}
+template <int NB>
+__device__ __forceinline__ void store_cols(const d4 (&acc)[NB / 32], double* C, int lo, int hi) {
+  const int lane = lane_id(), g = lane >> 4, h = wave_id() >> 2;
+#pragma unroll
+  for (int j = 0; j < NB / 32; ++j) {
+    const int rb = 2 * j + h;
+    if (rb < lo || rb >= hi) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) C[rb * 16 + 4 * i + g] = acc[j][i];
+  }
+}
+
+// Apply one ib-block of reflectors (first column c0) to the column group's
+// 16 columns.  Vs (leading dimension ldv) holds the block's reflectors
+// explicitly (zeros and unit diagonal included):
 //   V_UNM  rows relative to the block's first row c0 (unit lower trapezoid);
 //   V_TS   all nb rows of V2;
 //   V_TT   rows 0..c0+ib-1 of V2, zero below each reflector's support.
-// acc[rb][i] holds row 16 rb + 4 i + g of C (V_UNM) or of C2 (pairs).
 // c1 points at the lane's column of C1 (pairs only); rows c0..c0+ib-1 of
-// C1 take part.  trans: 1 applies Q^T (T^T), 0 applies Q (T).
+// C1 take part.  wx is the group's W exchange area.  Every thread must call
+// this (it contains a barrier); active says whether the group has columns.
+// trans: 1 applies Q^T (T^T), 0 applies Q (T).
 template <int NB, int VAR>
-__device__ __forceinline__ void apply_block(const double* Vs, int ldv, const double* Ts, int c0,
-                                            d4 (&acc)[NB / 16], double* c1, int lane, int trans) {
-  const int g = lane >> 4, n = lane & 15;
+__device__ __forceinline__ void apply_block(const double* Vs, int ldv, const double* Ts, int c0, d4 (&acc)[NB / 32],
+                                            double* c1, bool active, int trans, double* wx) {
+  const int lane = lane_id(), g = lane >> 4, n = lane & 15;
+  const int h = wave_id() >> 2;
   const int rb_lo = (VAR == V_UNM) ? (c0 >> 4) : 0;
   const int rb_hi = (VAR == V_TT) ? ((c0 + IB) >> 4) : (NB >> 4);
   const int vbase = (VAR == V_UNM) ? c0 : 0;
-  d4 w[2];
+  // Partial W over this wave's row blocks: lane (n, g) supplies
+  // V[16 rb + 4 i + g][16 mb + n]; two accumulators per mb.
+  d4 w[2][2] = {{zero4(), zero4()}, {zero4(), zero4()}};
+  if (active) {
+    const double* va = Vs + (g - vbase) + n * ldv;
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb) {
-    if (VAR == V_UNM) {
-      w[mb] = zero4();
-    } else {
+    for (int j = 0; j < NB / 32; ++j) {
+      const int rb = 2 * j + h;
+      if (rb < rb_lo || rb >= rb_hi) continue;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) w[mb][i] = c1[c0 + mb * 16 + 4 * i + g];
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+          w[mb][i & 1] = mfma(va[rb * 16 + 4 * i + mb * 16 * ldv], acc[j][i], w[mb][i & 1]);
     }
   }
-  // W += V^T C: lane (n, g) supplies V[16 rb + 4 i + g][16 mb + n].
-  const double* va = Vs + (g - vbase) + n * ldv;
+  d4 ws[2] = {w[0][0] + w[0][1], w[1][0] + w[1][1]};
+  // Both waves of the group read their C1 rows before the barrier; the h = 0
+  // wave writes them back only after it, so no read sees the update.
+  d4 c1v[2] = {zero4(), zero4()};
+  if (VAR != V_UNM && active) {
 #pragma unroll
-  for (int rb = 0; rb < NB / 16; ++rb) {
-    if (rb < rb_lo || rb >= rb_hi) continue;
+    for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 4; ++i) c1v[mb][i] = c1[c0 + mb * 16 + 4 * i + g];
+  }
+  double* mine = wx + h * 8 * 64;
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb) w[mb] = mfma(va[rb * 16 + 4 * i + mb * 16 * ldv], acc[rb][i], w[mb]);
-    __builtin_amdgcn_sched_barrier(0);
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) mine[(mb * 4 + i) * 64 + lane] = ws[mb][i];
+  __syncthreads();
+  const double* other = wx + (1 - h) * 8 * 64;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ws[mb][i] += other[(mb * 4 + i) * 64 + lane];
+  if (!active) return;
+  if (VAR != V_UNM) {
+    ws[0] += c1v[0];
+    ws[1] += c1v[1];
   }
   // W' = T^T W (trans) or T W
   d4 wt[2] = {zero4(), zero4()};
@@ -97,84 +267,91 @@ __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const dou
       if (trans ? (jb > ab) : (jb < ab)) continue;  // T is upper triangular
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int j = jb * 16 + 4 * i + g, aa = ab * 16 + n;
-        const double t = trans ? Ts[j + aa * IB] : Ts[aa + j * IB];
-        wt[ab] = mfma(t, w[jb][i], wt[ab]);
+        const int jj = jb * 16 + 4 * i + g, aa = ab * 16 + n;
+        const double t = trans ? Ts[jj + aa * IB] : Ts[aa + jj * IB];
+        wt[ab] = mfma(t, ws[jb][i], wt[ab]);
       }
     }
   }
-  if (VAR != V_UNM) {
+  if (VAR != V_UNM && h == 0) {
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) c1[c0 + mb * 16 + 4 * i + g] -= wt[mb][i];
+      for (int i = 0; i < 4; ++i) c1[c0 + mb * 16 + 4 * i + g] = c1v[mb][i] - wt[mb][i];
   }
-  // C -= V W': lane (n, g) supplies V[16 rb + n][16 mb + 4 i + g].
+  wt[0] = -wt[0];
+  wt[1] = -wt[1];
+  // C -= V W': lane (n, g) supplies V[16 rb + n][16 mb + 4 i + g]; the row
+  // blocks are the inner loop so consecutive MFMAs are independent.
   const double* vb = Vs + (n - vbase) + g * ldv;
 #pragma unroll
-  for (int rb = 0; rb < NB / 16; ++rb) {
-    if (rb < rb_lo || rb >= rb_hi) continue;
+  for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) acc[rb] = mfma(-vb[rb * 16 + (mb * 16 + 4 * i) * ldv], wt[mb][i], acc[rb]);
-    __builtin_amdgcn_sched_barrier(0);
-  }
-}
-
-// Load / store a wave's nb x 16 column block (column col0 + n of a tile with
-// leading dimension NB) in D layout, rows 16 rb .. for rb in [lo, hi).
-template <int NB>
-__device__ __forceinline__ void load_cols(d4 (&acc)[NB / 16], const double* C, int lane, int lo, int hi) {
-  const int g = lane >> 4;
-#pragma unroll
-  for (int rb = 0; rb < NB / 16; ++rb) {
-    if (rb < lo || rb >= hi) {
-      acc[rb] = zero4();
-      continue;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) acc[rb][i] = C[rb * 16 + 4 * i + g];
-  }
-}
-template <int NB>
-__device__ __forceinline__ void store_cols(const d4 (&acc)[NB / 16], double* C, int lane, int lo, int hi) {
-  const int g = lane >> 4;
-#pragma unroll
-  for (int rb = 0; rb < NB / 16; ++rb) {
-    if (rb < lo || rb >= hi) continue;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) C[rb * 16 + 4 * i + g] = acc[rb][i];
-  }
+      for (int j = 0; j < NB / 32; ++j) {
+        const int rb = 2 * j + h;
+        if (rb < rb_lo || rb >= rb_hi) continue;
+        acc[j] = mfma(vb[rb * 16 + (mb * 16 + 4 * i) * ldv], wt[mb][i], acc[j]);
+      }
 }
 
 // ---------------------------------------------------------------------------
-// Panel factorization of ib columns held in LDS.
+// Panel factorization of ib columns (held in LDS on entry and exit, in
+// registers in between).
 //
-// Ps (ld ldp) holds the rows below the block's top: for GEQRT rows c0..nb-1
-// of the panel (diagonal element of column jj at row jj); for the pair
-// kernels the A2 rows 0..K-1, with the triangle block Rs (ib x ib) of R1 on
-// top.  Column jj is owned by wave jj % 4, which computes its reflector
-// (LAPACK convention: beta = -sign(alpha) ||(alpha, x)||, tau = (beta -
-// alpha) / beta, v = x / (alpha - beta)); each wave then updates the panel
-// columns it owns.
-//
-// PAIR = 0: GEQRT panel (alpha = Ps[jj][jj], x = Ps[jj+1.., jj]).
-// PAIR = 1: alpha = Rs[jj][jj], x = Ps[0..len(jj)-1, jj] with len(jj) = K for
-//           TS and c0 + jj + 1 for TT.
-template <int PAIR>
-__device__ __forceinline__ void panel_factor(double* Ps, int ldp, int K, double* Rs, double* tau, int tt, int c0) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+// Ps (ld ldp) holds: for GEQRT (PAIR = 0) rows c0..nb-1 of the panel (K rows,
+// diagonal of column jj at row jj); for the pair kernels (PAIR = 1) the A2
+// rows 0..K-1, with the triangle block Rs (ib x ib) of R1 on top.  Wave w
+// owns columns w, w + 8, ...; a lane holds rows lane + 64 u.  Column jj's
+// reflector is computed by its owner (LAPACK convention: beta = -sign(alpha)
+// ||(alpha, x)||, tau = (beta - alpha) / beta, v = x / (alpha - beta)) and
+// broadcast through LDS; each wave then updates the columns it owns.  TT
+// (PAIR = 1, tt) limits column jj's reflector to rows 0..c0+jj.
+template <int NB, int PAIR>
+__device__ __forceinline__ void panel_factor(double* Ps, int ldp, int K, double* Rs, double* tau, double* vbuf,
+                                             int tt, int c0) {
+  constexpr int RCH = (NB + 63) / 64;
+  const int lane = lane_id(), wave = wave_id();
+  double pc[4][RCH];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int u = 0; u < RCH; ++u) {
+      const int r = lane + 64 * u;
+      pc[q][u] = r < K ? Ps[r + (wave + NWAVES * q) * ldp] : 0.0;
+    }
   for (int jj = 0; jj < IB; ++jj) {
     const int r0 = PAIR ? 0 : jj + 1;
     const int r1 = PAIR ? (tt ? c0 + jj + 1 : K) : K;
-    double* colj = Ps + jj * ldp;
-    if (wave == (jj & 3)) {
+    double* vb = vbuf + (jj & 1) * NB;
+    if (wave == (jj & 7)) {
+      const int q = jj >> 3;
+      double x[RCH];
+#pragma unroll
+      for (int u = 0; u < RCH; ++u) {
+        x[u] = pc[0][u];
+#pragma unroll
+        for (int qq = 1; qq < 4; ++qq)
+          if (q == qq) x[u] = pc[qq][u];
+      }
       double s = 0.0;
-      for (int r = r0 + lane; r < r1; r += 64) s += colj[r] * colj[r];
+#pragma unroll
+      for (int u = 0; u < RCH; ++u) {
+        const int r = lane + 64 * u;
+        if (r >= r0 && r < r1) s += x[u] * x[u];
+      }
       s = wave_sum(s);
-      double* ap = PAIR ? (Rs + jj + jj * IB) : (colj + jj);
-      const double alpha = *ap;
+      double alpha;
+      if (PAIR) {
+        alpha = Rs[jj + jj * IB];
+      } else {
+        double av = x[0];
+#pragma unroll
+        for (int u = 1; u < RCH; ++u)
+          if ((jj >> 6) == u) av = x[u];
+        alpha = lane_d(av, jj & 63);
+      }
       double beta = alpha, t = 0.0, scale = 0.0;
       if (s != 0.0) {
         const double nrm = sqrt(alpha * alpha + s);
@@ -182,111 +359,144 @@ __device__ __forceinline__ void panel_factor(double* Ps, int ldp, int K, double*
         t = (beta - alpha) / beta;
         scale = 1.0 / (alpha - beta);
       }
-      for (int r = r0 + lane; r < r1; r += 64) colj[r] *= scale;
+#pragma unroll
+      for (int u = 0; u < RCH; ++u) {
+        const int r = lane + 64 * u;
+        const bool in = r >= r0 && r < r1;
+        if (in) x[u] *= scale;
+        if (!PAIR && r == jj) x[u] = beta;
+        if (r < NB) vb[r] = in ? x[u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < RCH; ++u)
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq)
+          if (q == qq) pc[qq][u] = x[u];
       if (lane == 0) {
-        *ap = beta;
         tau[jj] = t;
+        if (PAIR) Rs[jj + jj * IB] = beta;
       }
     }
     __syncthreads();
-    const double t = tau[jj];
+    const double t = uniform_d(tau[jj]);
     if (t != 0.0) {
-      for (int c = jj + 1; c < IB; ++c) {
-        if ((c & 3) != wave) continue;
-        double* colc = Ps + c * ldp;
+      double v[RCH];
+#pragma unroll
+      for (int u = 0; u < RCH; ++u) {
+        const int r = lane + 64 * u;
+        v[u] = r < NB ? vb[r] : 0.0;
+      }
+#pragma unroll
+      for (int q2 = 0; q2 < 4; ++q2) {
+        const int c = wave + NWAVES * q2;
+        if (c <= jj) continue;
         double d = 0.0;
-        for (int r = r0 + lane; r < r1; r += 64) d += colj[r] * colc[r];
-        double* top = PAIR ? (Rs + jj + c * IB) : (colc + jj);
-        d = (wave_sum(d) + *top) * t;
-        for (int r = r0 + lane; r < r1; r += 64) colc[r] -= colj[r] * d;
-        if (lane == 0) *top -= d;
+#pragma unroll
+        for (int u = 0; u < RCH; ++u) d += v[u] * pc[q2][u];
+        d = wave_sum(d);
+        if (PAIR) {
+          d += Rs[jj + c * IB];
+        } else {
+          double top = pc[q2][0];
+#pragma unroll
+          for (int u = 1; u < RCH; ++u)
+            if ((jj >> 6) == u) top = pc[q2][u];
+          d += lane_d(top, jj & 63);
+        }
+        d *= t;
+#pragma unroll
+        for (int u = 0; u < RCH; ++u) {
+          pc[q2][u] -= v[u] * d;
+          if (!PAIR && lane + 64 * u == jj) pc[q2][u] -= d;
+        }
+        if (PAIR && lane == 0) Rs[jj + c * IB] -= d;
       }
     }
   }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int u = 0; u < RCH; ++u) {
+      const int r = lane + 64 * u;
+      if (r < K) Ps[r + (wave + NWAVES * q) * ldp] = pc[q][u];
+    }
   __syncthreads();
 }
 
 // T factor of the block (forward, columnwise, as LAPACK dlarft):
-// T[j][j] = tau_j, T[0:j, j] = -tau_j T[0:j, 0:j] (V^T v_j)[0:j].
-// G[a][j] = v_a^T v_j for a < j is computed first.
-//   PAIR = 0: v_a = e_a + Ps[a+1.., a] (unit lower), rows relative to c0.
-//   PAIR = 1: v_a = e_a (in R1) + Ps[0..K-1, a]; for TT the stored zeros
-//             below the support make the full-length dot correct.
-template <int PAIR>
+// T[j][j] = tau_j and T[0:j, j] = -tau_j T[0:j, 0:j] (V^T v_j)[0:j].
+// Ps holds the block's reflectors explicitly (K rows); the Gram matrix
+// G = V^T V comes from FP64 MFMAs on waves 0..2 (upper 16 x 16 blocks), the
+// recurrence runs on wave 0 with one row of T per lane in registers.
+template <int NB>
 __device__ __forceinline__ void build_t(const double* Ps, int ldp, int K, const double* tau, double* Gs, double* Ts) {
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int pr = wave; pr < IB * IB; pr += 4) {
-    const int a = pr / IB, j = pr % IB;
-    if (a >= j) continue;
-    const double* va = Ps + a * ldp;
-    const double* vj = Ps + j * ldp;
-    double d = 0.0;
-    const int r0 = PAIR ? 0 : j + 1;
-    for (int r = r0 + lane; r < K; r += 64) d += va[r] * vj[r];
-    d = wave_sum(d);
-    if (lane == 0) Gs[a + j * IB] = d + (PAIR ? 0.0 : va[j]);
+  const int lane = lane_id(), wave = wave_id(), g = lane >> 4, n = lane & 15;
+  if (wave < 3) {
+    const int ab = (wave == 2) ? 1 : 0, jb = (wave == 0) ? 0 : 1;
+    d4 a0 = zero4(), a1 = zero4();
+    const double* pa = Ps + g + (ab * 16 + n) * ldp;
+    const double* pb = Ps + g + (jb * 16 + n) * ldp;
+    for (int k0 = 0; k0 < K; k0 += 8) {
+      a0 = mfma(pa[k0], pb[k0], a0);
+      a1 = mfma(pa[k0 + 4], pb[k0 + 4], a1);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Gs[(ab * 16 + 4 * i + g) + (jb * 16 + n) * IB] = a0[i] + a1[i];
   }
   __syncthreads();
   if (wave == 0 && lane < IB) {
     const int a = lane;
+    double trow[IB];
+#pragma unroll
     for (int j = 0; j < IB; ++j) {
-      double v;
-      if (a < j) {
-        double s = 0.0;
-        for (int b = a; b < j; ++b) s += Ts[a + b * IB] * Gs[b + j * IB];
-        v = -tau[j] * s;
-      } else {
-        v = (a == j) ? tau[j] : 0.0;
-      }
-      Ts[a + j * IB] = v;
+      double s = 0.0;
+#pragma unroll
+      for (int b = 0; b < j; ++b) s += trow[b] * Gs[b + j * IB];
+      const double tj = tau[j];
+      trow[j] = (a < j) ? -tj * s : (a == j ? tj : 0.0);
     }
+#pragma unroll
+    for (int j = 0; j < IB; ++j) Ts[a + j * IB] = trow[j];
   }
   __syncthreads();
 }
-
-template <int NB>
-struct Smem {
-  static constexpr int LDP = NB + 1;
-  static constexpr int PS = LDP * IB;
-  static constexpr int TOTAL = PS + 3 * IB * IB + IB;
-};
 
 // ---- GEQRT ---------------------------------------------------------------
 template <int NB>
 __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm) {
   constexpr int ldp = Smem<NB>::LDP;
-  double* Ps = sm;
-  double* Ts = Ps + Smem<NB>::PS;
-  double* Gs = Ts + IB * IB;
-  double* Rs = Gs + IB * IB;  // unused here
-  double* tau = Rs + IB * IB;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* Ps = sm + Smem<NB>::PS;
+  double* Ts = sm + Smem<NB>::TS;
+  double* Gs = sm + Smem<NB>::GS;
+  double* tau = sm + Smem<NB>::TAU;
+  double* vbuf = sm + Smem<NB>::VBUF;
+  const int tid = threadIdx.x, lane = lane_id(), gw = wave_id() & 3;
+  double* wx = sm + Smem<NB>::WX + gw * 16 * 64;
   for (int c0 = 0; c0 < NB; c0 += IB) {
     const int K = NB - c0;
-    for (int idx = tid; idx < K * IB; idx += NTHREADS) {
-      const int m = idx / K, kk = idx - m * K;
-      Ps[kk + m * ldp] = A[(c0 + m) * NB + c0 + kk];
-    }
+    stage_block<NB, ST_FULL>(Ps, ldp, A + c0 * NB + c0, K, c0);
     __syncthreads();
-    panel_factor<0>(Ps, ldp, K, nullptr, tau, 0, c0);
-    for (int idx = tid; idx < K * IB; idx += NTHREADS) {
-      const int m = idx / K, kk = idx - m * K;
-      A[(c0 + m) * NB + c0 + kk] = Ps[kk + m * ldp];
-    }
-    build_t<0>(Ps, ldp, K, tau, Gs, Ts);
+    panel_factor<NB, 0>(Ps, ldp, K, nullptr, tau, vbuf, 0, c0);
+    unstage_block<NB, false>(Ps, ldp, A + c0 * NB + c0, K, c0);
+    __syncthreads();
+    // R has been stored: make the reflectors explicit (unit diagonal).
     for (int e = tid; e < IB * IB; e += NTHREADS) {
-      T[(c0 / IB) * IB * IB + e] = Ts[e];
-      const int a = e % IB, c = e / IB;  // R has been stored: make V explicit
+      const int a = e % IB, c = e / IB;
       if (a <= c) Ps[a + c * ldp] = (a == c) ? 1.0 : 0.0;
     }
     __syncthreads();
+    build_t<NB>(Ps, ldp, K, tau, Gs, Ts);
+    for (int e = tid; e < IB * IB; e += NTHREADS) T[(c0 / IB) * IB * IB + e] = Ts[e];
     const int nch = (NB - c0 - IB) / 16;
-    for (int ch = wave; ch < nch; ch += 4) {
+    for (int base = 0; base < nch; base += 4) {
+      const int ch = base + gw;
+      const bool active = ch < nch;
       double* C = A + (c0 + IB + ch * 16 + (lane & 15)) * NB;
-      d4 acc[NB / 16];
-      load_cols<NB>(acc, C, lane, c0 / 16, NB / 16);
-      apply_block<NB, V_UNM>(Ps, ldp, Ts, c0, acc, nullptr, lane, 1);
-      store_cols<NB>(acc, C, lane, c0 / 16, NB / 16);
+      d4 acc[NB / 32];
+      if (active) load_cols<NB>(acc, C, c0 / 16, NB / 16);
+      apply_block<NB, V_UNM>(Ps, ldp, Ts, c0, acc, nullptr, active, 1, wx);
+      if (active) store_cols<NB>(acc, C, c0 / 16, NB / 16);
+      __syncthreads();
     }
     __syncthreads();
   }
@@ -297,111 +507,114 @@ __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm) {
 template <int NB>
 __device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T, double* sm, int tt) {
   constexpr int ldp = Smem<NB>::LDP;
-  double* Ps = sm;
-  double* Ts = Ps + Smem<NB>::PS;
-  double* Gs = Ts + IB * IB;
-  double* Rs = Gs + IB * IB;
-  double* tau = Rs + IB * IB;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* Ps = sm + Smem<NB>::PS;
+  double* Ts = sm + Smem<NB>::TS;
+  double* Gs = sm + Smem<NB>::GS;
+  double* Rs = sm + Smem<NB>::RS;
+  double* tau = sm + Smem<NB>::TAU;
+  double* vbuf = sm + Smem<NB>::VBUF;
+  const int tid = threadIdx.x, lane = lane_id(), gw = wave_id() & 3;
+  double* wx = sm + Smem<NB>::WX + gw * 16 * 64;
   for (int c0 = 0; c0 < NB; c0 += IB) {
     const int K = tt ? c0 + IB : NB;
     for (int e = tid; e < IB * IB; e += NTHREADS) {
       const int a = e % IB, c = e / IB;
       Rs[e] = (a <= c) ? R1[(c0 + c) * NB + c0 + a] : 0.0;
     }
-    for (int idx = tid; idx < K * IB; idx += NTHREADS) {
-      const int m = idx / K, kk = idx - m * K;
-      Ps[kk + m * ldp] = (!tt || kk <= c0 + m) ? A2[(c0 + m) * NB + kk] : 0.0;
-    }
+    if (tt)
+      stage_block<NB, ST_UPPER>(Ps, ldp, A2 + c0 * NB, K, c0);
+    else
+      stage_block<NB, ST_FULL>(Ps, ldp, A2 + c0 * NB, K, c0);
     __syncthreads();
-    panel_factor<1>(Ps, ldp, K, Rs, tau, tt, c0);
+    panel_factor<NB, 1>(Ps, ldp, K, Rs, tau, vbuf, tt, c0);
     for (int e = tid; e < IB * IB; e += NTHREADS) {
       const int a = e % IB, c = e / IB;
       if (a <= c) R1[(c0 + c) * NB + c0 + a] = Rs[e];
     }
-    for (int idx = tid; idx < K * IB; idx += NTHREADS) {
-      const int m = idx / K, kk = idx - m * K;
-      if (!tt || kk <= c0 + m) A2[(c0 + m) * NB + kk] = Ps[kk + m * ldp];
-    }
-    build_t<1>(Ps, ldp, K, tau, Gs, Ts);
+    if (tt)
+      unstage_block<NB, true>(Ps, ldp, A2 + c0 * NB, K, c0);
+    else
+      unstage_block<NB, false>(Ps, ldp, A2 + c0 * NB, K, c0);
+    build_t<NB>(Ps, ldp, K, tau, Gs, Ts);
     for (int e = tid; e < IB * IB; e += NTHREADS) T[(c0 / IB) * IB * IB + e] = Ts[e];
     const int nch = (NB - c0 - IB) / 16;
     const int hi = tt ? (c0 + IB) / 16 : NB / 16;
-    for (int ch = wave; ch < nch; ch += 4) {
+    for (int base = 0; base < nch; base += 4) {
+      const int ch = base + gw;
+      const bool active = ch < nch;
       const int col = c0 + IB + ch * 16 + (lane & 15);
       double* C2 = A2 + col * NB;
-      d4 acc[NB / 16];
-      load_cols<NB>(acc, C2, lane, 0, hi);
+      d4 acc[NB / 32];
+      if (active) load_cols<NB>(acc, C2, 0, hi);
       if (tt)
-        apply_block<NB, V_TT>(Ps, ldp, Ts, c0, acc, R1 + col * NB, lane, 1);
+        apply_block<NB, V_TT>(Ps, ldp, Ts, c0, acc, R1 + col * NB, active, 1, wx);
       else
-        apply_block<NB, V_TS>(Ps, ldp, Ts, c0, acc, R1 + col * NB, lane, 1);
-      store_cols<NB>(acc, C2, lane, 0, hi);
+        apply_block<NB, V_TS>(Ps, ldp, Ts, c0, acc, R1 + col * NB, active, 1, wx);
+      if (active) store_cols<NB>(acc, C2, 0, hi);
+      __syncthreads();
     }
     __syncthreads();
   }
 }
 
-// ---- UNMQR (and apply of a GEQRT set to B) --------------------------------
-// V: the factored tile; T: its T factors; C: target with leading dim NB and
-// ncol columns; the subtask covers columns col0..col0+63.
+// ---- UNMQR (and application of a GEQRT set to B) ---------------------------
+// V: the factored tile; T: its T factors; C: target with leading dimension
+// NB and ncol columns; the subtask covers columns col0..col0+63.
 template <int NB>
-__device__ __forceinline__ void unmqr_task(const double* V, const double* T, double* C, int col0, int ncol, double* sm, int trans) {
+__device__ __forceinline__ void unmqr_task(const double* V, const double* T, double* C, int col0, int ncol, double* sm,
+                                           int trans) {
   constexpr int ldv = Smem<NB>::LDP;
-  double* Vs = sm;
-  double* Ts = Vs + Smem<NB>::PS;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int mycol = col0 + wave * 16;
+  double* Vs = sm + Smem<NB>::PS;
+  double* Ts = sm + Smem<NB>::TS;
+  const int lane = lane_id(), gw = wave_id() & 3;
+  double* wx = sm + Smem<NB>::WX + gw * 16 * 64;
+  const int mycol = col0 + gw * 16;
   const bool active = mycol < ncol;
   double* Cw = C + static_cast<size_t>(mycol + (lane & 15)) * NB;
-  d4 acc[NB / 16];
-  if (active) load_cols<NB>(acc, Cw, lane, 0, NB / 16);
+  d4 acc[NB / 32];
+  if (active) load_cols<NB>(acc, Cw, 0, NB / 16);
   for (int step = 0; step < NB / IB; ++step) {
     const int c0 = trans ? step * IB : NB - IB - step * IB;
     const int K = NB - c0;
-    for (int idx = tid; idx < K * IB; idx += NTHREADS) {
-      const int m = idx / K, kk = idx - m * K;
-      Vs[kk + m * ldv] = kk > m ? V[(c0 + m) * NB + c0 + kk] : (kk == m ? 1.0 : 0.0);
-    }
-    for (int e = tid; e < IB * IB; e += NTHREADS) Ts[e] = T[(c0 / IB) * IB * IB + e];
+    stage_block<NB, ST_UNIT_LOWER>(Vs, ldv, V + c0 * NB + c0, K, c0);
+    stage_t(Ts, T + (c0 / IB) * IB * IB);
     __syncthreads();
-    if (active) apply_block<NB, V_UNM>(Vs, ldv, Ts, c0, acc, nullptr, lane, trans);
+    apply_block<NB, V_UNM>(Vs, ldv, Ts, c0, acc, nullptr, active, trans, wx);
     __syncthreads();
   }
-  if (active) store_cols<NB>(acc, Cw, lane, 0, NB / 16);
+  if (active) store_cols<NB>(acc, Cw, 0, NB / 16);
 }
 
-// ---- TSMQR / TTMQR (and apply of a pair set to B) --------------------------
+// ---- TSMQR / TTMQR (and application of a pair set to B) --------------------
 template <int NB>
-__device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T, double* C1, double* C2, int col0, int ncol,
-                              double* sm, int tt, int trans) {
+__device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T, double* C1, double* C2, int col0,
+                                              int ncol, double* sm, int tt, int trans) {
   constexpr int ldv = Smem<NB>::LDP;
-  double* Vs = sm;
-  double* Ts = Vs + Smem<NB>::PS;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int mycol = col0 + wave * 16;
+  double* Vs = sm + Smem<NB>::PS;
+  double* Ts = sm + Smem<NB>::TS;
+  const int lane = lane_id(), gw = wave_id() & 3;
+  double* wx = sm + Smem<NB>::WX + gw * 16 * 64;
+  const int mycol = col0 + gw * 16;
   const bool active = mycol < ncol;
   const size_t off = static_cast<size_t>(mycol + (lane & 15)) * NB;
-  d4 acc[NB / 16];
-  if (active) load_cols<NB>(acc, C2 + off, lane, 0, NB / 16);
+  d4 acc[NB / 32];
+  if (active) load_cols<NB>(acc, C2 + off, 0, NB / 16);
   for (int step = 0; step < NB / IB; ++step) {
     const int c0 = trans ? step * IB : NB - IB - step * IB;
     const int K = tt ? c0 + IB : NB;
-    for (int idx = tid; idx < K * IB; idx += NTHREADS) {
-      const int m = idx / K, kk = idx - m * K;
-      Vs[kk + m * ldv] = (!tt || kk <= c0 + m) ? V2[(c0 + m) * NB + kk] : 0.0;
-    }
-    for (int e = tid; e < IB * IB; e += NTHREADS) Ts[e] = T[(c0 / IB) * IB * IB + e];
+    if (tt)
+      stage_block<NB, ST_UPPER>(Vs, ldv, V2 + c0 * NB, K, c0);
+    else
+      stage_block<NB, ST_FULL>(Vs, ldv, V2 + c0 * NB, K, c0);
+    stage_t(Ts, T + (c0 / IB) * IB * IB);
     __syncthreads();
-    if (active) {
-      if (tt)
-        apply_block<NB, V_TT>(Vs, ldv, Ts, c0, acc, C1 + off, lane, trans);
-      else
-        apply_block<NB, V_TS>(Vs, ldv, Ts, c0, acc, C1 + off, lane, trans);
-    }
+    if (tt)
+      apply_block<NB, V_TT>(Vs, ldv, Ts, c0, acc, C1 + off, active, trans, wx);
+    else
+      apply_block<NB, V_TS>(Vs, ldv, Ts, c0, acc, C1 + off, active, trans, wx);
     __syncthreads();
   }
-  if (active) store_cols<NB>(acc, C2 + off, lane, 0, NB / 16);
+  if (active) store_cols<NB>(acc, C2 + off, 0, NB / 16);
 }
 
 template <int NB>
@@ -456,8 +669,8 @@ __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
   // (scalar) value, so the compiler keeps the loop structured: wave 0 takes
   // the ticket and waits for the predecessors as a whole wave; only the
   // single atomic operations are guarded by lane == 0.
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = lane_id();
+  const int wave = wave_id();
   for (;;) {
     if (wave == 0) {
       int t = a.nsub;
@@ -471,6 +684,7 @@ __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
       if (t < a.nsub) {
         const int db = a.sub[t].dep_begin, de = a.sub[t].dep_end;
         const uint64_t t0 = wall_clock64();
+        if (a.trace && lane == 0) a.trace[4 * static_cast<int64_t>(t)] = static_cast<int64_t>(t0);
         for (int e = db; e < de && t < a.nsub; ++e) {
           int32_t* f = a.flags + a.deps[e];
           for (;;) {
@@ -495,11 +709,22 @@ __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
     // visible to the compiler (scalar loop exit and task dispatch).
     const int t = __builtin_amdgcn_readfirstlane(s_t);
     if (t >= a.nsub) break;
+    if (a.trace && threadIdx.x == 0) a.trace[4 * static_cast<int64_t>(t) + 1] = static_cast<int64_t>(wall_clock64());
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (a.debug & 1) {
+      for (int e = threadIdx.x; e < Smem<NB>::TOTAL; e += NTHREADS) sm[e] = 0.0;
+      __syncthreads();
+    }
     run_sub<NB>(a, a.sub[t], sm);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     __syncthreads();
-    if (wave == 0 && lane == 0) __hip_atomic_store(a.flags + t, a.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (wave == 0 && lane == 0) {
+      __hip_atomic_store(a.flags + t, a.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      if (a.trace) {
+        a.trace[4 * static_cast<int64_t>(t) + 2] = static_cast<int64_t>(wall_clock64());
+        a.trace[4 * static_cast<int64_t>(t) + 3] = blockIdx.x;
+      }
+    }
   }
 }
 
@@ -555,107 +780,6 @@ int persistent_occupancy(int nb) {
     default: break;
   }
   return (e == hipSuccess && blocks > 0) ? blocks : 1;
-}
-
-// ---- layout conversions ------------------------------------------------------
-
-// Column-major A (lda) -> tiles.  One thread per element of the tile matrix.
-__global__ void pack_kernel(const double* A, int64_t lda, double* tiles, int p, int q, int nb) {
-  const int64_t m = static_cast<int64_t>(p) * nb;
-  const int64_t total = m * q * nb;
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t col = e / m, row = e - col * m;
-    const int64_t r = row / nb, c = col / nb;
-    tiles[(c * p + r) * nb * nb + (col - c * nb) * nb + (row - r * nb)] = A[col * lda + row];
-  }
-}
-
-// tiles -> column-major out (ld) for rows x cols (upper_only: zero below the
-// diagonal, used for R).
-__global__ void unpack_kernel(const double* tiles, double* out, int64_t ld, int p, int nb, int64_t rows, int64_t cols,
-                              int upper_only) {
-  const int64_t total = rows * cols;
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t col = e / rows, row = e - col * rows;
-    const int64_t r = row / nb, c = col / nb;
-    double v = tiles[(c * p + r) * nb * nb + (col - c * nb) * nb + (row - r * nb)];
-    if (upper_only && row > col) v = 0.0;
-    out[col * ld + row] = v;
-  }
-}
-
-__global__ void tau_kernel(const double* Tg, const double* Tp, double* tau, int p, int q, int nb) {
-  const int64_t per = static_cast<int64_t>(p) * q * nb;
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < 2 * per;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int which = e >= per;
-    const int64_t x = e - which * per;
-    const int64_t t = x / nb, j = x - t * nb;
-    const double* T = (which ? Tp : Tg) + t * static_cast<int64_t>(IB) * nb;
-    const int64_t b = j / IB, jj = j - b * IB;
-    tau[e] = T[b * IB * IB + jj + jj * IB];
-  }
-}
-
-// B (ldb, m x nrhs) -> p row tiles of nb x ncolB (ld nb), zero padded.
-__global__ void pack_b_kernel(const double* B, int64_t ldb, int64_t nrhs, double* Bt, int p, int nb, int ncolB) {
-  const int64_t total = static_cast<int64_t>(p) * nb * ncolB;
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t r = e / (static_cast<int64_t>(nb) * ncolB);
-    const int64_t x = e - r * nb * ncolB;
-    const int64_t col = x / nb, row = x - col * nb;
-    Bt[e] = col < nrhs ? B[col * ldb + r * nb + row] : 0.0;
-  }
-}
-
-__global__ void unpack_b_kernel(const double* Bt, double* B, int64_t ldb, int64_t nrhs, int64_t rows, int nb,
-                                int ncolB) {
-  const int64_t total = rows * nrhs;
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t col = e / rows, row = e - col * rows;
-    const int64_t r = row / nb;
-    B[col * ldb + row] = Bt[r * nb * ncolB + col * nb + (row - r * nb)];
-  }
-}
-
-static int grid_for(int64_t total) {
-  int64_t g = (total + 255) / 256;
-  if (g > 8192) g = 8192;
-  if (g < 1) g = 1;
-  return static_cast<int>(g);
-}
-
-hipError_t launch_pack(const double* A, int64_t lda, double* tiles, int p, int q, int nb, hipStream_t s) {
-  const int64_t total = static_cast<int64_t>(p) * nb * q * nb;
-  hipLaunchKernelGGL(pack_kernel, dim3(grid_for(total)), dim3(256), 0, s, A, lda, tiles, p, q, nb);
-  return hipGetLastError();
-}
-hipError_t launch_unpack(const double* tiles, double* out, int64_t ld, int p, int q, int nb, int rows, int cols,
-                         int upper_only, hipStream_t s) {
-  (void)q;
-  hipLaunchKernelGGL(unpack_kernel, dim3(grid_for(static_cast<int64_t>(rows) * cols)), dim3(256), 0, s, tiles, out,
-                     ld, p, nb, static_cast<int64_t>(rows), static_cast<int64_t>(cols), upper_only);
-  return hipGetLastError();
-}
-hipError_t launch_tau(const double* Tg, const double* Tp, double* tau, int p, int q, int nb, hipStream_t s) {
-  hipLaunchKernelGGL(tau_kernel, dim3(grid_for(2LL * p * q * nb)), dim3(256), 0, s, Tg, Tp, tau, p, q, nb);
-  return hipGetLastError();
-}
-hipError_t launch_pack_b(const double* B, int64_t ldb, int64_t nrhs, double* Bt, int p, int nb, int ncolB,
-                         hipStream_t s) {
-  hipLaunchKernelGGL(pack_b_kernel, dim3(grid_for(static_cast<int64_t>(p) * nb * ncolB)), dim3(256), 0, s, B, ldb,
-                     nrhs, Bt, p, nb, ncolB);
-  return hipGetLastError();
-}
-hipError_t launch_unpack_b(const double* Bt, double* B, int64_t ldb, int64_t nrhs, int rows, int nb, int ncolB,
-                           hipStream_t s) {
-  hipLaunchKernelGGL(unpack_b_kernel, dim3(grid_for(static_cast<int64_t>(rows) * nrhs)), dim3(256), 0, s, Bt, B, ldb,
-                     nrhs, static_cast<int64_t>(rows), nb, ncolB);
-  return hipGetLastError();
 }
 
 }  // namespace tqr
