@@ -165,6 +165,52 @@ __device__ __forceinline__ void stage_t(double* Ts, const double* T) {
   for (int u = 0; u < PER; ++u) Ts[threadIdx.x + NTHREADS * u] = v[u];
 }
 
+// Register copy of a reflector block and its T block, loaded one block ahead
+// so that the global-memory latency overlaps the current block's MFMAs.
+template <int NB>
+struct Prefetch {
+  static constexpr int RCH = (NB + 63) / 64;
+  static constexpr int TPER = IB * IB / NTHREADS;
+  double v[4][RCH];
+  double t[TPER];
+};
+
+template <int NB, int MODE>
+__device__ __forceinline__ void prefetch_load(Prefetch<NB>& pf, const double* src, int K, int c0, const double* T) {
+  const int lane = lane_id(), wave = wave_id();
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int m = wave + NWAVES * c;
+#pragma unroll
+    for (int u = 0; u < Prefetch<NB>::RCH; ++u) {
+      const int kk = lane + 64 * u;
+      bool use = kk < K;
+      if (MODE == ST_UNIT_LOWER) use = use && kk > m;
+      if (MODE == ST_UPPER) use = use && kk <= c0 + m;
+      const double fill = (MODE == ST_UNIT_LOWER && kk == m) ? 1.0 : 0.0;
+      pf.v[c][u] = use ? src[m * NB + kk] : fill;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < Prefetch<NB>::TPER; ++u) pf.t[u] = T[threadIdx.x + NTHREADS * u];
+}
+
+template <int NB>
+__device__ __forceinline__ void prefetch_store(const Prefetch<NB>& pf, double* Vs, int ldv, int K, double* Ts) {
+  const int lane = lane_id(), wave = wave_id();
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int m = wave + NWAVES * c;
+#pragma unroll
+    for (int u = 0; u < Prefetch<NB>::RCH; ++u) {
+      const int kk = lane + 64 * u;
+      if (kk < K) Vs[kk + m * ldv] = pf.v[c][u];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < Prefetch<NB>::TPER; ++u) Ts[threadIdx.x + NTHREADS * u] = pf.t[u];
+}
+
 // ---------------------------------------------------------------------------
 // Block update.
 enum { V_UNM = 0, V_TS = 1, V_TT = 2 };
@@ -230,6 +276,9 @@ __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const dou
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
           w[mb][i & 1] = mfma(va[rb * 16 + 4 * i + mb * 16 * ldv], acc[j][i], w[mb][i & 1]);
+      // Keep the operand loads of one row block together (bounds the
+      // registers the scheduler spends on hoisted LDS reads).
+      __builtin_amdgcn_sched_barrier(0);
     }
   }
   d4 ws[2] = {w[0][0] + w[0][1], w[1][0] + w[1][1]};
@@ -285,15 +334,16 @@ __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const dou
   // blocks are the inner loop so consecutive MFMAs are independent.
   const double* vb = Vs + (n - vbase) + g * ldv;
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+  for (int j = 0; j < NB / 32; ++j) {
+    const int rb = 2 * j + h;
+    if (rb < rb_lo || rb >= rb_hi) continue;
+    d4 c = acc[j];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int j = 0; j < NB / 32; ++j) {
-        const int rb = 2 * j + h;
-        if (rb < rb_lo || rb >= rb_hi) continue;
-        acc[j] = mfma(vb[rb * 16 + (mb * 16 + 4 * i) * ldv], wt[mb][i], acc[j]);
-      }
+      for (int i = 0; i < 4; ++i) c = mfma(vb[rb * 16 + (mb * 16 + 4 * i) * ldv], wt[mb][i], c);
+    acc[j] = c;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -321,6 +371,7 @@ __device__ __forceinline__ void panel_factor(double* Ps, int ldp, int K, double*
       const int r = lane + 64 * u;
       pc[q][u] = r < K ? Ps[r + (wave + NWAVES * q) * ldp] : 0.0;
     }
+#pragma unroll 1
   for (int jj = 0; jj < IB; ++jj) {
     const int r0 = PAIR ? 0 : jj + 1;
     const int r1 = PAIR ? (tt ? c0 + jj + 1 : K) : K;
@@ -472,6 +523,7 @@ __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm) {
   double* vbuf = sm + Smem<NB>::VBUF;
   const int tid = threadIdx.x, lane = lane_id(), gw = wave_id() & 3;
   double* wx = sm + Smem<NB>::WX + gw * 16 * 64;
+#pragma unroll 1
   for (int c0 = 0; c0 < NB; c0 += IB) {
     const int K = NB - c0;
     stage_block<NB, ST_FULL>(Ps, ldp, A + c0 * NB + c0, K, c0);
@@ -488,6 +540,7 @@ __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm) {
     build_t<NB>(Ps, ldp, K, tau, Gs, Ts);
     for (int e = tid; e < IB * IB; e += NTHREADS) T[(c0 / IB) * IB * IB + e] = Ts[e];
     const int nch = (NB - c0 - IB) / 16;
+#pragma unroll 1
     for (int base = 0; base < nch; base += 4) {
       const int ch = base + gw;
       const bool active = ch < nch;
@@ -515,6 +568,7 @@ __device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T,
   double* vbuf = sm + Smem<NB>::VBUF;
   const int tid = threadIdx.x, lane = lane_id(), gw = wave_id() & 3;
   double* wx = sm + Smem<NB>::WX + gw * 16 * 64;
+#pragma unroll 1
   for (int c0 = 0; c0 < NB; c0 += IB) {
     const int K = tt ? c0 + IB : NB;
     for (int e = tid; e < IB * IB; e += NTHREADS) {
@@ -539,6 +593,7 @@ __device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T,
     for (int e = tid; e < IB * IB; e += NTHREADS) T[(c0 / IB) * IB * IB + e] = Ts[e];
     const int nch = (NB - c0 - IB) / 16;
     const int hi = tt ? (c0 + IB) / 16 : NB / 16;
+#pragma unroll 1
     for (int base = 0; base < nch; base += 4) {
       const int ch = base + gw;
       const bool active = ch < nch;
@@ -571,14 +626,23 @@ __device__ __forceinline__ void unmqr_task(const double* V, const double* T, dou
   const int mycol = col0 + gw * 16;
   const bool active = mycol < ncol;
   double* Cw = C + static_cast<size_t>(mycol + (lane & 15)) * NB;
+  Prefetch<NB> pf;
+  {
+    const int c0 = trans ? 0 : NB - IB;
+    prefetch_load<NB, ST_UNIT_LOWER>(pf, V + c0 * NB + c0, NB - c0, c0, T + (c0 / IB) * IB * IB);
+  }
   d4 acc[NB / 32];
   if (active) load_cols<NB>(acc, Cw, 0, NB / 16);
+#pragma unroll 1
   for (int step = 0; step < NB / IB; ++step) {
     const int c0 = trans ? step * IB : NB - IB - step * IB;
     const int K = NB - c0;
-    stage_block<NB, ST_UNIT_LOWER>(Vs, ldv, V + c0 * NB + c0, K, c0);
-    stage_t(Ts, T + (c0 / IB) * IB * IB);
+    prefetch_store<NB>(pf, Vs, ldv, K, Ts);
     __syncthreads();
+    if (step + 1 < NB / IB) {
+      const int n0 = trans ? c0 + IB : c0 - IB;
+      prefetch_load<NB, ST_UNIT_LOWER>(pf, V + n0 * NB + n0, NB - n0, n0, T + (n0 / IB) * IB * IB);
+    }
     apply_block<NB, V_UNM>(Vs, ldv, Ts, c0, acc, nullptr, active, trans, wx);
     __syncthreads();
   }
@@ -597,17 +661,29 @@ __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T,
   const int mycol = col0 + gw * 16;
   const bool active = mycol < ncol;
   const size_t off = static_cast<size_t>(mycol + (lane & 15)) * NB;
+  Prefetch<NB> pf;
+  {
+    const int c0 = trans ? 0 : NB - IB;
+    if (tt)
+      prefetch_load<NB, ST_UPPER>(pf, V2 + c0 * NB, c0 + IB, c0, T + (c0 / IB) * IB * IB);
+    else
+      prefetch_load<NB, ST_FULL>(pf, V2 + c0 * NB, NB, c0, T + (c0 / IB) * IB * IB);
+  }
   d4 acc[NB / 32];
   if (active) load_cols<NB>(acc, C2 + off, 0, NB / 16);
+#pragma unroll 1
   for (int step = 0; step < NB / IB; ++step) {
     const int c0 = trans ? step * IB : NB - IB - step * IB;
     const int K = tt ? c0 + IB : NB;
-    if (tt)
-      stage_block<NB, ST_UPPER>(Vs, ldv, V2 + c0 * NB, K, c0);
-    else
-      stage_block<NB, ST_FULL>(Vs, ldv, V2 + c0 * NB, K, c0);
-    stage_t(Ts, T + (c0 / IB) * IB * IB);
+    prefetch_store<NB>(pf, Vs, ldv, K, Ts);
     __syncthreads();
+    if (step + 1 < NB / IB) {
+      const int n0 = trans ? c0 + IB : c0 - IB;
+      if (tt)
+        prefetch_load<NB, ST_UPPER>(pf, V2 + n0 * NB, n0 + IB, n0, T + (n0 / IB) * IB * IB);
+      else
+        prefetch_load<NB, ST_FULL>(pf, V2 + n0 * NB, NB, n0, T + (n0 / IB) * IB * IB);
+    }
     if (tt)
       apply_block<NB, V_TT>(Vs, ldv, Ts, c0, acc, C1 + off, active, trans, wx);
     else
