@@ -36,6 +36,18 @@ __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
 }
 __device__ __forceinline__ d4 zero4() { return d4{0.0, 0.0, 0.0, 0.0}; }
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+
+// Tile, T and right-hand-side data move with device-coherent (sc1) loads and
+// stores.  The eight XCDs have L2 caches that are not coherent with each
+// other; with every data access coherent at device scope, a task publishes
+// its results by waiting for its stores to complete, without writing back
+// and invalidating the whole L2 of its XCD around every task.
+__device__ __forceinline__ double gld(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void gst(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 __device__ __forceinline__ double uniform_d(double v) {
@@ -125,7 +137,7 @@ __device__ __forceinline__ void stage_block(double* Vs, int ldv, const double* s
       if (MODE == ST_UNIT_LOWER) use = use && kk > m;
       if (MODE == ST_UPPER) use = use && kk <= c0 + m;
       const double fill = (MODE == ST_UNIT_LOWER && kk == m) ? 1.0 : 0.0;
-      v[c][u] = use ? src[m * NB + kk] : fill;
+      v[c][u] = use ? gld(src + m * NB + kk) : fill;
     }
   }
 #pragma unroll
@@ -150,7 +162,7 @@ __device__ __forceinline__ void unstage_block(const double* Vs, int ldv, double*
 #pragma unroll
     for (int u = 0; u < RCH; ++u) {
       const int kk = lane + 64 * u;
-      if (kk < K && (!UPPER_ONLY || kk <= c0 + m)) dst[m * NB + kk] = Vs[kk + m * ldv];
+      if (kk < K && (!UPPER_ONLY || kk <= c0 + m)) gst(dst + m * NB + kk, Vs[kk + m * ldv]);
     }
   }
 }
@@ -160,7 +172,7 @@ __device__ __forceinline__ void stage_t(double* Ts, const double* T) {
   constexpr int PER = IB * IB / NTHREADS;
   double v[PER];
 #pragma unroll
-  for (int u = 0; u < PER; ++u) v[u] = T[threadIdx.x + NTHREADS * u];
+  for (int u = 0; u < PER; ++u) v[u] = gld(T + threadIdx.x + NTHREADS * u);
 #pragma unroll
   for (int u = 0; u < PER; ++u) Ts[threadIdx.x + NTHREADS * u] = v[u];
 }
@@ -188,11 +200,11 @@ __device__ __forceinline__ void prefetch_load(Prefetch<NB>& pf, const double* sr
       if (MODE == ST_UNIT_LOWER) use = use && kk > m;
       if (MODE == ST_UPPER) use = use && kk <= c0 + m;
       const double fill = (MODE == ST_UNIT_LOWER && kk == m) ? 1.0 : 0.0;
-      pf.v[c][u] = use ? src[m * NB + kk] : fill;
+      pf.v[c][u] = use ? gld(src + m * NB + kk) : fill;
     }
   }
 #pragma unroll
-  for (int u = 0; u < Prefetch<NB>::TPER; ++u) pf.t[u] = T[threadIdx.x + NTHREADS * u];
+  for (int u = 0; u < Prefetch<NB>::TPER; ++u) pf.t[u] = gld(T + threadIdx.x + NTHREADS * u);
 }
 
 template <int NB>
@@ -229,7 +241,7 @@ __device__ __forceinline__ void load_cols(d4 (&acc)[NB / 32], const double* C, i
       continue;
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) acc[j][i] = C[rb * 16 + 4 * i + g];
+    for (int i = 0; i < 4; ++i) acc[j][i] = gld(C + rb * 16 + 4 * i + g);
   }
 }
 template <int NB>
@@ -240,7 +252,7 @@ __device__ __forceinline__ void store_cols(const d4 (&acc)[NB / 32], double* C, 
     const int rb = 2 * j + h;
     if (rb < lo || rb >= hi) continue;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) C[rb * 16 + 4 * i + g] = acc[j][i];
+    for (int i = 0; i < 4; ++i) gst(C + rb * 16 + 4 * i + g, acc[j][i]);
   }
 }
 
@@ -289,7 +301,7 @@ __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const dou
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) c1v[mb][i] = c1[c0 + mb * 16 + 4 * i + g];
+      for (int i = 0; i < 4; ++i) c1v[mb][i] = gld(c1 + c0 + mb * 16 + 4 * i + g);
   }
   double* mine = wx + h * 8 * 64;
 #pragma unroll
@@ -326,7 +338,7 @@ __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const dou
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) c1[c0 + mb * 16 + 4 * i + g] = c1v[mb][i] - wt[mb][i];
+      for (int i = 0; i < 4; ++i) gst(c1 + c0 + mb * 16 + 4 * i + g, c1v[mb][i] - wt[mb][i]);
   }
   wt[0] = -wt[0];
   wt[1] = -wt[1];
@@ -538,7 +550,7 @@ __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm) {
     }
     __syncthreads();
     build_t<NB>(Ps, ldp, K, tau, Gs, Ts);
-    for (int e = tid; e < IB * IB; e += NTHREADS) T[(c0 / IB) * IB * IB + e] = Ts[e];
+    for (int e = tid; e < IB * IB; e += NTHREADS) gst(T + (c0 / IB) * IB * IB + e, Ts[e]);
     const int nch = (NB - c0 - IB) / 16;
 #pragma unroll 1
     for (int base = 0; base < nch; base += 4) {
@@ -573,7 +585,7 @@ __device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T,
     const int K = tt ? c0 + IB : NB;
     for (int e = tid; e < IB * IB; e += NTHREADS) {
       const int a = e % IB, c = e / IB;
-      Rs[e] = (a <= c) ? R1[(c0 + c) * NB + c0 + a] : 0.0;
+      Rs[e] = (a <= c) ? gld(R1 + (c0 + c) * NB + c0 + a) : 0.0;
     }
     if (tt)
       stage_block<NB, ST_UPPER>(Ps, ldp, A2 + c0 * NB, K, c0);
@@ -583,14 +595,14 @@ __device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T,
     panel_factor<NB, 1>(Ps, ldp, K, Rs, tau, vbuf, tt, c0);
     for (int e = tid; e < IB * IB; e += NTHREADS) {
       const int a = e % IB, c = e / IB;
-      if (a <= c) R1[(c0 + c) * NB + c0 + a] = Rs[e];
+      if (a <= c) gst(R1 + (c0 + c) * NB + c0 + a, Rs[e]);
     }
     if (tt)
       unstage_block<NB, true>(Ps, ldp, A2 + c0 * NB, K, c0);
     else
       unstage_block<NB, false>(Ps, ldp, A2 + c0 * NB, K, c0);
     build_t<NB>(Ps, ldp, K, tau, Gs, Ts);
-    for (int e = tid; e < IB * IB; e += NTHREADS) T[(c0 / IB) * IB * IB + e] = Ts[e];
+    for (int e = tid; e < IB * IB; e += NTHREADS) gst(T + (c0 / IB) * IB * IB + e, Ts[e]);
     const int nch = (NB - c0 - IB) / 16;
     const int hi = tt ? (c0 + IB) / 16 : NB / 16;
 #pragma unroll 1
@@ -765,7 +777,7 @@ __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
           int32_t* f = a.flags + a.deps[e];
           for (;;) {
             const int v = __builtin_amdgcn_readfirstlane(
-                __hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+                __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
             if (v == a.epoch) break;
             const int err = __builtin_amdgcn_readfirstlane(
                 __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -786,16 +798,17 @@ __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
     const int t = __builtin_amdgcn_readfirstlane(s_t);
     if (t >= a.nsub) break;
     if (a.trace && threadIdx.x == 0) a.trace[4 * static_cast<int64_t>(t) + 1] = static_cast<int64_t>(wall_clock64());
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (a.debug & 1) {
       for (int e = threadIdx.x; e < Smem<NB>::TOTAL; e += NTHREADS) sm[e] = 0.0;
       __syncthreads();
     }
     run_sub<NB>(a, a.sub[t], sm);
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    // Every data store of the task is device-coherent: once each wave has
+    // seen its stores complete the flag can be published.
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (wave == 0 && lane == 0) {
-      __hip_atomic_store(a.flags + t, a.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(a.flags + t, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (a.trace) {
         a.trace[4 * static_cast<int64_t>(t) + 2] = static_cast<int64_t>(wall_clock64());
         a.trace[4 * static_cast<int64_t>(t) + 3] = blockIdx.x;
