@@ -35,6 +35,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", choices=["square", "tall"], default="square")
     ap.add_argument("--kappa", type=float, default=1e2)
+    ap.add_argument("--matrix", choices=["conditioned", "gaussian"], default="conditioned",
+                    help="square workload: U diag(s) V^T with condition number kappa, or N(0,1) entries")
     ap.add_argument("--upd", choices=list(UPD), default="f32")
     ap.add_argument("--tree", choices=list(TREES), default="greedy")
     ap.add_argument("--bs", type=int, default=1)
@@ -42,6 +44,8 @@ def parse():
     ap.add_argument("--nrhs", type=int, default=4)
     ap.add_argument("--tol", type=float, default=1e-12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain 256 MiB device copy first (HBM counter calibration under rocprofv3 --pmc)")
     return ap.parse_args()
 
 
@@ -60,14 +64,14 @@ def update_flop_fraction(p, q):
 
 def cpu_baseline(nb, tree, bs, kappa):
     """The FP64 oracle (plain NumPy tiled QR) on a bounded sample of the same
-    workload: the conditioned matrix at 2048 x 2048 (p = q = 8 tiles of the
+    workload: the conditioned matrix at 1792 x 1792 (p = q = 7 tiles of the
     same nb), BLAS limited to one thread."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import tqr_inputs
     from oracle import tiled
-    n = 2048
+    n = 7 * nb
     A = tqr_inputs.conditioned(n, kappa, 102, 103)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
@@ -94,10 +98,14 @@ def main():
 
     dev = "cuda"
     nb, nrhs = args.nb, args.nrhs
-    if args.workload == "square":
+    if args.workload == "square" and args.matrix == "conditioned":
         m = n = 10240
         A = tqr_inputs.conditioned_device(n, args.kappa, tqr_inputs.SEED_C3, tqr_inputs.SEED_C3 + 1, dev).t()
         workload = "square LS %dx%d, kappa %g, nb %d, %d rhs" % (m, n, args.kappa, nb, nrhs)
+    elif args.workload == "square":
+        m = n = 10240
+        A = tqr_inputs.gaussian_device(m, n, tqr_inputs.SEED_C3, dev).t()
+        workload = "square LS %dx%d N(0,1), nb %d, %d rhs" % (m, n, nb, nrhs)
     else:
         m, n = 16384, 2048
         A = tqr_inputs.gaussian_device(m, n, tqr_inputs.SEED_C2, dev).t()
@@ -107,6 +115,12 @@ def main():
     Xt = torch.randn((nrhs, n), generator=g, dtype=torch.float64, device=dev).t()
     B = (A @ Xt).t().contiguous().t()
     torch.cuda.synchronize()
+    if args.copy_calibration:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     tree = TREES[args.tree]
     p, q = m // nb, n // nb
     F = flops(m, n)
