@@ -211,7 +211,6 @@ int check_opts(const tqr_opts* o, int64_t lda) {
   if (o->m % o->nb || o->n % o->nb || o->m < o->n) return TQR_EINVAL;
   if (lda < o->m) return TQR_EINVAL;
   if (o->upd < TQR_UPD_F64 || o->upd > TQR_UPD_BF16) return TQR_EINVAL;
-  if (o->upd != TQR_UPD_F64) return TQR_EUNSUPPORTED;
   if (o->kernels < TQR_KERN_DEFAULT || o->kernels > TQR_KERN_TS) return TQR_EINVAL;
   const int64_t p = o->m / o->nb, q = o->n / o->nb;
   if (p > (1 << 20)) return TQR_EINVAL;
@@ -244,7 +243,7 @@ int create(const tqr_opts* o, tqr_factors** out) {
   HIP_TRY(hipMemset(F->Tg, 0, ntile * tqr::IB * nbb * sizeof(double)));
   HIP_TRY(hipMemset(F->Tp, 0, ntile * tqr::IB * nbb * sizeof(double)));
   HIP_TRY(hipMemset(F->ctl, 0, 2 * sizeof(int32_t)));
-  F->grid = device_cus() * tqr::persistent_occupancy(F->nb);
+  F->grid = device_cus() * tqr::persistent_occupancy(F->nb, F->o.upd);
   *out = F.release();
   return TQR_OK;
 }

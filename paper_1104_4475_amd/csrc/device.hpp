@@ -38,7 +38,7 @@ struct ExecArgs {
   int32_t p, q, nb;
   int32_t ncolB;        // columns of the B row tiles (multiple of 16)
   int32_t transB;       // apply_q: 1 = Q^T, 0 = Q
-  int32_t upd;          // tqr_update_prec
+  int32_t upd;          // tqr_update_prec: precision of the update subtasks
   int64_t spin_ticks;   // wall-clock ticks a wait may last before giving up
   int64_t* trace;       // optional: per subtask (ticket, ready, end, workgroup)
   int32_t debug;        // diagnostics: bit 0 = clear the workgroup's LDS before each task
@@ -63,6 +63,6 @@ hipError_t launch_residual(const double* A, int64_t lda, int64_t m, int64_t n, c
 hipError_t launch_colnorms2(const double* M, int64_t ld, int64_t rows, int64_t cols, double* out, hipStream_t s);
 hipError_t launch_axpy_cols(double* X, int64_t ldx, const double* D, int64_t ldd, int64_t rows, int64_t cols,
                             hipStream_t s);
-int persistent_occupancy(int nb);
+int persistent_occupancy(int nb, int upd);
 
 }  // namespace tqr

@@ -24,17 +24,34 @@
 // contraction over those rows directly.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device.hpp"
 
 namespace tqr {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 constexpr int NWAVES = NTHREADS / 64;
 
 __device__ __forceinline__ d4 mfma(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ d4 zero4() { return d4{0.0, 0.0, 0.0, 0.0}; }
+__device__ __forceinline__ f4 zero4f() { return f4{0.0f, 0.0f, 0.0f, 0.0f}; }
+// FP32 MFMA 16x16x4 and BF16 MFMA 16x16x32 (FP32 accumulation).  Measured
+// on gfx950: both write D[4 g + r][n] (lane l = 16 g + n, register r), and
+// the k index of an A element is that of the B element in the same lane
+// and position, so any consistent assignment of k to (g, e) contracts
+// correctly.
+__device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfmabf(bf8 a, bf8 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 // Tile, T and right-hand-side data move with device-coherent (sc1) loads and
@@ -97,11 +114,31 @@ __device__ __forceinline__ double* tp_ptr(const ExecArgs& a, int r, int c) {
 }
 
 // LDS of one workgroup, in doubles.
+// Precision of the update kernels' two large contractions (the panel
+// kernels and everything else stay FP64).
+enum { P_F64 = 0, P_F32 = 1, P_BF16 = 2 };
+
+// Low-precision copies of one ib-block of reflectors in LDS, in two layouts:
+// column-major (reflector columns, rows contiguous; operand of V^T C) and
+// row-major (the ib entries of a row contiguous; operand of V W).  The
+// strides spread the 64 lanes of one LDS read over distinct banks.
+template <int NB, int P>
+struct LpV {
+  using T = typename std::conditional<P == P_F32, float, __bf16>::type;
+  static constexpr int LCM = (P == P_F32) ? NB + 3 : NB + 8;
+  static constexpr int SRM = (P == P_F32) ? 33 : 40;
+  static constexpr int CM = 0;
+  static constexpr int RM = IB * LCM;
+  static constexpr int BYTES = (IB * LCM + NB * SRM) * static_cast<int>(sizeof(T));
+};
+
 template <int NB>
 struct Smem {
   static constexpr int LDP = NB + 1;            // odd leading dimension of blocks
-  static constexpr int PS = 0;                  // reflector / panel block (LDP x IB)
-  static constexpr int TS = PS + LDP * IB;      // T block
+  static constexpr int PS = 0;                  // reflector / panel block (LDP x IB), or the LpV copies
+  static constexpr int PSZ = (LDP * IB * 8 > LpV<NB, P_F32>::BYTES ? LDP * IB : (LpV<NB, P_F32>::BYTES + 7) / 8);
+  static_assert(LpV<NB, P_BF16>::BYTES <= PSZ * 8, "LDS region of the BF16 reflector copies");
+  static constexpr int TS = PS + PSZ;           // T block
   static constexpr int GS = TS + IB * IB;       // Gram matrix V^T V
   static constexpr int RS = GS + IB * IB;       // triangle block of R1 (pair kernels)
   static constexpr int TAU = RS + IB * IB;      // tau of the panel
@@ -355,6 +392,228 @@ __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const dou
 #pragma unroll
       for (int i = 0; i < 4; ++i) c = mfma(vb[rb * 16 + (mb * 16 + 4 * i) * ldv], wt[mb][i], c);
     acc[j] = c;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Mixed-precision block update (P = P_F32 or P_BF16).  C stays FP64 in
+// registers, here with acc[j][r] = row 16 rb + 4 g + r (the D layout of the
+// FP32-output MFMAs).  V, C, W and T enter the MFMAs rounded to nearest
+// (BF16 via FP32), products accumulate in FP32, and each correction is
+// subtracted from the FP64 C.  The T-apply (W' = T^T W, 1/16 of the flops)
+// runs in FP32 in both modes.
+template <int NB>
+__device__ __forceinline__ void load_cols_lp(d4 (&acc)[NB / 32], const double* C, int lo, int hi) {
+  const int lane = lane_id(), g = lane >> 4, h = wave_id() >> 2;
+#pragma unroll
+  for (int j = 0; j < NB / 32; ++j) {
+    const int rb = 2 * j + h;
+    if (rb < lo || rb >= hi) {
+      acc[j] = zero4();
+      continue;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[j][r] = gld(C + rb * 16 + 4 * g + r);
+  }
+}
+template <int NB>
+__device__ __forceinline__ void store_cols_lp(const d4 (&acc)[NB / 32], double* C, int lo, int hi) {
+  const int lane = lane_id(), g = lane >> 4, h = wave_id() >> 2;
+#pragma unroll
+  for (int j = 0; j < NB / 32; ++j) {
+    const int rb = 2 * j + h;
+    if (rb < lo || rb >= hi) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) gst(C + rb * 16 + 4 * g + r, acc[j][r]);
+  }
+}
+
+template <int P>
+__device__ __forceinline__ typename LpV<32, P>::T to_lp(double x) {
+  if constexpr (P == P_F32)
+    return static_cast<float>(x);
+  else
+    return static_cast<__bf16>(static_cast<float>(x));
+}
+
+// Prefetched reflector block (FP64 registers) into both low-precision LDS
+// copies; the T block stays FP64.
+template <int NB, int P>
+__device__ __forceinline__ void prefetch_store_lp(const Prefetch<NB>& pf, unsigned char* vl, int K, double* Ts) {
+  using L = LpV<NB, P>;
+  using T = typename L::T;
+  T* cm = reinterpret_cast<T*>(vl) + L::CM;
+  T* rm = reinterpret_cast<T*>(vl) + L::RM;
+  const int lane = lane_id(), wave = wave_id();
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int m = wave + NWAVES * c;
+#pragma unroll
+    for (int u = 0; u < Prefetch<NB>::RCH; ++u) {
+      const int kk = lane + 64 * u;
+      if (kk < K) {
+        const T v = to_lp<P>(pf.v[c][u]);
+        cm[m * L::LCM + kk] = v;
+        rm[kk * L::SRM + m] = v;
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < Prefetch<NB>::TPER; ++u) Ts[threadIdx.x + NTHREADS * u] = pf.t[u];
+}
+
+// Same contract as apply_block (rows, c1, barrier, trans); vl holds the
+// LpV copies of the block's reflectors, wx is the group's exchange area.
+template <int NB, int VAR, int P>
+__device__ __forceinline__ void apply_block_lp(const unsigned char* vl, const double* Ts, int c0, d4 (&acc)[NB / 32],
+                                               double* c1, bool active, int trans, float* wx) {
+  using L = LpV<NB, P>;
+  using T = typename L::T;
+  const T* cm = reinterpret_cast<const T*>(vl) + L::CM;
+  const T* rm = reinterpret_cast<const T*>(vl) + L::RM;
+  const int lane = lane_id(), g = lane >> 4, n = lane & 15;
+  const int h = wave_id() >> 2;
+  const int rb_lo = (VAR == V_UNM) ? (c0 >> 4) : 0;
+  const int rb_hi = (VAR == V_TT) ? ((c0 + IB) >> 4) : (NB >> 4);
+  const int vbase = (VAR == V_UNM) ? c0 : 0;
+  constexpr int NJ = NB / 32;
+  // Partial W = V^T C over this wave's row blocks: w[mb] holds rows
+  // 16 mb + 4 g + r of W.
+  f4 w[2] = {zero4f(), zero4f()};
+  if (active) {
+    if constexpr (P == P_F32) {
+      // k-slice r of row block rb: rows 16 rb + 4 g + r.
+      f4 w1[2] = {zero4f(), zero4f()};
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        const int rb = 2 * j + h;
+        if (rb < rb_lo || rb >= rb_hi) continue;
+        const float* va = cm + n * L::LCM + (rb * 16 + 4 * g - vbase);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float b = static_cast<float>(acc[j][r]);
+          if (r & 1) {
+            w1[0] = mfma32(va[r], b, w1[0]);
+            w1[1] = mfma32(va[16 * L::LCM + r], b, w1[1]);
+          } else {
+            w[0] = mfma32(va[r], b, w[0]);
+            w[1] = mfma32(va[16 * L::LCM + r], b, w[1]);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      w[0] += w1[0];
+      w[1] += w1[1];
+    } else {
+      // One k-slice of 32 rows per pair of this wave's row blocks:
+      // element e of lane (g, n) is row 16 rb_{e/4} + 4 g + e % 4.
+      const bf4 zb = {static_cast<__bf16>(0.0f), static_cast<__bf16>(0.0f), static_cast<__bf16>(0.0f),
+                      static_cast<__bf16>(0.0f)};
+#pragma unroll
+      for (int j = 0; j < NJ; j += 2) {
+        const int j1 = (j + 1 < NJ) ? j + 1 : j;
+        const int rb0 = 2 * j + h, rb1 = 2 * (j + 1) + h;
+        const bool v0 = rb0 >= rb_lo && rb0 < rb_hi;
+        const bool v1 = (j + 1 < NJ) && rb1 >= rb_lo && rb1 < rb_hi;
+        if (!v0 && !v1) continue;
+        bf8 b;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          b[e] = v0 ? to_lp<P>(acc[j][e]) : static_cast<__bf16>(0.0f);
+          b[4 + e] = v1 ? to_lp<P>(acc[j1][e]) : static_cast<__bf16>(0.0f);
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+          const T* col = cm + (mb * 16 + n) * L::LCM + 4 * g - vbase;
+          const bf4 a0 = v0 ? *reinterpret_cast<const bf4*>(col + rb0 * 16) : zb;
+          const bf4 a1 = v1 ? *reinterpret_cast<const bf4*>(col + rb1 * 16) : zb;
+          w[mb] = mfmabf(__builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7), b, w[mb]);
+        }
+      }
+    }
+  }
+  // C1 rows c0 + 16 mb + 4 g + r (pairs), read by both waves before the
+  // barrier and written by the h = 0 wave after it.
+  d4 c1v[2] = {zero4(), zero4()};
+  if (VAR != V_UNM && active) {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) c1v[mb][r] = gld(c1 + c0 + mb * 16 + 4 * g + r);
+  }
+  float* mine = wx + h * 8 * 64;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) mine[(mb * 4 + r) * 64 + lane] = w[mb][r];
+  __syncthreads();
+  const float* other = wx + (1 - h) * 8 * 64;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) w[mb][r] += other[(mb * 4 + r) * 64 + lane];
+  if (!active) return;
+  if (VAR != V_UNM) {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) w[mb][r] += static_cast<float>(c1v[mb][r]);
+  }
+  // W' = op(T) W in FP32: wt[ab] holds rows 16 ab + 4 g + r.
+  f4 wt[2] = {zero4f(), zero4f()};
+#pragma unroll
+  for (int ab = 0; ab < 2; ++ab) {
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) {
+      if (trans ? (jb > ab) : (jb < ab)) continue;  // T is upper triangular
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int kk = jb * 16 + 4 * g + r, aa = ab * 16 + n;
+        const double t = trans ? Ts[kk + aa * IB] : Ts[aa + kk * IB];
+        wt[ab] = mfma32(static_cast<float>(t), w[jb][r], wt[ab]);
+      }
+    }
+  }
+  if (VAR != V_UNM && h == 0) {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gst(c1 + c0 + mb * 16 + 4 * g + r, c1v[mb][r] - static_cast<double>(wt[mb][r]));
+  }
+  // C -= V W'.
+  if constexpr (P == P_F32) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int rb = 2 * j + h;
+      if (rb < rb_lo || rb >= rb_hi) continue;
+      const float* vr = rm + (rb * 16 + n - vbase) * L::SRM + 4 * g;
+      f4 d = zero4f();
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) d = mfma32(vr[mb * 16 + r], wt[mb][r], d);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[j][r] -= static_cast<double>(d[r]);
+    }
+  } else {
+    // k-slice: element e of lane (g, n) is reflector 16 (e / 4) + 4 g + e % 4.
+    bf8 bw;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      bw[e] = static_cast<__bf16>(wt[0][e]);
+      bw[4 + e] = static_cast<__bf16>(wt[1][e]);
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int rb = 2 * j + h;
+      if (rb < rb_lo || rb >= rb_hi) continue;
+      const T* vr = rm + (rb * 16 + n - vbase) * L::SRM + 4 * g;
+      const bf4 a0 = *reinterpret_cast<const bf4*>(vr);
+      const bf4 a1 = *reinterpret_cast<const bf4*>(vr + 16);
+      const f4 d = mfmabf(__builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7), bw, zero4f());
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[j][r] -= static_cast<double>(d[r]);
+    }
   }
 }
 
@@ -627,7 +886,7 @@ __device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T,
 // ---- UNMQR (and application of a GEQRT set to B) ---------------------------
 // V: the factored tile; T: its T factors; C: target with leading dimension
 // NB and ncol columns; the subtask covers columns col0..col0+63.
-template <int NB>
+template <int NB, int P>
 __device__ __forceinline__ void unmqr_task(const double* V, const double* T, double* C, int col0, int ncol, double* sm,
                                            int trans) {
   constexpr int ldv = Smem<NB>::LDP;
@@ -643,26 +902,43 @@ __device__ __forceinline__ void unmqr_task(const double* V, const double* T, dou
     const int c0 = trans ? 0 : NB - IB;
     prefetch_load<NB, ST_UNIT_LOWER>(pf, V + c0 * NB + c0, NB - c0, c0, T + (c0 / IB) * IB * IB);
   }
+  unsigned char* vl = reinterpret_cast<unsigned char*>(sm + Smem<NB>::PS);
   d4 acc[NB / 32];
-  if (active) load_cols<NB>(acc, Cw, 0, NB / 16);
+  if (active) {
+    if constexpr (P == P_F64)
+      load_cols<NB>(acc, Cw, 0, NB / 16);
+    else
+      load_cols_lp<NB>(acc, Cw, 0, NB / 16);
+  }
 #pragma unroll 1
   for (int step = 0; step < NB / IB; ++step) {
     const int c0 = trans ? step * IB : NB - IB - step * IB;
     const int K = NB - c0;
-    prefetch_store<NB>(pf, Vs, ldv, K, Ts);
+    if constexpr (P == P_F64)
+      prefetch_store<NB>(pf, Vs, ldv, K, Ts);
+    else
+      prefetch_store_lp<NB, P>(pf, vl, K, Ts);
     __syncthreads();
     if (step + 1 < NB / IB) {
       const int n0 = trans ? c0 + IB : c0 - IB;
       prefetch_load<NB, ST_UNIT_LOWER>(pf, V + n0 * NB + n0, NB - n0, n0, T + (n0 / IB) * IB * IB);
     }
-    apply_block<NB, V_UNM>(Vs, ldv, Ts, c0, acc, nullptr, active, trans, wx);
+    if constexpr (P == P_F64)
+      apply_block<NB, V_UNM>(Vs, ldv, Ts, c0, acc, nullptr, active, trans, wx);
+    else
+      apply_block_lp<NB, V_UNM, P>(vl, Ts, c0, acc, nullptr, active, trans, reinterpret_cast<float*>(wx));
     __syncthreads();
   }
-  if (active) store_cols<NB>(acc, Cw, 0, NB / 16);
+  if (active) {
+    if constexpr (P == P_F64)
+      store_cols<NB>(acc, Cw, 0, NB / 16);
+    else
+      store_cols_lp<NB>(acc, Cw, 0, NB / 16);
+  }
 }
 
 // ---- TSMQR / TTMQR (and application of a pair set to B) --------------------
-template <int NB>
+template <int NB, int P>
 __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T, double* C1, double* C2, int col0,
                                               int ncol, double* sm, int tt, int trans) {
   constexpr int ldv = Smem<NB>::LDP;
@@ -681,13 +957,22 @@ __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T,
     else
       prefetch_load<NB, ST_FULL>(pf, V2 + c0 * NB, NB, c0, T + (c0 / IB) * IB * IB);
   }
+  unsigned char* vl = reinterpret_cast<unsigned char*>(sm + Smem<NB>::PS);
   d4 acc[NB / 32];
-  if (active) load_cols<NB>(acc, C2 + off, 0, NB / 16);
+  if (active) {
+    if constexpr (P == P_F64)
+      load_cols<NB>(acc, C2 + off, 0, NB / 16);
+    else
+      load_cols_lp<NB>(acc, C2 + off, 0, NB / 16);
+  }
 #pragma unroll 1
   for (int step = 0; step < NB / IB; ++step) {
     const int c0 = trans ? step * IB : NB - IB - step * IB;
     const int K = tt ? c0 + IB : NB;
-    prefetch_store<NB>(pf, Vs, ldv, K, Ts);
+    if constexpr (P == P_F64)
+      prefetch_store<NB>(pf, Vs, ldv, K, Ts);
+    else
+      prefetch_store_lp<NB, P>(pf, vl, K, Ts);
     __syncthreads();
     if (step + 1 < NB / IB) {
       const int n0 = trans ? c0 + IB : c0 - IB;
@@ -696,23 +981,38 @@ __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T,
       else
         prefetch_load<NB, ST_FULL>(pf, V2 + n0 * NB, NB, n0, T + (n0 / IB) * IB * IB);
     }
-    if (tt)
-      apply_block<NB, V_TT>(Vs, ldv, Ts, c0, acc, C1 + off, active, trans, wx);
-    else
-      apply_block<NB, V_TS>(Vs, ldv, Ts, c0, acc, C1 + off, active, trans, wx);
+    if constexpr (P == P_F64) {
+      if (tt)
+        apply_block<NB, V_TT>(Vs, ldv, Ts, c0, acc, C1 + off, active, trans, wx);
+      else
+        apply_block<NB, V_TS>(Vs, ldv, Ts, c0, acc, C1 + off, active, trans, wx);
+    } else {
+      float* wxf = reinterpret_cast<float*>(wx);
+      if (tt)
+        apply_block_lp<NB, V_TT, P>(vl, Ts, c0, acc, C1 + off, active, trans, wxf);
+      else
+        apply_block_lp<NB, V_TS, P>(vl, Ts, c0, acc, C1 + off, active, trans, wxf);
+    }
     __syncthreads();
   }
-  if (active) store_cols<NB>(acc, C2 + off, 0, NB / 16);
+  if (active) {
+    if constexpr (P == P_F64)
+      store_cols<NB>(acc, C2 + off, 0, NB / 16);
+    else
+      store_cols_lp<NB>(acc, C2 + off, 0, NB / 16);
+  }
 }
 
-template <int NB>
+// P: precision of the update subtasks (UNMQR, TSMQR, TTMQR); the panel
+// subtasks and the application of Q to right-hand sides are FP64.
+template <int NB, int P>
 __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, double* sm) {
   switch (s.kind) {
     case D_GEQRT:
       geqrt_task<NB>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), sm);
       break;
     case D_UNMQR:
-      unmqr_task<NB>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), tile_ptr(a, s.i, s.j), s.slab * SLAB, NB, sm, 1);
+      unmqr_task<NB, P>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), tile_ptr(a, s.i, s.j), s.slab * SLAB, NB, sm, 1);
       break;
     case D_TSQRT:
     case D_TTQRT:
@@ -720,19 +1020,19 @@ __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, doub
       break;
     case D_TSMQR:
     case D_TTMQR:
-      pair_mqr_task<NB>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), tile_ptr(a, s.piv, s.j), tile_ptr(a, s.i, s.j),
+      pair_mqr_task<NB, P>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), tile_ptr(a, s.piv, s.j), tile_ptr(a, s.i, s.j),
                         s.slab * SLAB, NB, sm, s.kind == D_TTMQR, 1);
       break;
     case D_APPLY_GE: {
       double* Bi = a.B + static_cast<size_t>(s.i) * NB * a.ncolB;
-      unmqr_task<NB>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), Bi, s.slab * SLAB, a.ncolB, sm, a.transB);
+      unmqr_task<NB, P_F64>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), Bi, s.slab * SLAB, a.ncolB, sm, a.transB);
       break;
     }
     case D_APPLY_TS:
     case D_APPLY_TT: {
       double* Bp = a.B + static_cast<size_t>(s.piv) * NB * a.ncolB;
       double* Bi = a.B + static_cast<size_t>(s.i) * NB * a.ncolB;
-      pair_mqr_task<NB>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), Bp, Bi, s.slab * SLAB, a.ncolB, sm,
+      pair_mqr_task<NB, P_F64>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), Bp, Bi, s.slab * SLAB, a.ncolB, sm,
                         s.kind == D_APPLY_TT, a.transB);
       break;
     }
@@ -749,7 +1049,7 @@ __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, doub
 // so the smallest unfinished subtask can always proceed (no residency
 // assumption).  A wait longer than spin_ticks sets *err, and every
 // workgroup then leaves at its next wait or ticket.
-template <int NB>
+template <int NB, int P>
 __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
   __shared__ double sm[Smem<NB>::TOTAL];
   __shared__ int s_t;
@@ -802,7 +1102,7 @@ __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
       for (int e = threadIdx.x; e < Smem<NB>::TOTAL; e += NTHREADS) sm[e] = 0.0;
       __syncthreads();
     }
-    run_sub<NB>(a, a.sub[t], sm);
+    run_sub<NB, P>(a, a.sub[t], sm);
     // Every data store of the task is device-coherent: once each wave has
     // seen its stores complete the flag can be published.
     __builtin_amdgcn_s_waitcnt(0);
@@ -819,11 +1119,11 @@ __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
 
 // Level-synchronous executor: one launch per DAG depth level, one subtask
 // per workgroup (kernel boundaries order the levels).
-template <int NB>
+template <int NB, int P>
 __global__ __launch_bounds__(NTHREADS) void exec_level(ExecArgs a, const int32_t* order, int begin) {
   __shared__ double sm[Smem<NB>::TOTAL];
   const int t = __builtin_amdgcn_readfirstlane(order[begin + blockIdx.x]);
-  run_sub<NB>(a, a.sub[t], sm);
+  run_sub<NB, P>(a, a.sub[t], sm);
 }
 
 __global__ void reset_kernel(int32_t* ticket, int32_t* err) {
@@ -836,12 +1136,33 @@ hipError_t launch_reset(int32_t* ticket, int32_t* err, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <int NB>
+static hipError_t launch_persistent_nb(const ExecArgs& a, int grid, hipStream_t s) {
+  switch (a.upd) {
+    case P_F64: hipLaunchKernelGGL((exec_persistent<NB, P_F64>), dim3(grid), dim3(NTHREADS), 0, s, a); break;
+    case P_F32: hipLaunchKernelGGL((exec_persistent<NB, P_F32>), dim3(grid), dim3(NTHREADS), 0, s, a); break;
+    case P_BF16: hipLaunchKernelGGL((exec_persistent<NB, P_BF16>), dim3(grid), dim3(NTHREADS), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_persistent(const ExecArgs& a, int grid, hipStream_t s) {
   switch (a.nb) {
-    case 32: hipLaunchKernelGGL(exec_persistent<32>, dim3(grid), dim3(NTHREADS), 0, s, a); break;
-    case 64: hipLaunchKernelGGL(exec_persistent<64>, dim3(grid), dim3(NTHREADS), 0, s, a); break;
-    case 128: hipLaunchKernelGGL(exec_persistent<128>, dim3(grid), dim3(NTHREADS), 0, s, a); break;
-    case 256: hipLaunchKernelGGL(exec_persistent<256>, dim3(grid), dim3(NTHREADS), 0, s, a); break;
+    case 32: return launch_persistent_nb<32>(a, grid, s);
+    case 64: return launch_persistent_nb<64>(a, grid, s);
+    case 128: return launch_persistent_nb<128>(a, grid, s);
+    case 256: return launch_persistent_nb<256>(a, grid, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NB>
+static hipError_t launch_level_nb(const ExecArgs& a, const int32_t* order, int begin, int count, hipStream_t s) {
+  switch (a.upd) {
+    case P_F64: hipLaunchKernelGGL((exec_level<NB, P_F64>), dim3(count), dim3(NTHREADS), 0, s, a, order, begin); break;
+    case P_F32: hipLaunchKernelGGL((exec_level<NB, P_F32>), dim3(count), dim3(NTHREADS), 0, s, a, order, begin); break;
+    case P_BF16: hipLaunchKernelGGL((exec_level<NB, P_BF16>), dim3(count), dim3(NTHREADS), 0, s, a, order, begin); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -849,26 +1170,35 @@ hipError_t launch_persistent(const ExecArgs& a, int grid, hipStream_t s) {
 
 hipError_t launch_level(const ExecArgs& a, const int32_t* order, int begin, int count, hipStream_t s) {
   switch (a.nb) {
-    case 32: hipLaunchKernelGGL(exec_level<32>, dim3(count), dim3(NTHREADS), 0, s, a, order, begin); break;
-    case 64: hipLaunchKernelGGL(exec_level<64>, dim3(count), dim3(NTHREADS), 0, s, a, order, begin); break;
-    case 128: hipLaunchKernelGGL(exec_level<128>, dim3(count), dim3(NTHREADS), 0, s, a, order, begin); break;
-    case 256: hipLaunchKernelGGL(exec_level<256>, dim3(count), dim3(NTHREADS), 0, s, a, order, begin); break;
+    case 32: return launch_level_nb<32>(a, order, begin, count, s);
+    case 64: return launch_level_nb<64>(a, order, begin, count, s);
+    case 128: return launch_level_nb<128>(a, order, begin, count, s);
+    case 256: return launch_level_nb<256>(a, order, begin, count, s);
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
-int persistent_occupancy(int nb) {
+template <int NB>
+static int occupancy_nb(int upd) {
   int blocks = 0;
   hipError_t e = hipErrorInvalidValue;
-  switch (nb) {
-    case 32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, exec_persistent<32>, NTHREADS, 0); break;
-    case 64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, exec_persistent<64>, NTHREADS, 0); break;
-    case 128: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, exec_persistent<128>, NTHREADS, 0); break;
-    case 256: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, exec_persistent<256>, NTHREADS, 0); break;
+  switch (upd) {
+    case P_F64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, exec_persistent<NB, P_F64>, NTHREADS, 0); break;
+    case P_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, exec_persistent<NB, P_F32>, NTHREADS, 0); break;
+    case P_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, exec_persistent<NB, P_BF16>, NTHREADS, 0); break;
     default: break;
   }
   return (e == hipSuccess && blocks > 0) ? blocks : 1;
+}
+
+int persistent_occupancy(int nb, int upd) {
+  switch (nb) {
+    case 32: return occupancy_nb<32>(upd);
+    case 64: return occupancy_nb<64>(upd);
+    case 128: return occupancy_nb<128>(upd);
+    case 256: return occupancy_nb<256>(upd);
+    default: return 1;
+  }
 }
 
 }  // namespace tqr
