@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <map>
@@ -118,9 +119,36 @@ bool use_level_path() {
   return e && std::strcmp(e, "level") == 0;
 }
 
+// Dispatch priority of the executor: largest bottom level first (the
+// longest remaining path through the DAG), or for diagnostics (TQR_ORDER)
+// the ASAP or ALAP start time.
 int exec_order() {
   const char* e = std::getenv("TQR_ORDER");
-  return (e && std::strcmp(e, "alap") == 0) ? 1 : 0;
+  if (e && std::strcmp(e, "asap") == 0) return 0;
+  if (e && std::strcmp(e, "alap") == 0) return 1;
+  return 2;
+}
+
+// Per-kind task weights (GEQRT, UNMQR, TSQRT, TSMQR, TTQRT, TTMQR) for the
+// priorities: measured durations on MI355X of one task (all column slabs of
+// an update) in microseconds, per tile size and update precision.  Other
+// tile sizes use the Table 1 flop weights.  TQR_WEIGHTS (six comma-separated
+// numbers) overrides them for diagnostics.
+void exec_weights(int nb, int upd, double w[6]) {
+  static const double table1[6] = {4, 6, 6, 12, 2, 6};
+  static const double nb256[3][6] = {{600, 364, 735, 480, 533, 412},
+                                     {610, 300, 770, 430, 560, 396},
+                                     {620, 268, 775, 372, 568, 352}};
+  static const double nb128[6] = {199, 164, 260, 300, 213, 228};
+  const double* src = table1;
+  if (nb == 256 && upd >= 0 && upd < 3) src = nb256[upd];
+  if (nb == 128) src = nb128;
+  for (int k = 0; k < 6; ++k) w[k] = src[k];
+  if (const char* e = std::getenv("TQR_WEIGHTS")) {
+    double v[6];
+    if (std::sscanf(e, "%lf,%lf,%lf,%lf,%lf,%lf", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 6)
+      for (int k = 0; k < 6; ++k) w[k] = v[k];
+  }
 }
 
 }  // namespace
@@ -227,7 +255,8 @@ int create(const tqr_opts* o, tqr_factors** out) {
   F->p = static_cast<int>(o->m / o->nb);
   F->q = static_cast<int>(o->n / o->nb);
   if (!tqr::make_plan(F->p, F->q, o->tree, o->bs, o->kernels, F->plan)) return TQR_EINVAL;
-  const double w[6] = {4, 6, 6, 12, 2, 6};
+  double w[6];
+  exec_weights(o->nb, o->upd, w);
   ExecPlan ex;
   const int nslab = std::max(1, F->nb / tqr::SLAB);
   tqr::make_exec_plan(F->plan, nslab, exec_order(), w, ex);

@@ -327,8 +327,9 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
     }
   }
 
-  // Priorities: ASAP start (order 0) or ALAP start (order 1) of each subtask
-  // with per-kind weights (updates divided among their slabs).
+  // Priorities: ASAP start (order 0), ALAP start (order 1) or largest bottom
+  // level first (order 2) of each subtask, with per-kind weights (updates
+  // divided among their slabs).
   const size_t n = sub.size();
   std::vector<double> wt(n), est(n, 0.0), lst(n, 0.0);
   for (size_t s = 0; s < n; ++s) {
@@ -351,7 +352,16 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
     for (int32_t c : succ[s]) lf = std::min(lf, lst[c]);
     lst[s] = lf - wt[s];
   }
-  const std::vector<double>& key = (order == 1) ? lst : est;
+  // Bottom level: longest path from the start of the subtask to the end.
+  std::vector<double> bl(n, 0.0);
+  for (size_t s = n; s-- > 0;) {
+    double m = 0.0;
+    for (int32_t c : succ[s]) m = std::max(m, bl[c]);
+    bl[s] = m + wt[s];
+  }
+  std::vector<double> negbl(n);
+  for (size_t s = 0; s < n; ++s) negbl[s] = -bl[s];
+  const std::vector<double>& key = (order == 1) ? lst : (order == 2 ? negbl : est);
   std::vector<int32_t> perm(n);
   std::iota(perm.begin(), perm.end(), 0);
   std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {

@@ -121,10 +121,13 @@ def test_level_executor_matches_persistent(torch_cuda, monkeypatch):
     monkeypatch.setenv("TQR_EXEC", "persistent")
 
 
-def test_alap_order_matches(torch_cuda, monkeypatch):
-    _say("alap order")
+@pytest.mark.parametrize("order", ["asap", "alap"])
+def test_other_dispatch_orders_match(torch_cuda, monkeypatch, order):
+    """The default dispatch order is largest bottom level first; the ASAP
+    and ALAP orders must give the same factors."""
+    _say("%s order" % order)
     A = tqr_inputs.gaussian(512, 256, seed=4)
-    monkeypatch.setenv("TQR_ORDER", "alap")
+    monkeypatch.setenv("TQR_ORDER", order)
     F, O = _factor_both(torch_cuda, A, 64, trees.FIBONACCI, 1, dag.KERN_TT)
     monkeypatch.delenv("TQR_ORDER")
     _compare(torch_cuda, F, O, A)
