@@ -162,7 +162,8 @@ struct tqr_factors {
   double* tiles = nullptr;
   double* Tg = nullptr;
   double* Tp = nullptr;
-  int32_t* ctl = nullptr;  // [0] ticket, [1] err
+  int32_t* ctl = nullptr;  // [0] ticket, [1] executor err, [2] solve err, [3..3+q) solve flags
+  mutable int32_t solve_epoch = 0;  // advanced by every triangular solve launch
   hipStream_t stream = nullptr;
   int grid = 1;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -207,6 +208,12 @@ ExecArgs base_args(const tqr_factors* F, const DevPlan& d) {
   const char* dbg = std::getenv("TQR_DEBUG");
   a.debug = dbg ? std::atoi(dbg) : 0;
   return a;
+}
+
+// X <- R^{-1} X (n x nrhs, in place) with the handle's tiled R.
+hipError_t solve_r(const tqr_factors* F, double* X, int64_t ldx, int64_t nrhs, hipStream_t s) {
+  return tqr::launch_trsm_upper(F->tiles, F->p, F->q, F->nb, X, ldx, nrhs, F->ctl + 3, &F->solve_epoch, F->ctl + 2,
+                                4 * wall_ticks_per_second(), s);
 }
 
 int run_plan(tqr_factors* F, DevPlan& d, ExecArgs a, hipStream_t s) {
@@ -267,11 +274,11 @@ int create(const tqr_opts* o, tqr_factors** out) {
   if (!hip_ok(hipMalloc(&F->tiles, ntile * nbb * nbb * sizeof(double))) ||
       !hip_ok(hipMalloc(&F->Tg, ntile * tqr::IB * nbb * sizeof(double))) ||
       !hip_ok(hipMalloc(&F->Tp, ntile * tqr::IB * nbb * sizeof(double))) ||
-      !hip_ok(hipMalloc(&F->ctl, 2 * sizeof(int32_t))))
+      !hip_ok(hipMalloc(&F->ctl, (3 + F->q) * sizeof(int32_t))))
     return TQR_ENOMEM;
   HIP_TRY(hipMemset(F->Tg, 0, ntile * tqr::IB * nbb * sizeof(double)));
   HIP_TRY(hipMemset(F->Tp, 0, ntile * tqr::IB * nbb * sizeof(double)));
-  HIP_TRY(hipMemset(F->ctl, 0, 2 * sizeof(int32_t)));
+  HIP_TRY(hipMemset(F->ctl, 0, (3 + F->q) * sizeof(int32_t)));
   F->grid = device_cus() * tqr::persistent_occupancy(F->nb, F->o.upd);
   *out = F.release();
   return TQR_OK;
@@ -362,8 +369,9 @@ int tiledqr_sync(tqr_factors* F) {
   if (!F) return TQR_EINVAL;
   HIP_TRY(hipStreamSynchronize(F->stream));
   int32_t err = 0;
-  HIP_TRY(hipMemcpy(&err, F->ctl + 1, sizeof(int32_t), hipMemcpyDeviceToHost));
-  return err ? TQR_EEXEC : TQR_OK;
+  int32_t errs[2] = {0, 0};
+  HIP_TRY(hipMemcpy(errs, F->ctl + 1, 2 * sizeof(int32_t), hipMemcpyDeviceToHost));
+  return (errs[0] || errs[1]) ? TQR_EEXEC : TQR_OK;
 }
 
 int tiledqr_exec_time(tqr_factors* F, float* ms) {
@@ -533,7 +541,7 @@ int tiledqr_lstsq(const tqr_factors* F, const double* A0, int64_t lda, const dou
   st = apply_tiles(F, 1, Bt, ncolB, s);
   if (st != TQR_OK) return fail(st);
   if (!hip_ok(tqr::launch_unpack_b(Bt, X, ldx, nrhs, static_cast<int>(n), F->nb, ncolB, s))) return fail(TQR_EHIP);
-  if (!hip_ok(tqr::launch_trsm_upper(F->tiles, F->p, F->q, F->nb, X, ldx, nrhs, s))) return fail(TQR_EHIP);
+  if (!hip_ok(solve_r(F, X, ldx, nrhs, s))) return fail(TQR_EHIP);
   if (!refine) {
     if (info) {
       info->iters = 0;
@@ -576,9 +584,12 @@ int tiledqr_lstsq(const tqr_factors* F, const double* A0, int64_t lda, const dou
     if (!hip_ok(tqr::launch_colnorms2(Rv, m, m, nrhs, nrm, s)) ||
         !hip_ok(tqr::launch_colnorms2(X, ldx, n, nrhs, nrm + nrhs, s)))
       return fail(TQR_EHIP);
+    int32_t serr = 0;
     if (!hip_ok(hipMemcpyAsync(h.data(), nrm, 3 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s)) ||
+        !hip_ok(hipMemcpyAsync(&serr, F->ctl + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s)) ||
         !hip_ok(hipStreamSynchronize(s)))
       return fail(TQR_EHIP);
+    if (serr) return fail(TQR_EEXEC);
     double fa = 0.0;
     for (double v : colA) fa += v;
     fa = std::sqrt(fa);
@@ -600,7 +611,7 @@ int tiledqr_lstsq(const tqr_factors* F, const double* A0, int64_t lda, const dou
     st = apply_tiles(F, 1, Bt, ncolB, s);
     if (st != TQR_OK) return fail(st);
     if (!hip_ok(tqr::launch_unpack_b(Bt, D, n, nrhs, static_cast<int>(n), F->nb, ncolB, s)) ||
-        !hip_ok(tqr::launch_trsm_upper(F->tiles, F->p, F->q, F->nb, D, n, nrhs, s)) ||
+        !hip_ok(solve_r(F, D, n, nrhs, s)) ||
         !hip_ok(tqr::launch_axpy_cols(X, ldx, D, n, n, nrhs, s)))
       return fail(TQR_EHIP);
   }

@@ -56,8 +56,11 @@ hipError_t launch_pack_b(const double* B, int64_t ldb, int64_t nrhs, double* Bt,
                          hipStream_t s);
 hipError_t launch_unpack_b(const double* Bt, double* B, int64_t ldb, int64_t nrhs, int rows, int nb, int ncolB,
                            hipStream_t s);
+// X = R^{-1} Y in place (Y: n x nrhs, column-major).  flags: q int32 owned
+// by the caller, compared with the per-launch epoch (*epoch is advanced);
+// err: set when a wait exceeds spin_ticks.
 hipError_t launch_trsm_upper(const double* tiles, int p, int q, int nb, double* Y, int64_t ldy, int64_t nrhs,
-                             hipStream_t s);
+                             int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks, hipStream_t s);
 hipError_t launch_residual(const double* A, int64_t lda, int64_t m, int64_t n, const double* X, int64_t ldx,
                            const double* B, int64_t ldb, int64_t nrhs, double* Rv, int64_t ldr, hipStream_t s);
 hipError_t launch_colnorms2(const double* M, int64_t ld, int64_t rows, int64_t cols, double* out, hipStream_t s);

@@ -12,49 +12,159 @@ __device__ __forceinline__ const double* rtile(const double* tiles, int p, int n
   return tiles + (static_cast<size_t>(c) * p + r) * static_cast<size_t>(nb) * nb;
 }
 
-// Solve R_kk X_k = Y_k in place for the diagonal tile k (one workgroup).
-// Column-oriented back substitution: x_c = y_c / R[c][c], then
-// y_r -= R[r][c] x_c for r < c, one thread per row.
-__global__ __launch_bounds__(256) void trsm_diag_kernel(const double* tiles, int p, int nb, int k, double* Y,
-                                                        int64_t ldy, int64_t nrhs) {
-  __shared__ double xs[8];
-  const double* R = rtile(tiles, p, nb, k, k);
-  const int tid = threadIdx.x;
-  double* Yk = Y + static_cast<int64_t>(k) * nb;
-  for (int64_t c0 = 0; c0 < nrhs; c0 += 8) {
-    const int nc = static_cast<int>(nrhs - c0 < 8 ? nrhs - c0 : 8);
-    double y[8];
-    for (int h = 0; h < 8; ++h) y[h] = (tid < nb && h < nc) ? Yk[(c0 + h) * ldy + tid] : 0.0;
-    for (int c = nb - 1; c >= 0; --c) {
-      if (tid == c) {
-        const double d = R[c * nb + c];
-        for (int h = 0; h < nc; ++h) {
-          y[h] /= d;
-          xs[h] = y[h];
-        }
+// Back substitution X = R^{-1} Y with the tiled upper triangular R (tiles
+// (i, k), i <= k < q), in place in Y (rows i nb .. i nb + nb - 1 of tile row
+// i).  One workgroup per tile row, block b taking row i = q - 1 - b, so a
+// workgroup only waits for workgroups with smaller indices (already
+// running): no residency assumption.  Row i applies Y_i -= R_ik X_k for
+// k = q-1 .. i+1 as each X_k is published (flag k set to the launch's epoch),
+// then solves R_ii X_i = Y_i: 32-row blocks from the bottom, each solved on
+// one wave by sequential substitution with broadcasts by readlane, and
+// subtracted from the rows above by all waves.  Up to TR_COLS right-hand
+// sides per launch.  A wait longer than spin_ticks sets *err and the
+// workgroup leaves.
+constexpr int TR_THREADS = 512;
+constexpr int TR_COLS = 16;
+
+__device__ __forceinline__ double ld_coh(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_coh(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double readlane_d(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane(static_cast<int>(b), src);
+  const int hi = __builtin_amdgcn_readlane(static_cast<int>(b >> 32), src);
+  return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
+}
+
+// ys[c * NB + row] -= sum_l M[(l0 + l) * NB + row] * xs[c * NB + l0 + l] for
+// rows < nrow, l < nl, columns < nc.  Thread t handles row t % NB and the
+// l-range part t / NB of G = TR_THREADS / NB parts (loads issued 16 at a
+// time); the G partial sums meet in ps and are added in a fixed order.
+// Contains barriers: every thread calls it.
+template <int NB>
+__device__ __forceinline__ void tr_update(double* ys, const double* xs, const double* M, int l0, int nl, int nrow,
+                                          int nc, double* ps) {
+  constexpr int G = TR_THREADS / NB;
+  const int row = threadIdx.x % NB, part = threadIdx.x / NB;
+  const int per = (nl + G - 1) / G;
+  const int la = part * per, lb = (la + per < nl) ? la + per : nl;
+  double acc[TR_COLS];
+#pragma unroll
+  for (int c = 0; c < TR_COLS; ++c) acc[c] = 0.0;
+  if (row < nrow) {
+    for (int l = la; l < lb; l += 16) {
+      double m[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) m[u] = (l + u < lb) ? M[static_cast<size_t>(l0 + l + u) * NB + row] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        if (l + u >= lb) break;
+#pragma unroll
+        for (int c = 0; c < TR_COLS; ++c)
+          if (c < nc) acc[c] += m[u] * xs[c * NB + l0 + l + u];
       }
-      __syncthreads();
-      if (tid < c) {
-        const double rc = R[c * nb + tid];
-        for (int h = 0; h < nc; ++h) y[h] -= rc * xs[h];
-      }
-      __syncthreads();
     }
-    if (tid < nb)
-      for (int h = 0; h < nc; ++h) Yk[(c0 + h) * ldy + tid] = y[h];
+  }
+#pragma unroll
+  for (int c = 0; c < TR_COLS; ++c)
+    if (c < nc) ps[(part * TR_COLS + c) * NB + row] = acc[c];
+  __syncthreads();
+  for (int e = threadIdx.x; e < TR_COLS * NB; e += TR_THREADS) {
+    const int c = e / NB, r = e % NB;
+    if (c < nc && r < nrow) {
+      double t = 0.0;
+      for (int g = 0; g < G; ++g) t += ps[(g * TR_COLS + c) * NB + r];
+      ys[c * NB + r] -= t;
+    }
   }
 }
 
-// Y_i -= R_ik X_k for every tile row i < k.  Grid: (k, nrhs); block: nb rows.
-__global__ __launch_bounds__(256) void trsm_update_kernel(const double* tiles, int p, int nb, int k, double* Y,
-                                                          int64_t ldy) {
-  const int i = blockIdx.x, h = blockIdx.y, row = threadIdx.x;
-  if (row >= nb) return;
-  const double* R = rtile(tiles, p, nb, i, k);
-  const double* xk = Y + h * ldy + static_cast<int64_t>(k) * nb;
-  double s = 0.0;
-  for (int c = 0; c < nb; ++c) s += R[c * nb + row] * xk[c];
-  Y[h * ldy + static_cast<int64_t>(i) * nb + row] -= s;
+template <int NB>
+__global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* tiles, int p, int q, double* Y,
+                                                               int64_t ldy, int nc, int32_t* flags, int32_t epoch,
+                                                               int64_t spin_ticks, int32_t* err) {
+  __shared__ double ys[NB * TR_COLS];
+  __shared__ double xs[NB * TR_COLS];
+  __shared__ double ps[TR_THREADS * TR_COLS];  // partial sums of tr_update
+  __shared__ int s_abort;
+  const int i = q - 1 - static_cast<int>(blockIdx.x);
+  const int tid = threadIdx.x;
+  const int64_t r0 = static_cast<int64_t>(i) * NB;
+  for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
+    const int c = e / NB, r = e % NB;
+    ys[e] = c < nc ? Y[c * ldy + r0 + r] : 0.0;
+  }
+  if (tid == 0) s_abort = 0;
+  __syncthreads();
+  for (int k = q - 1; k > i; --k) {
+    if (tid == 0) {
+      const uint64_t t0 = wall_clock64();
+      while (__hip_atomic_load(flags + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            static_cast<int64_t>(wall_clock64() - t0) > spin_ticks) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_abort = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_abort)) return;
+    const int64_t k0 = static_cast<int64_t>(k) * NB;
+    for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
+      const int c = e / NB, r = e % NB;
+      xs[e] = c < nc ? ld_coh(Y + c * ldy + k0 + r) : 0.0;
+    }
+    __syncthreads();
+    const double* R = tiles + (static_cast<size_t>(k) * p + i) * NB * NB;
+    tr_update<NB>(ys, xs, R, 0, NB, NB, nc, ps);
+    __syncthreads();
+  }
+  // Diagonal tile.
+  const double* R = tiles + (static_cast<size_t>(i) * p + i) * NB * NB;
+  const int lane = tid & 63, rr = lane & 31, half = lane >> 5;
+  for (int b = NB / 32 - 1; b >= 0; --b) {
+    const int base = 32 * b;
+    if (tid < 64) {
+      double ur[32];
+#pragma unroll
+      for (int l = 0; l < 32; ++l) ur[l] = R[static_cast<size_t>(base + l) * NB + base + rr];
+      double yv[TR_COLS / 2];
+#pragma unroll
+      for (int u = 0; u < TR_COLS / 2; ++u) yv[u] = ys[(half + 2 * u) * NB + base + rr];
+#pragma unroll
+      for (int st = 31; st >= 0; --st) {
+        if (rr == st) {
+#pragma unroll
+          for (int u = 0; u < TR_COLS / 2; ++u) yv[u] /= ur[st];
+        }
+#pragma unroll
+        for (int u = 0; u < TR_COLS / 2; ++u) {
+          if (2 * u >= nc) break;
+          const double x0 = readlane_d(yv[u], st), x1 = readlane_d(yv[u], st + 32);
+          if (rr < st) yv[u] -= ur[st] * (half ? x1 : x0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TR_COLS / 2; ++u) ys[(half + 2 * u) * NB + base + rr] = yv[u];
+    }
+    __syncthreads();
+    if (b > 0) {
+      tr_update<NB>(ys, ys, R, base, 32, base, nc, ps);
+      __syncthreads();
+    }
+  }
+  for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
+    const int c = e / NB, r = e % NB;
+    if (c < nc) st_coh(Y + c * ldy + r0 + r, ys[e]);
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (tid == 0) __hip_atomic_store(flags + i, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Rv = B - A X for m x n A; grid (row blocks, column chunks), partial sums
@@ -128,11 +238,18 @@ int grid_of(int64_t total) {
 }  // namespace
 
 hipError_t launch_trsm_upper(const double* tiles, int p, int q, int nb, double* Y, int64_t ldy, int64_t nrhs,
-                             hipStream_t s) {
-  for (int k = q - 1; k >= 0; --k) {
-    hipLaunchKernelGGL(trsm_diag_kernel, dim3(1), dim3(256), 0, s, tiles, p, nb, k, Y, ldy, nrhs);
-    if (k > 0) hipLaunchKernelGGL(trsm_update_kernel, dim3(k, static_cast<unsigned>(nrhs)), dim3(nb), 0, s, tiles, p,
-                                  nb, k, Y, ldy);
+                             int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks, hipStream_t s) {
+  for (int64_t c0 = 0; c0 < nrhs; c0 += TR_COLS) {
+    const int nc = static_cast<int>(nrhs - c0 < TR_COLS ? nrhs - c0 : TR_COLS);
+    const int32_t ep = ++*epoch;
+    double* Yc = Y + c0 * ldy;
+    switch (nb) {
+      case 32: hipLaunchKernelGGL(trsm_wave_kernel<32>, dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
+      case 64: hipLaunchKernelGGL(trsm_wave_kernel<64>, dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
+      case 128: hipLaunchKernelGGL(trsm_wave_kernel<128>, dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
+      case 256: hipLaunchKernelGGL(trsm_wave_kernel<256>, dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
+      default: return hipErrorInvalidValue;
+    }
   }
   return hipGetLastError();
 }
