@@ -184,12 +184,42 @@ int tiledqr_lstsq(const tqr_factors* F, const double* A0, int64_t lda,
 
 /* ---- batched ------------------------------------------------------------ */
 
-/* Factor nprob independent matrices in one persistent launch (all problems'
- * task graphs are concatenated and walked by one kernel).  opts, A, lda and
- * F are host arrays of length nprob; A[i] are device pointers.  Each F[i] is
- * an ordinary handle usable with every other entry point and released with
- * tiledqr_destroy.  All problems must share upd.
- * Errors: as tiledqr_factor for each problem. */
+/* Many independent factorizations in one persistent launch.  The task
+ * graphs of all problems (each built as for tiledqr_factor, Sec. 2.3) are
+ * merged into one dispatch order by the executor's priority, and one
+ * persistent kernel walks them; a problem's subtasks run on its own tiles.
+ * Tile sizes 32 and 64 may be mixed; all problems share upd.  The run (pack
+ * every problem into tiles, reset the executor, execute) is captured once
+ * as a HIP graph and replayed by every tiledqr_batch_run.
+ *
+ * tiledqr_batch_create: opts and lda are host arrays of nprob entries (lda
+ *   is the leading dimension each run will use).  Allocates every problem's
+ *   storage.  Errors: TQR_EINVAL (as tiledqr_factor per problem, differing
+ *   upd), TQR_EUNSUPPORTED (nb other than 32 or 64), TQR_ENOMEM, TQR_EHIP.
+ * tiledqr_batch_run: A is a host array of nprob device pointers (read by the
+ *   device when the run executes; the matrices must stay unchanged until
+ *   then).  Enqueued on stream.  Errors: TQR_EINVAL, TQR_EHIP.
+ * tiledqr_batch_sync: waits for the last run; TQR_EEXEC if its executor
+ *   stopped on a wait time limit.
+ * tiledqr_batch_time: milliseconds of the last run's graph (HIP events).
+ * tiledqr_batch_get: borrowed handle of problem i (valid until the batch is
+ *   destroyed; not to be passed to tiledqr_destroy), usable with
+ *   tiledqr_apply_q, tiledqr_get_r, tiledqr_lstsq and the other handle
+ *   entry points once the run is complete.
+ * tiledqr_batch_destroy: releases everything (NULL accepted). */
+typedef struct tqr_batch tqr_batch;
+int tiledqr_batch_create(int32_t nprob, const tqr_opts* opts, const int64_t* lda, tqr_batch** batch);
+int tiledqr_batch_run(tqr_batch* batch, const double* const* A, void* stream);
+int tiledqr_batch_sync(tqr_batch* batch);
+int tiledqr_batch_time(tqr_batch* batch, float* ms);
+int tiledqr_batch_get(tqr_batch* batch, int32_t i, tqr_factors** F);
+int tiledqr_batch_destroy(tqr_batch* batch);
+
+/* One-shot batched factorization: create a batch, run it once, wait, and
+ * hand each problem's handle to the caller in F[i] (an ordinary handle,
+ * released with tiledqr_destroy).  opts, A, lda and F are host arrays of
+ * nprob entries; A[i] are device pointers.  Synchronizes the stream.
+ * Errors: as tiledqr_batch_create / tiledqr_batch_run / tiledqr_batch_sync. */
 int tiledqr_factor_batched(int32_t nprob, const tqr_opts* opts,
                            const double* const* A, const int64_t* lda,
                            tqr_factors** F, void* stream);

@@ -42,16 +42,17 @@ def _ld(A):
 class Factors:
     """Owner of a tqr_factors handle."""
 
-    def __init__(self, handle, m, n, nb, opts):
+    def __init__(self, handle, m, n, nb, opts, owner=None):
         self.handle = handle
         self.m, self.n, self.nb = m, n, nb
         self.opts = opts
+        self.owner = owner  # a Batch that owns the handle (then not destroyed here)
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
+        if h and getattr(self, "owner", None) is None:
             _lib.tiledqr_destroy(h)
-            self.handle = None
+        self.handle = None
 
     def sync(self):
         check(_lib.tiledqr_sync(self.handle), "tiledqr_sync")
@@ -149,16 +150,74 @@ def factor(A, nb, tree=_lib.TREE_GREEDY, bs=1, kernels=_lib.KERN_DEFAULT, upd=_l
     return Factors(h, m, n, nb, opts)
 
 
+def _batch_opts(shapes, nbs, tree, bs, kernels, upd):
+    k = len(shapes)
+    opts = (_lib.Opts * k)()
+    for i, ((m, n), nb) in enumerate(zip(shapes, nbs)):
+        opts[i] = _lib.Opts(m, n, nb, 0, tree, bs, kernels, upd)
+    return opts
+
+
+class Batch:
+    """Many factorizations in one persistent launch, replayable as a HIP
+    graph (tiledqr_batch_*).  shapes: list of (m, n); nbs: tile sizes (32
+    or 64); lds: leading dimensions the runs will use (default m)."""
+
+    def __init__(self, shapes, nbs, tree=_lib.TREE_GREEDY, bs=1, kernels=_lib.KERN_DEFAULT, upd=_lib.UPD_F64,
+                 lds=None):
+        k = len(shapes)
+        self.shapes, self.nbs = list(shapes), list(nbs)
+        self.opts = _batch_opts(shapes, nbs, tree, bs, kernels, upd)
+        ldas = (ctypes.c_int64 * k)(*[(lds[i] if lds else shapes[i][0]) for i in range(k)])
+        self.lds = list(ldas)
+        h = ctypes.c_void_p()
+        self.handle = None
+        check(_lib.tiledqr_batch_create(k, self.opts, ldas, ctypes.byref(h)), "tiledqr_batch_create")
+        self.handle = h
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.tiledqr_batch_destroy(h)
+            self.handle = None
+
+    def run(self, mats):
+        """Enqueue one run on the current stream (mats: column-major float64
+        CUDA tensors of the batch's shapes and leading dimensions)."""
+        k = len(self.shapes)
+        ptrs = (ctypes.c_void_p * k)()
+        self._mats = mats  # keep alive until the run completes
+        for i, A in enumerate(mats):
+            if tuple(A.shape) != tuple(self.shapes[i]) or _ld(A) != self.lds[i] or A.stride(0) != 1:
+                raise ValueError("matrix %d does not match the batch layout" % i)
+            ptrs[i] = A.data_ptr()
+        check(_lib.tiledqr_batch_run(self.handle, ptrs, _stream()), "tiledqr_batch_run")
+
+    def sync(self):
+        check(_lib.tiledqr_batch_sync(self.handle), "tiledqr_batch_sync")
+
+    def time_ms(self):
+        ms = ctypes.c_float()
+        check(_lib.tiledqr_batch_time(self.handle, ctypes.byref(ms)), "tiledqr_batch_time")
+        return ms.value
+
+    def factors(self, i):
+        """Borrowed Factors of problem i (valid while the batch lives)."""
+        h = ctypes.c_void_p()
+        check(_lib.tiledqr_batch_get(self.handle, i, ctypes.byref(h)), "tiledqr_batch_get")
+        m, n = self.shapes[i]
+        return Factors(h, m, n, self.nbs[i], self.opts[i], owner=self)
+
+
 def factor_batched(mats, nbs, tree=_lib.TREE_GREEDY, bs=1, kernels=_lib.KERN_DEFAULT, upd=_lib.UPD_F64):
-    """Factor a list of matrices in one batched call; returns a list of
-    Factors."""
+    """Factor a list of matrices in one batched launch (tiledqr_factor_batched);
+    returns a list of independent Factors."""
     mats = [colmajor(A) for A in mats]
     k = len(mats)
-    opts = (_lib.Opts * k)()
+    opts = _batch_opts([tuple(A.shape) for A in mats], nbs, tree, bs, kernels, upd)
     ptrs = (ctypes.c_void_p * k)()
     ldas = (ctypes.c_int64 * k)()
-    for i, (A, nb) in enumerate(zip(mats, nbs)):
-        opts[i] = _lib.Opts(A.shape[0], A.shape[1], nb, 0, tree, bs, kernels, upd)
+    for i, A in enumerate(mats):
         ptrs[i] = A.data_ptr()
         ldas[i] = _ld(A)
     hs = (ctypes.c_void_p * k)()

@@ -183,6 +183,46 @@ struct tqr_factors {
   }
 };
 
+struct tqr_batch {
+  int32_t nprob = 0;
+  int32_t upd = 0;
+  std::vector<tqr_factors*> F;  // owned; entries handed out by tiledqr_factor_batched become null
+  std::vector<int64_t> lda;
+  DevPlan exec;
+  tqr::ProbDesc* prob = nullptr;
+  int32_t* prob_of = nullptr;
+  int64_t* tile_start = nullptr;
+  int64_t* lda_dev = nullptr;
+  double** aptr_dev = nullptr;
+  double** aptr_host = nullptr;  // pinned staging of the A pointers
+  int32_t* ctl = nullptr;        // ticket, err, epoch
+  int64_t ntiles = 0;
+  int grid = 1;
+  hipStream_t cap = nullptr;
+  hipStream_t stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  bool ran = false;
+
+  ~tqr_batch() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (ev0) (void)hipEventDestroy(ev0);
+    if (ev1) (void)hipEventDestroy(ev1);
+    exec.release();
+    if (prob) (void)hipFree(prob);
+    if (prob_of) (void)hipFree(prob_of);
+    if (tile_start) (void)hipFree(tile_start);
+    if (lda_dev) (void)hipFree(lda_dev);
+    if (aptr_dev) (void)hipFree(aptr_dev);
+    if (aptr_host) (void)hipHostFree(aptr_host);
+    if (ctl) (void)hipFree(ctl);
+    for (tqr_factors* f : F) delete f;
+  }
+};
+
 namespace {
 
 ExecArgs base_args(const tqr_factors* F, const DevPlan& d) {
@@ -253,7 +293,7 @@ int check_opts(const tqr_opts* o, int64_t lda) {
   return TQR_OK;
 }
 
-int create(const tqr_opts* o, tqr_factors** out) {
+int create(const tqr_opts* o, tqr_factors** out, ExecPlan* keep = nullptr) {
   std::unique_ptr<tqr_factors> F(new (std::nothrow) tqr_factors());
   if (!F) return TQR_ENOMEM;
   F->o = *o;
@@ -269,6 +309,7 @@ int create(const tqr_opts* o, tqr_factors** out) {
   tqr::make_exec_plan(F->plan, nslab, exec_order(), w, ex);
   int st = upload(ex, F->exec);
   if (st != TQR_OK) return st;
+  if (keep) *keep = ex;
   const size_t ntile = static_cast<size_t>(F->p) * F->q;
   const size_t nbb = static_cast<size_t>(F->nb);
   if (!hip_ok(hipMalloc(&F->tiles, ntile * nbb * nbb * sizeof(double))) ||
@@ -623,26 +664,189 @@ int tiledqr_lstsq(const tqr_factors* F, const double* A0, int64_t lda, const dou
   return fail(conv ? TQR_OK : TQR_ENOTCONV);
 }
 
+int tiledqr_batch_create(int32_t nprob, const tqr_opts* opts, const int64_t* lda, tqr_batch** out) {
+  if (!out || nprob < 1 || !opts || !lda) return TQR_EINVAL;
+  *out = nullptr;
+  for (int32_t i = 0; i < nprob; ++i) {
+    const int st = check_opts(opts + i, lda[i]);
+    if (st != TQR_OK) return st;
+    if (opts[i].nb != 32 && opts[i].nb != 64) return TQR_EUNSUPPORTED;
+    if (opts[i].upd != opts[0].upd) return TQR_EINVAL;
+  }
+  std::unique_ptr<tqr_batch> b(new (std::nothrow) tqr_batch());
+  if (!b) return TQR_ENOMEM;
+  b->nprob = nprob;
+  b->upd = opts[0].upd;
+  b->lda.assign(lda, lda + nprob);
+  // Per-problem handles (tile storage, T factors, apply plans) and their
+  // executor plans, merged into one priority order.  Within a problem a
+  // predecessor has a strictly smaller key than its successors (positive
+  // weights), so the merged order keeps every dependency pointing backwards.
+  std::vector<ExecPlan> plans(nprob);
+  std::vector<tqr::ProbDesc> desc(nprob);
+  std::vector<int64_t> tile_start(nprob + 1, 0);
+  size_t total = 0;
+  for (int32_t i = 0; i < nprob; ++i) {
+    tqr_factors* F = nullptr;
+    const int st = create(opts + i, &F, &plans[i]);
+    if (st != TQR_OK) return st;
+    b->F.push_back(F);
+    desc[i] = tqr::ProbDesc{F->tiles, F->Tg, F->Tp, F->p, F->q, F->nb, 0};
+    tile_start[i + 1] = tile_start[i] + static_cast<int64_t>(F->p) * F->q;
+    total += plans[i].sub.size();
+  }
+  if (total >= static_cast<size_t>(INT32_MAX)) return TQR_EUNSUPPORTED;
+  std::vector<std::pair<int32_t, int32_t>> order;  // (problem, local index)
+  order.reserve(total);
+  for (int32_t i = 0; i < nprob; ++i)
+    for (int32_t r = 0; r < static_cast<int32_t>(plans[i].sub.size()); ++r) order.emplace_back(i, r);
+  std::stable_sort(order.begin(), order.end(), [&](const std::pair<int32_t, int32_t>& x,
+                                                   const std::pair<int32_t, int32_t>& y) {
+    const double kx = plans[x.first].key[x.second], ky = plans[y.first].key[y.second];
+    if (kx != ky) return kx < ky;
+    if (x.first != y.first) return x.first < y.first;
+    return x.second < y.second;
+  });
+  std::vector<std::vector<int32_t>> gpos(nprob);
+  for (int32_t i = 0; i < nprob; ++i) gpos[i].resize(plans[i].sub.size());
+  for (size_t g = 0; g < order.size(); ++g) gpos[order[g].first][order[g].second] = static_cast<int32_t>(g);
+  ExecPlan merged;
+  std::vector<int32_t> prob_of(total);
+  merged.sub.resize(total);
+  for (size_t g = 0; g < order.size(); ++g) {
+    const int32_t i = order[g].first, r = order[g].second;
+    tqr::SubTask st = plans[i].sub[r];
+    st.dep_begin = static_cast<int32_t>(merged.deps.size());
+    for (int32_t e = plans[i].sub[r].dep_begin; e < plans[i].sub[r].dep_end; ++e)
+      merged.deps.push_back(gpos[i][plans[i].deps[e]]);
+    st.dep_end = static_cast<int32_t>(merged.deps.size());
+    merged.sub[g] = st;
+    prob_of[g] = i;
+  }
+  int st = upload(merged, b->exec);
+  if (st != TQR_OK) return st;
+  b->ntiles = tile_start[nprob];
+  if (!hip_ok(hipMalloc(&b->prob, nprob * sizeof(tqr::ProbDesc))) ||
+      !hip_ok(hipMalloc(&b->prob_of, std::max<size_t>(1, total) * sizeof(int32_t))) ||
+      !hip_ok(hipMalloc(&b->tile_start, (nprob + 1) * sizeof(int64_t))) ||
+      !hip_ok(hipMalloc(&b->lda_dev, nprob * sizeof(int64_t))) ||
+      !hip_ok(hipMalloc(&b->aptr_dev, nprob * sizeof(double*))) ||
+      !hip_ok(hipMalloc(&b->ctl, 3 * sizeof(int32_t))) ||
+      !hip_ok(hipHostMalloc(&b->aptr_host, nprob * sizeof(double*))))
+    return TQR_ENOMEM;
+  HIP_TRY(hipMemcpy(b->prob, desc.data(), nprob * sizeof(tqr::ProbDesc), hipMemcpyHostToDevice));
+  if (total) HIP_TRY(hipMemcpy(b->prob_of, prob_of.data(), total * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->tile_start, tile_start.data(), (nprob + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(b->lda_dev, lda, nprob * sizeof(int64_t), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(b->ctl, 0, 3 * sizeof(int32_t)));
+  HIP_TRY(hipMemset(b->aptr_dev, 0, nprob * sizeof(double*)));
+  b->grid = device_cus() * tqr::batched_occupancy(b->upd);
+  // The whole run (pack every problem, reset the executor, execute) as one
+  // captured graph; the A pointers are read from device memory, so the same
+  // graph serves every run.
+  HIP_TRY(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  tqr::BatchArgs a{};
+  a.prob = b->prob;
+  a.prob_of = b->prob_of;
+  a.sub = b->exec.sub;
+  a.deps = b->exec.deps;
+  a.flags = b->exec.flags;
+  a.ctl = b->ctl;
+  a.nsub = b->exec.nsub;
+  a.upd = b->upd;
+  a.spin_ticks = 4 * wall_ticks_per_second();
+  HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e1 = tqr::launch_pack_batched(b->aptr_dev, b->lda_dev, b->prob, b->tile_start, nprob, b->ntiles, 64,
+                                           b->cap);
+  hipError_t e2 = tqr::launch_batch_reset(b->ctl, b->cap);
+  hipError_t e3 = (b->exec.nsub > 0) ? tqr::launch_batched(a, b->grid, b->cap) : hipSuccess;
+  hipGraph_t g = nullptr;
+  hipError_t e4 = hipStreamEndCapture(b->cap, &g);
+  if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    g_last_hip = static_cast<int>((e1 != hipSuccess) ? e1 : (e2 != hipSuccess) ? e2 : (e3 != hipSuccess) ? e3 : e4);
+    return TQR_EHIP;
+  }
+  b->graph = g;
+  HIP_TRY(hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0));
+  HIP_TRY(hipEventCreate(&b->ev0));
+  HIP_TRY(hipEventCreate(&b->ev1));
+  *out = b.release();
+  return TQR_OK;
+}
+
+int tiledqr_batch_run(tqr_batch* b, const double* const* A, void* stream) {
+  if (!b || !A) return TQR_EINVAL;
+  for (int32_t i = 0; i < b->nprob; ++i)
+    if (!A[i]) return TQR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // The pinned staging copy is reused: wait for the previous run's copy.
+  if (b->ran) HIP_TRY(hipEventSynchronize(b->ev0));
+  std::memcpy(b->aptr_host, A, b->nprob * sizeof(double*));
+  HIP_TRY(hipMemcpyAsync(b->aptr_dev, b->aptr_host, b->nprob * sizeof(double*), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(b->ev0, s));
+  HIP_TRY(hipGraphLaunch(b->gexec, s));
+  HIP_TRY(hipEventRecord(b->ev1, s));
+  for (tqr_factors* F : b->F) {
+    F->stream = s;
+    F->timed = false;
+  }
+  b->stream = s;
+  b->ran = true;
+  return TQR_OK;
+}
+
+int tiledqr_batch_sync(tqr_batch* b) {
+  if (!b) return TQR_EINVAL;
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  int32_t err = 0;
+  HIP_TRY(hipMemcpy(&err, b->ctl + 1, sizeof(int32_t), hipMemcpyDeviceToHost));
+  return err ? TQR_EEXEC : TQR_OK;
+}
+
+int tiledqr_batch_time(tqr_batch* b, float* ms) {
+  if (!b || !ms || !b->ran) return TQR_EINVAL;
+  HIP_TRY(hipEventSynchronize(b->ev1));
+  HIP_TRY(hipEventElapsedTime(ms, b->ev0, b->ev1));
+  return TQR_OK;
+}
+
+int tiledqr_batch_get(tqr_batch* b, int32_t i, tqr_factors** F) {
+  if (!b || !F || i < 0 || i >= b->nprob || !b->F[i]) return TQR_EINVAL;
+  *F = b->F[i];
+  return TQR_OK;
+}
+
+int tiledqr_batch_destroy(tqr_batch* b) {
+  if (!b) return TQR_OK;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  delete b;
+  return TQR_OK;
+}
+
 int tiledqr_factor_batched(int32_t nprob, const tqr_opts* opts, const double* const* A, const int64_t* lda,
                            tqr_factors** F, void* stream) {
   if (nprob < 0 || (nprob > 0 && (!opts || !A || !lda || !F))) return TQR_EINVAL;
-  for (int32_t i = 0; i < nprob; ++i) {
+  if (nprob == 0) return TQR_OK;
+  for (int32_t i = 0; i < nprob; ++i)
     if (!A[i]) return TQR_EINVAL;
-    const int st = check_opts(opts + i, lda[i]);
-    if (st != TQR_OK) return st;
+  tqr_batch* b = nullptr;
+  int st = tiledqr_batch_create(nprob, opts, lda, &b);
+  if (st != TQR_OK) {
+    tiledqr_batch_destroy(b);
+    return st;
   }
-  // Placeholder path: one handle per problem, factored back to back.
-  for (int32_t i = 0; i < nprob; ++i) {
-    const int st = tiledqr_factor(opts + i, A[i], lda[i], F + i, stream);
-    if (st != TQR_OK) {
-      for (int32_t j = 0; j < i; ++j) {
-        tiledqr_destroy(F[j]);
-        F[j] = nullptr;
-      }
-      return st;
+  st = tiledqr_batch_run(b, A, stream);
+  if (st == TQR_OK) st = tiledqr_batch_sync(b);
+  if (st == TQR_OK) {
+    // Hand the problems' handles to the caller.
+    for (int32_t i = 0; i < nprob; ++i) {
+      F[i] = b->F[i];
+      b->F[i] = nullptr;
     }
   }
-  return TQR_OK;
+  tiledqr_batch_destroy(b);
+  return st;
 }
 
 }  // extern "C"

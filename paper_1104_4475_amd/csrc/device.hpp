@@ -44,6 +44,30 @@ struct ExecArgs {
   int32_t debug;        // diagnostics: bit 0 = clear the workgroup's LDS before each task
 };
 
+// One problem of a batched launch: its tile storage and shape.
+struct ProbDesc {
+  double* tiles;
+  double* Tg;
+  double* Tp;
+  int32_t p, q, nb, pad;
+};
+
+// Batched executor: the subtasks of all problems in one priority order;
+// prob_of[t] names the problem of subtask t.  ctl holds the ticket, the
+// error word and the epoch, which the reset kernel advances before every
+// run (so a captured graph can be replayed).
+struct BatchArgs {
+  const ProbDesc* prob;
+  const int32_t* prob_of;
+  const DevSub* sub;
+  const int32_t* deps;
+  int32_t* flags;
+  int32_t* ctl;         // [0] ticket, [1] err, [2] epoch
+  int32_t nsub;
+  int32_t upd;
+  int64_t spin_ticks;
+};
+
 // Kernel launchers (defined in kernels.hip).
 hipError_t launch_persistent(const ExecArgs& a, int grid, hipStream_t s);
 hipError_t launch_level(const ExecArgs& a, const int32_t* order, int begin, int count, hipStream_t s);
@@ -67,5 +91,13 @@ hipError_t launch_colnorms2(const double* M, int64_t ld, int64_t rows, int64_t c
 hipError_t launch_axpy_cols(double* X, int64_t ldx, const double* D, int64_t ldd, int64_t rows, int64_t cols,
                             hipStream_t s);
 int persistent_occupancy(int nb, int upd);
+hipError_t launch_batch_reset(int32_t* ctl, hipStream_t s);
+hipError_t launch_batched(const BatchArgs& b, int grid, hipStream_t s);
+int batched_occupancy(int upd);
+// All problems' column-major A (device pointer array Aptr, leading
+// dimensions lda) into their tiles; tile_start[i] is the first global tile
+// of problem i (nprob + 1 entries).
+hipError_t launch_pack_batched(const double* const* Aptr, const int64_t* lda, const ProbDesc* prob,
+                               const int64_t* tile_start, int nprob, int64_t ntiles, int nbmax, hipStream_t s);
 
 }  // namespace tqr

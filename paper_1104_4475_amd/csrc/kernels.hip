@@ -1043,15 +1043,27 @@ __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, doub
 
 // ---- executors ---------------------------------------------------------------
 
-// Persistent executor: workgroups take subtasks in dispatch order from an
-// atomic ticket and wait for their predecessors' flags.  Every predecessor
-// has a smaller index and was taken by a workgroup that is already running,
-// so the smallest unfinished subtask can always proceed (no residency
-// assumption).  A wait longer than spin_ticks sets *err, and every
-// workgroup then leaves at its next wait or ticket.
-template <int NB, int P>
-__global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
-  __shared__ double sm[Smem<NB>::TOTAL];
+// Ticket loop of the persistent executors: workgroups take subtasks in
+// dispatch order from an atomic ticket and wait for their predecessors'
+// flags.  Every predecessor has a smaller index and was taken by a
+// workgroup that is already running, so the smallest unfinished subtask can
+// always proceed (no residency assumption).  A wait longer than spin_ticks
+// sets *err, and every workgroup then leaves at its next wait or ticket.
+// run(t) executes subtask t with the whole workgroup.
+struct LoopCtl {
+  const DevSub* sub;
+  const int32_t* deps;
+  int32_t* flags;
+  int32_t* ticket;
+  int32_t* err;
+  int32_t nsub;
+  int32_t epoch;
+  int64_t spin_ticks;
+  int64_t* trace;
+};
+
+template <class Run>
+__device__ __forceinline__ void exec_loop(const LoopCtl& c, Run run) {
   __shared__ int s_t;
   // Every branch that encloses or follows a barrier is on a wave-uniform
   // (scalar) value, so the compiler keeps the loop structured: wave 0 takes
@@ -1061,29 +1073,29 @@ __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
   const int wave = wave_id();
   for (;;) {
     if (wave == 0) {
-      int t = a.nsub;
+      int t = c.nsub;
       const int err0 = __builtin_amdgcn_readfirstlane(
-          __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+          __hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
       if (err0 == 0) {
         int tk = 0;
-        if (lane == 0) tk = atomicAdd(a.ticket, 1);
+        if (lane == 0) tk = atomicAdd(c.ticket, 1);
         t = __builtin_amdgcn_readfirstlane(tk);
       }
-      if (t < a.nsub) {
-        const int db = a.sub[t].dep_begin, de = a.sub[t].dep_end;
+      if (t < c.nsub) {
+        const int db = c.sub[t].dep_begin, de = c.sub[t].dep_end;
         const uint64_t t0 = wall_clock64();
-        if (a.trace && lane == 0) a.trace[4 * static_cast<int64_t>(t)] = static_cast<int64_t>(t0);
-        for (int e = db; e < de && t < a.nsub; ++e) {
-          int32_t* f = a.flags + a.deps[e];
+        if (c.trace && lane == 0) c.trace[4 * static_cast<int64_t>(t)] = static_cast<int64_t>(t0);
+        for (int e = db; e < de && t < c.nsub; ++e) {
+          int32_t* f = c.flags + c.deps[e];
           for (;;) {
             const int v = __builtin_amdgcn_readfirstlane(
                 __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            if (v == a.epoch) break;
+            if (v == c.epoch) break;
             const int err = __builtin_amdgcn_readfirstlane(
-                __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            if (err != 0 || static_cast<int64_t>(wall_clock64() - t0) > a.spin_ticks) {
-              if (lane == 0) __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              t = a.nsub;
+                __hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (err != 0 || static_cast<int64_t>(wall_clock64() - t0) > c.spin_ticks) {
+              if (lane == 0) __hip_atomic_store(c.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              t = c.nsub;
               break;
             }
             __builtin_amdgcn_s_sleep(1);
@@ -1096,25 +1108,92 @@ __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
     // The ticket is the same for every thread; readfirstlane makes that
     // visible to the compiler (scalar loop exit and task dispatch).
     const int t = __builtin_amdgcn_readfirstlane(s_t);
-    if (t >= a.nsub) break;
-    if (a.trace && threadIdx.x == 0) a.trace[4 * static_cast<int64_t>(t) + 1] = static_cast<int64_t>(wall_clock64());
-    if (a.debug & 1) {
-      for (int e = threadIdx.x; e < Smem<NB>::TOTAL; e += NTHREADS) sm[e] = 0.0;
-      __syncthreads();
-    }
-    run_sub<NB, P>(a, a.sub[t], sm);
+    if (t >= c.nsub) break;
+    if (c.trace && threadIdx.x == 0) c.trace[4 * static_cast<int64_t>(t) + 1] = static_cast<int64_t>(wall_clock64());
+    run(t);
     // Every data store of the task is device-coherent: once each wave has
     // seen its stores complete the flag can be published.
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (wave == 0 && lane == 0) {
-      __hip_atomic_store(a.flags + t, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (a.trace) {
-        a.trace[4 * static_cast<int64_t>(t) + 2] = static_cast<int64_t>(wall_clock64());
-        a.trace[4 * static_cast<int64_t>(t) + 3] = blockIdx.x;
+      __hip_atomic_store(c.flags + t, c.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (c.trace) {
+        c.trace[4 * static_cast<int64_t>(t) + 2] = static_cast<int64_t>(wall_clock64());
+        c.trace[4 * static_cast<int64_t>(t) + 3] = blockIdx.x;
       }
     }
   }
+}
+
+template <int NB, int P>
+__global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
+  __shared__ double sm[Smem<NB>::TOTAL];
+  const LoopCtl c{a.sub, a.deps, a.flags, a.ticket, a.err, a.nsub, a.epoch, a.spin_ticks, a.trace};
+  exec_loop(c, [&](int t) {
+    if (a.debug & 1) {
+      for (int e = threadIdx.x; e < Smem<NB>::TOTAL; e += NTHREADS) sm[e] = 0.0;
+      __syncthreads();
+    }
+    run_sub<NB, P>(a, a.sub[t], sm);
+  });
+}
+
+// Batched executor: subtasks of many problems (tile sizes 32 or 64) in one
+// launch; each subtask runs on its problem's tiles.
+template <int P>
+__global__ __launch_bounds__(NTHREADS) void exec_batched(BatchArgs b) {
+  __shared__ double sm[Smem<64>::TOTAL];
+  const int epoch = __builtin_amdgcn_readfirstlane(
+      __hip_atomic_load(b.ctl + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  const LoopCtl c{b.sub, b.deps, b.flags, b.ctl, b.ctl + 1, b.nsub, epoch, b.spin_ticks, nullptr};
+  exec_loop(c, [&](int t) {
+    const ProbDesc& pd = b.prob[__builtin_amdgcn_readfirstlane(b.prob_of[t])];
+    ExecArgs a{};
+    a.tiles = pd.tiles;
+    a.Tg = pd.Tg;
+    a.Tp = pd.Tp;
+    a.p = __builtin_amdgcn_readfirstlane(pd.p);
+    a.q = __builtin_amdgcn_readfirstlane(pd.q);
+    a.nb = __builtin_amdgcn_readfirstlane(pd.nb);
+    a.upd = P;
+    if (a.nb == 32)
+      run_sub<32, P>(a, b.sub[t], sm);
+    else
+      run_sub<64, P>(a, b.sub[t], sm);
+  });
+}
+
+__global__ void batch_reset_kernel(int32_t* ctl) {
+  ctl[0] = 0;
+  ctl[1] = 0;
+  ctl[2] = ctl[2] + 1;
+}
+
+hipError_t launch_batch_reset(int32_t* ctl, hipStream_t s) {
+  hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, s, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_batched(const BatchArgs& b, int grid, hipStream_t s) {
+  switch (b.upd) {
+    case P_F64: hipLaunchKernelGGL((exec_batched<P_F64>), dim3(grid), dim3(NTHREADS), 0, s, b); break;
+    case P_F32: hipLaunchKernelGGL((exec_batched<P_F32>), dim3(grid), dim3(NTHREADS), 0, s, b); break;
+    case P_BF16: hipLaunchKernelGGL((exec_batched<P_BF16>), dim3(grid), dim3(NTHREADS), 0, s, b); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+int batched_occupancy(int upd) {
+  int blocks = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (upd) {
+    case P_F64: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, exec_batched<P_F64>, NTHREADS, 0); break;
+    case P_F32: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, exec_batched<P_F32>, NTHREADS, 0); break;
+    case P_BF16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, exec_batched<P_BF16>, NTHREADS, 0); break;
+    default: break;
+  }
+  return (e == hipSuccess && blocks > 0) ? blocks : 1;
 }
 
 // Level-synchronous executor: one launch per DAG depth level, one subtask

@@ -19,6 +19,32 @@ __global__ void pack_kernel(const double* A, int64_t lda, double* tiles, int p, 
   }
 }
 
+// Batched pack: block g copies global tile g (problem found by binary
+// search in tile_start) from its problem's column-major A.
+__global__ __launch_bounds__(256) void pack_batched_kernel(const double* const* Aptr, const int64_t* lda,
+                                                           const ProbDesc* prob, const int64_t* tile_start, int nprob) {
+  const int64_t g = blockIdx.x;
+  int lo = 0, hi = nprob - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (tile_start[mid] <= g)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  const ProbDesc& pd = prob[lo];
+  const int64_t t = g - tile_start[lo];
+  const int64_t r = t % pd.p, c = t / pd.p;
+  const int nb = pd.nb;
+  const double* A = Aptr[lo];
+  const int64_t ld = lda[lo];
+  double* dst = pd.tiles + (c * pd.p + r) * nb * nb;
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    const int cc = e / nb, rr = e - cc * nb;
+    dst[e] = A[(c * nb + cc) * ld + r * nb + rr];
+  }
+}
+
 // tiles -> column-major out (ld) for rows x cols (upper_only: zero below the
 // diagonal, used for R).
 __global__ void unpack_kernel(const double* tiles, double* out, int64_t ld, int p, int nb, int64_t rows, int64_t cols,
@@ -103,6 +129,15 @@ hipError_t launch_unpack_b(const double* Bt, double* B, int64_t ldb, int64_t nrh
                            hipStream_t s) {
   hipLaunchKernelGGL(unpack_b_kernel, dim3(grid_for(static_cast<int64_t>(rows) * nrhs)), dim3(256), 0, s, Bt, B, ldb,
                      nrhs, static_cast<int64_t>(rows), nb, ncolB);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_batched(const double* const* Aptr, const int64_t* lda, const ProbDesc* prob,
+                               const int64_t* tile_start, int nprob, int64_t ntiles, int nbmax, hipStream_t s) {
+  if (ntiles <= 0) return hipSuccess;
+  (void)nbmax;
+  hipLaunchKernelGGL(pack_batched_kernel, dim3(static_cast<unsigned>(ntiles)), dim3(256), 0, s, Aptr, lda, prob,
+                     tile_start, nprob);
   return hipGetLastError();
 }
 

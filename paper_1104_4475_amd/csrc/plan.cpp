@@ -373,6 +373,8 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
 
   ex.sub.resize(n);
   ex.deps.clear();
+  ex.key.resize(n);
+  for (size_t r = 0; r < n; ++r) ex.key[r] = key[perm[r]];
   for (size_t r = 0; r < n; ++r) {
     const int32_t s = perm[r];
     SubTask st = sub[s];

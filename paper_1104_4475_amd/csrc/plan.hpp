@@ -47,10 +47,12 @@ struct ExecPlan {
   std::vector<int32_t> deps;
   std::vector<int32_t> level_ptr;    // subtasks grouped by DAG depth
   std::vector<int32_t> level_order;  // indices into sub, level by level
+  std::vector<double> key;           // priority key of each subtask (ascending = earlier)
   int32_t nslab = 1;
 };
 
-// order: 0 = ascending ASAP start time, 1 = ascending ALAP start time.
+// order: 0 = ascending ASAP start time, 1 = ascending ALAP start time,
+// 2 = descending bottom level (longest remaining path).
 // w: per-kind weights used for the priority (any positive values).
 void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex);
 

@@ -60,3 +60,20 @@ def test_other_entry_points_reject_null_handles():
     assert _lib.tiledqr_lstsq(None, None, 1, None, 1, 1, None, 1, None, None, None) == tqr.TQR_EINVAL
     assert _lib.tiledqr_get_r(None, None, 1, None) == tqr.TQR_EINVAL
     assert _lib.tiledqr_destroy(None) == tqr.TQR_OK
+
+
+def test_batch_create_rejects_bad_options_before_allocating():
+    b = ctypes.c_void_p()
+    ok = _lib.Opts(256, 64, 32, 0, 4, 1, 0, 0)
+    big = _lib.Opts(512, 256, 128, 0, 4, 1, 0, 0)   # nb 128: not a batched tile size
+    f32 = _lib.Opts(256, 64, 32, 0, 4, 1, 0, 1)     # upd differs from problem 0
+    bad = _lib.Opts(250, 64, 32, 0, 4, 1, 0, 0)     # m % nb
+    two = lambda a, c: (_lib.Opts * 2)(a, c)  # noqa: E731
+    ld2 = (ctypes.c_int64 * 2)(512, 512)
+    assert _lib.tiledqr_batch_create(0, two(ok, ok), ld2, ctypes.byref(b)) == tqr.TQR_EINVAL
+    assert _lib.tiledqr_batch_create(2, two(ok, big), ld2, ctypes.byref(b)) == tqr.TQR_EUNSUPPORTED
+    assert _lib.tiledqr_batch_create(2, two(ok, f32), ld2, ctypes.byref(b)) == tqr.TQR_EINVAL
+    assert _lib.tiledqr_batch_create(2, two(ok, bad), ld2, ctypes.byref(b)) == tqr.TQR_EINVAL
+    assert _lib.tiledqr_batch_create(2, two(ok, ok), (ctypes.c_int64 * 2)(512, 100), ctypes.byref(b)) == tqr.TQR_EINVAL
+    assert _lib.tiledqr_batch_run(None, None, None) == tqr.TQR_EINVAL
+    assert _lib.tiledqr_batch_destroy(None) == tqr.TQR_OK
