@@ -224,6 +224,42 @@ int tiledqr_factor_batched(int32_t nprob, const tqr_opts* opts,
                            const double* const* A, const int64_t* lda,
                            tqr_factors** F, void* stream);
 
+/* ---- makespan model of the tree / tile-size selector ---------------------- */
+
+/* The paper chooses PlasmaTree's domain size by exhaustive search over
+ * measured runs (Sec. 4); the library adds a learned model of the makespan
+ * so that a tree, domain size and tile size can be picked without timing
+ * every candidate.  The model is a multilayer perceptron 13 -> 64 -> 64 -> 1
+ * (ReLU hidden units) mapping a candidate's features to log(makespan),
+ * trained with mean squared error and Adam, all in FP32 on the GPU.
+ *
+ * Features (13 floats per sample): log2 p, log2 q, log2 nb; one-hot of the
+ * algorithm (TS-FlatTree, TT-FlatTree, BinaryTree, Fibonacci, Greedy,
+ * PlasmaTree); log2 BS for PlasmaTree, else 0; one-hot of the update
+ * precision (FP64, FP32, BF16).
+ *
+ * Parameters: one FP32 array of tiledqr_mlp_nparam() = 5121 floats,
+ * row-major, y = relu(relu(x W1 + b1) W2 + b2) W3 + b3 with W1 [13][64] at
+ * 0, b1 at 832, W2 [64][64] at 896, b2 at 4992, W3 [64] at 5056, b3 at 5120.
+ * All arrays are device memory; calls are enqueued on stream.
+ *
+ * tiledqr_mlp_forward: y[i] = model(X[13 i .. 13 i + 12]) for i < n.
+ * tiledqr_mlp_loss_grad: *loss = mean_i (y_i - t_i)^2 and grad (nparam
+ *   floats) its gradient; loss may be NULL.  Deterministic (fixed reduction
+ *   order).  Allocates a stream-ordered workspace of about 20 KB per 64
+ *   samples.
+ * tiledqr_mlp_adam: one Adam step (Kingma and Ba, with bias correction; step
+ *   counts from 1): m <- b1 m + (1-b1) g, v <- b2 v + (1-b2) g^2,
+ *   params -= lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).
+ * Errors: TQR_EINVAL (null pointers, n < 0, bad hyper-parameters),
+ *   TQR_ENOMEM, TQR_EHIP. */
+int tiledqr_mlp_nparam(void);
+int tiledqr_mlp_forward(const float* params, const float* X, int64_t n, float* y, void* stream);
+int tiledqr_mlp_loss_grad(const float* params, const float* X, const float* t, int64_t n,
+                          float* grad, float* loss, void* stream);
+int tiledqr_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t nparam,
+                     float lr, float beta1, float beta2, float eps, int32_t step, void* stream);
+
 /* ---- host-only planning (no GPU needed) -------------------------------- */
 
 /* Elimination list of a tree (Sec. 3): triples (i, piv, k), 1-based, in the

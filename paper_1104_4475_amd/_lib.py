@@ -76,6 +76,11 @@ _sigs = {
     "tiledqr_batch_time": (ctypes.c_int, [_vp, _P(ctypes.c_float)]),
     "tiledqr_batch_get": (ctypes.c_int, [_vp, _i32, _P(_vp)]),
     "tiledqr_batch_destroy": (ctypes.c_int, [_vp]),
+    "tiledqr_mlp_nparam": (ctypes.c_int, []),
+    "tiledqr_mlp_forward": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp]),
+    "tiledqr_mlp_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "tiledqr_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                        ctypes.c_float, _i32, _vp]),
     "tiledqr_elim_list": (ctypes.c_int, [_i32, _i32, _i32, _i32, _P(_i32), _P(_i64)]),
     "tiledqr_schedule": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32, _P(_i32), _P(_i64), _P(_i64)]),
     "tiledqr_task_preds": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32, _P(_i64), _P(_i32)]),

@@ -61,10 +61,11 @@ __device__ __forceinline__ void tr_update(double* ys, const double* xs, const do
       for (int u = 0; u < 16; ++u) m[u] = (l + u < lb) ? M[static_cast<size_t>(l0 + l + u) * NB + row] : 0.0;
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
-        if (l + u >= lb) break;
+        if (l + u < lb) {
 #pragma unroll
-        for (int c = 0; c < TR_COLS; ++c)
-          if (c < nc) acc[c] += m[u] * xs[c * NB + l0 + l + u];
+          for (int c = 0; c < TR_COLS; ++c)
+            if (c < nc) acc[c] += m[u] * xs[c * NB + l0 + l + u];
+        }
       }
     }
   }
