@@ -65,6 +65,22 @@ __device__ __forceinline__ double gld(const double* p) {
 __device__ __forceinline__ void gst(double* p, double v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+
+// 16-byte device-coherent accesses through a buffer resource (the base
+// pointer is wave-uniform, the byte offset per lane): buffer loads and
+// stores with the sc1 cache policy, as the scalar accesses above.
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+constexpr int CPOL_SC1 = 16;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const double* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(base), 0, bytes, 0x00020000);
+}
+__device__ __forceinline__ d2 gld2(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(d2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, CPOL_SC1));
+}
+__device__ __forceinline__ void gst2(__amdgpu_buffer_rsrc_t r, int off, d2 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, off, 0, CPOL_SC1);
+}
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 __device__ __forceinline__ double uniform_d(double v) {
@@ -402,9 +418,13 @@ __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const dou
 // (BF16 via FP32), products accumulate in FP32, and each correction is
 // subtracted from the FP64 C.  The T-apply (W' = T^T W, 1/16 of the flops)
 // runs in FP32 in both modes.
+// Cg: first column of the wave's 16-column group (wave-uniform); lane
+// (g, n) moves rows 16 rb + 4 g .. 16 rb + 4 g + 3 of column n as two
+// 16-byte accesses.
 template <int NB>
-__device__ __forceinline__ void load_cols_lp(d4 (&acc)[NB / 32], const double* C, int lo, int hi) {
-  const int lane = lane_id(), g = lane >> 4, h = wave_id() >> 2;
+__device__ __forceinline__ void load_cols_lp(d4 (&acc)[NB / 32], const double* Cg, int lo, int hi) {
+  const int lane = lane_id(), g = lane >> 4, n = lane & 15, h = wave_id() >> 2;
+  const auto r = rsrc(Cg, 16 * NB * 8);
 #pragma unroll
   for (int j = 0; j < NB / 32; ++j) {
     const int rb = 2 * j + h;
@@ -412,19 +432,22 @@ __device__ __forceinline__ void load_cols_lp(d4 (&acc)[NB / 32], const double* C
       acc[j] = zero4();
       continue;
     }
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[j][r] = gld(C + rb * 16 + 4 * g + r);
+    const int off = (n * NB + rb * 16 + 4 * g) * 8;
+    const d2 a = gld2(r, off), b = gld2(r, off + 16);
+    acc[j] = d4{a[0], a[1], b[0], b[1]};
   }
 }
 template <int NB>
-__device__ __forceinline__ void store_cols_lp(const d4 (&acc)[NB / 32], double* C, int lo, int hi) {
-  const int lane = lane_id(), g = lane >> 4, h = wave_id() >> 2;
+__device__ __forceinline__ void store_cols_lp(const d4 (&acc)[NB / 32], double* Cg, int lo, int hi) {
+  const int lane = lane_id(), g = lane >> 4, n = lane & 15, h = wave_id() >> 2;
+  const auto r = rsrc(Cg, 16 * NB * 8);
 #pragma unroll
   for (int j = 0; j < NB / 32; ++j) {
     const int rb = 2 * j + h;
     if (rb < lo || rb >= hi) continue;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) gst(C + rb * 16 + 4 * g + r, acc[j][r]);
+    const int off = (n * NB + rb * 16 + 4 * g) * 8;
+    gst2(r, off, d2{acc[j][0], acc[j][1]});
+    gst2(r, off + 16, d2{acc[j][2], acc[j][3]});
   }
 }
 
@@ -466,7 +489,7 @@ __device__ __forceinline__ void prefetch_store_lp(const Prefetch<NB>& pf, unsign
 // LpV copies of the block's reflectors, wx is the group's exchange area.
 template <int NB, int VAR, int P>
 __device__ __forceinline__ void apply_block_lp(const unsigned char* vl, const double* Ts, int c0, d4 (&acc)[NB / 32],
-                                               double* c1, bool active, int trans, float* wx) {
+                                               double* c1g, bool active, int trans, float* wx) {
   using L = LpV<NB, P>;
   using T = typename L::T;
   const T* cm = reinterpret_cast<const T*>(vl) + L::CM;
@@ -535,11 +558,14 @@ __device__ __forceinline__ void apply_block_lp(const unsigned char* vl, const do
   // C1 rows c0 + 16 mb + 4 g + r (pairs), read by both waves before the
   // barrier and written by the h = 0 wave after it.
   d4 c1v[2] = {zero4(), zero4()};
+  const auto c1r = rsrc(c1g, 16 * NB * 8);
   if (VAR != V_UNM && active) {
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) c1v[mb][r] = gld(c1 + c0 + mb * 16 + 4 * g + r);
+    for (int mb = 0; mb < 2; ++mb) {
+      const int off = (n * NB + c0 + mb * 16 + 4 * g) * 8;
+      const d2 a = gld2(c1r, off), b = gld2(c1r, off + 16);
+      c1v[mb] = d4{a[0], a[1], b[0], b[1]};
+    }
   }
   float* mine = wx + h * 8 * 64;
 #pragma unroll
@@ -576,9 +602,12 @@ __device__ __forceinline__ void apply_block_lp(const unsigned char* vl, const do
   }
   if (VAR != V_UNM && h == 0) {
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) gst(c1 + c0 + mb * 16 + 4 * g + r, c1v[mb][r] - static_cast<double>(wt[mb][r]));
+    for (int mb = 0; mb < 2; ++mb) {
+      const int off = (n * NB + c0 + mb * 16 + 4 * g) * 8;
+      gst2(c1r, off, d2{c1v[mb][0] - static_cast<double>(wt[mb][0]), c1v[mb][1] - static_cast<double>(wt[mb][1])});
+      gst2(c1r, off + 16,
+           d2{c1v[mb][2] - static_cast<double>(wt[mb][2]), c1v[mb][3] - static_cast<double>(wt[mb][3])});
+    }
   }
   // C -= V W'.
   if constexpr (P == P_F32) {
@@ -908,7 +937,7 @@ __device__ __forceinline__ void unmqr_task(const double* V, const double* T, dou
     if constexpr (P == P_F64)
       load_cols<NB>(acc, Cw, 0, NB / 16);
     else
-      load_cols_lp<NB>(acc, Cw, 0, NB / 16);
+      load_cols_lp<NB>(acc, C + static_cast<size_t>(mycol) * NB, 0, NB / 16);
   }
 #pragma unroll 1
   for (int step = 0; step < NB / IB; ++step) {
@@ -933,7 +962,7 @@ __device__ __forceinline__ void unmqr_task(const double* V, const double* T, dou
     if constexpr (P == P_F64)
       store_cols<NB>(acc, Cw, 0, NB / 16);
     else
-      store_cols_lp<NB>(acc, Cw, 0, NB / 16);
+      store_cols_lp<NB>(acc, C + static_cast<size_t>(mycol) * NB, 0, NB / 16);
   }
 }
 
@@ -963,7 +992,7 @@ __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T,
     if constexpr (P == P_F64)
       load_cols<NB>(acc, C2 + off, 0, NB / 16);
     else
-      load_cols_lp<NB>(acc, C2 + off, 0, NB / 16);
+      load_cols_lp<NB>(acc, C2 + static_cast<size_t>(mycol) * NB, 0, NB / 16);
   }
 #pragma unroll 1
   for (int step = 0; step < NB / IB; ++step) {
@@ -988,10 +1017,11 @@ __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T,
         apply_block<NB, V_TS>(Vs, ldv, Ts, c0, acc, C1 + off, active, trans, wx);
     } else {
       float* wxf = reinterpret_cast<float*>(wx);
+      double* c1g = C1 + static_cast<size_t>(mycol) * NB;
       if (tt)
-        apply_block_lp<NB, V_TT, P>(vl, Ts, c0, acc, C1 + off, active, trans, wxf);
+        apply_block_lp<NB, V_TT, P>(vl, Ts, c0, acc, c1g, active, trans, wxf);
       else
-        apply_block_lp<NB, V_TS, P>(vl, Ts, c0, acc, C1 + off, active, trans, wxf);
+        apply_block_lp<NB, V_TS, P>(vl, Ts, c0, acc, c1g, active, trans, wxf);
     }
     __syncthreads();
   }
@@ -999,7 +1029,7 @@ __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T,
     if constexpr (P == P_F64)
       store_cols<NB>(acc, C2 + off, 0, NB / 16);
     else
-      store_cols_lp<NB>(acc, C2 + off, 0, NB / 16);
+      store_cols_lp<NB>(acc, C2 + static_cast<size_t>(mycol) * NB, 0, NB / 16);
   }
 }
 
@@ -1138,6 +1168,27 @@ __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
   });
 }
 
+// Executor of a Q application plan (apply_q kinds only, FP64): a kernel of
+// its own, so that it carries only the register budget of the update tasks.
+template <int NB>
+__global__ __launch_bounds__(NTHREADS) void exec_apply(ExecArgs a) {
+  __shared__ double sm[Smem<NB>::TOTAL];
+  const LoopCtl c{a.sub, a.deps, a.flags, a.ticket, a.err, a.nsub, a.epoch, a.spin_ticks, nullptr};
+  exec_loop(c, [&](int t) {
+    const DevSub& s = a.sub[t];
+    const int kind = __builtin_amdgcn_readfirstlane(s.kind);
+    if (kind == D_APPLY_GE) {
+      double* Bi = a.B + static_cast<size_t>(s.i) * NB * a.ncolB;
+      unmqr_task<NB, P_F64>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), Bi, s.slab * SLAB, a.ncolB, sm, a.transB);
+    } else {
+      double* Bp = a.B + static_cast<size_t>(s.piv) * NB * a.ncolB;
+      double* Bi = a.B + static_cast<size_t>(s.i) * NB * a.ncolB;
+      pair_mqr_task<NB, P_F64>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), Bp, Bi, s.slab * SLAB, a.ncolB, sm,
+                               kind == D_APPLY_TT, a.transB);
+    }
+  });
+}
+
 // Batched executor: subtasks of many problems (tile sizes 32 or 64) in one
 // launch; each subtask runs on its problem's tiles.
 template <int P>
@@ -1217,6 +1268,10 @@ hipError_t launch_reset(int32_t* ticket, int32_t* err, hipStream_t s) {
 
 template <int NB>
 static hipError_t launch_persistent_nb(const ExecArgs& a, int grid, hipStream_t s) {
+  if (a.B) {
+    hipLaunchKernelGGL((exec_apply<NB>), dim3(grid), dim3(NTHREADS), 0, s, a);
+    return hipGetLastError();
+  }
   switch (a.upd) {
     case P_F64: hipLaunchKernelGGL((exec_persistent<NB, P_F64>), dim3(grid), dim3(NTHREADS), 0, s, a); break;
     case P_F32: hipLaunchKernelGGL((exec_persistent<NB, P_F32>), dim3(grid), dim3(NTHREADS), 0, s, a); break;

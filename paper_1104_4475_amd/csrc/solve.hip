@@ -99,6 +99,34 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
     ys[e] = c < nc ? Y[c * ldy + r0 + r] : 0.0;
   }
   if (tid == 0) s_abort = 0;
+  // Inverse of diagonal block w (32 x 32, upper triangular) of R_ii on wave
+  // w, by back substitution on the identity: lane (rr, half) ends with row rr
+  // of the inverse (both halves alike).
+  const double* Rd = tiles + (static_cast<size_t>(i) * p + i) * NB * NB;
+  const int lane = tid & 63, rr = lane & 31, half = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double xinv[32];
+#pragma unroll
+  for (int c = 0; c < 32; ++c) xinv[c] = (c == rr) ? 1.0 : 0.0;
+  if (wave < NB / 32) {
+    const int base = 32 * wave;
+    double ur[32];
+#pragma unroll
+    for (int l = 0; l < 32; ++l) ur[l] = Rd[static_cast<size_t>(base + l) * NB + base + rr];
+#pragma unroll
+    for (int st = 31; st >= 0; --st) {
+      if (rr == st) {
+        const double d = 1.0 / ur[st];
+#pragma unroll
+        for (int c = st; c < 32; ++c) xinv[c] *= d;
+      }
+#pragma unroll
+      for (int c = st; c < 32; ++c) {
+        const double v = readlane_d(xinv[c], st);
+        if (rr < st) xinv[c] -= ur[st] * v;
+      }
+    }
+  }
   __syncthreads();
   for (int k = q - 1; k > i; --k) {
     if (tid == 0) {
@@ -125,37 +153,28 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
     tr_update<NB>(ys, xs, R, 0, NB, NB, nc, ps);
     __syncthreads();
   }
-  // Diagonal tile.
-  const double* R = tiles + (static_cast<size_t>(i) * p + i) * NB * NB;
-  const int lane = tid & 63, rr = lane & 31, half = lane >> 5;
+  // Diagonal tile, 32-row blocks from the bottom: x_b = inv(R_bb) y_b on
+  // wave b (the inverse computed before the waits), then y_a -= R_ab x_b for
+  // the blocks above.
   for (int b = NB / 32 - 1; b >= 0; --b) {
     const int base = 32 * b;
-    if (tid < 64) {
-      double ur[32];
+    if (wave == b) {
+      double xv[TR_COLS / 2];
 #pragma unroll
-      for (int l = 0; l < 32; ++l) ur[l] = R[static_cast<size_t>(base + l) * NB + base + rr];
-      double yv[TR_COLS / 2];
+      for (int u = 0; u < TR_COLS / 2; ++u) {
+        xv[u] = 0.0;
+        if (2 * u >= nc) continue;
+        const double* yc = ys + (half + 2 * u) * NB + base;
 #pragma unroll
-      for (int u = 0; u < TR_COLS / 2; ++u) yv[u] = ys[(half + 2 * u) * NB + base + rr];
-#pragma unroll
-      for (int st = 31; st >= 0; --st) {
-        if (rr == st) {
-#pragma unroll
-          for (int u = 0; u < TR_COLS / 2; ++u) yv[u] /= ur[st];
-        }
-#pragma unroll
-        for (int u = 0; u < TR_COLS / 2; ++u) {
-          if (2 * u >= nc) break;
-          const double x0 = readlane_d(yv[u], st), x1 = readlane_d(yv[u], st + 32);
-          if (rr < st) yv[u] -= ur[st] * (half ? x1 : x0);
-        }
+        for (int l = 0; l < 32; ++l) xv[u] += xinv[l] * yc[l];
       }
 #pragma unroll
-      for (int u = 0; u < TR_COLS / 2; ++u) ys[(half + 2 * u) * NB + base + rr] = yv[u];
+      for (int u = 0; u < TR_COLS / 2; ++u)
+        if (half + 2 * u < nc) ys[(half + 2 * u) * NB + base + rr] = xv[u];
     }
     __syncthreads();
     if (b > 0) {
-      tr_update<NB>(ys, ys, R, base, 32, base, nc, ps);
+      tr_update<NB>(ys, ys, Rd, base, 32, base, nc, ps);
       __syncthreads();
     }
   }
