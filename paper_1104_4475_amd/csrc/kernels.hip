@@ -658,6 +658,11 @@ __device__ __forceinline__ void apply_block_lp(const unsigned char* vl, const do
 // ||(alpha, x)||, tau = (beta - alpha) / beta, v = x / (alpha - beta)) and
 // broadcast through LDS; each wave then updates the columns it owns.  TT
 // (PAIR = 1, tt) limits column jj's reflector to rows 0..c0+jj.
+//
+// Look-ahead: while reflector jj is applied, the owner of column jj + 1
+// updates that column first and computes reflector jj + 1 at once, before
+// its other columns, so one barrier per column separates consecutive
+// reflectors and the chain between them is a single column update.
 template <int NB, int PAIR>
 __device__ __forceinline__ void panel_factor(double* Ps, int ldp, int K, double* Rs, double* tau, double* vbuf,
                                              int tt, int c0) {
@@ -671,96 +676,97 @@ __device__ __forceinline__ void panel_factor(double* Ps, int ldp, int K, double*
       const int r = lane + 64 * u;
       pc[q][u] = r < K ? Ps[r + (wave + NWAVES * q) * ldp] : 0.0;
     }
-#pragma unroll 1
-  for (int jj = 0; jj < IB; ++jj) {
+
+  // Reflector of column jj (owned by this wave, held in register slot x):
+  // writes v to vbuf[jj & 1], tau[jj], and (pairs) beta to Rs.  jj < 64, so
+  // the diagonal row jj of a GEQRT panel is in row chunk 0.
+  auto reflector = [&](int jj, double (&x)[RCH]) {
     const int r0 = PAIR ? 0 : jj + 1;
     const int r1 = PAIR ? (tt ? c0 + jj + 1 : K) : K;
     double* vb = vbuf + (jj & 1) * NB;
-    if (wave == (jj & 7)) {
-      const int q = jj >> 3;
-      double x[RCH];
+    double ssq = 0.0;
 #pragma unroll
-      for (int u = 0; u < RCH; ++u) {
-        x[u] = pc[0][u];
-#pragma unroll
-        for (int qq = 1; qq < 4; ++qq)
-          if (q == qq) x[u] = pc[qq][u];
-      }
-      double s = 0.0;
-#pragma unroll
-      for (int u = 0; u < RCH; ++u) {
-        const int r = lane + 64 * u;
-        if (r >= r0 && r < r1) s += x[u] * x[u];
-      }
-      s = wave_sum(s);
-      double alpha;
-      if (PAIR) {
-        alpha = Rs[jj + jj * IB];
-      } else {
-        double av = x[0];
-#pragma unroll
-        for (int u = 1; u < RCH; ++u)
-          if ((jj >> 6) == u) av = x[u];
-        alpha = lane_d(av, jj & 63);
-      }
-      double beta = alpha, t = 0.0, scale = 0.0;
-      if (s != 0.0) {
-        const double nrm = sqrt(alpha * alpha + s);
-        beta = alpha >= 0.0 ? -nrm : nrm;
-        t = (beta - alpha) / beta;
-        scale = 1.0 / (alpha - beta);
-      }
-#pragma unroll
-      for (int u = 0; u < RCH; ++u) {
-        const int r = lane + 64 * u;
-        const bool in = r >= r0 && r < r1;
-        if (in) x[u] *= scale;
-        if (!PAIR && r == jj) x[u] = beta;
-        if (r < NB) vb[r] = in ? x[u] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < RCH; ++u)
-#pragma unroll
-        for (int qq = 0; qq < 4; ++qq)
-          if (q == qq) pc[qq][u] = x[u];
-      if (lane == 0) {
-        tau[jj] = t;
-        if (PAIR) Rs[jj + jj * IB] = beta;
-      }
+    for (int u = 0; u < RCH; ++u) {
+      const int r = lane + 64 * u;
+      if (r >= r0 && r < r1) ssq += x[u] * x[u];
     }
-    __syncthreads();
-    const double t = uniform_d(tau[jj]);
-    if (t != 0.0) {
+    ssq = wave_sum(ssq);
+    const double alpha = PAIR ? Rs[jj + jj * IB] : lane_d(x[0], jj);
+    double beta = alpha, t = 0.0, scale = 0.0;
+    if (ssq != 0.0) {
+      const double nrm = sqrt(alpha * alpha + ssq);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      t = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+#pragma unroll
+    for (int u = 0; u < RCH; ++u) {
+      const int r = lane + 64 * u;
+      const bool in = r >= r0 && r < r1;
+      if (in) x[u] *= scale;
+      if (!PAIR && u == 0 && r == jj) x[u] = beta;
+      if (r < NB) vb[r] = in ? x[u] : 0.0;
+    }
+    if (lane == 0) {
+      tau[jj] = t;
+      if (PAIR) Rs[jj + jj * IB] = beta;
+    }
+  };
+
+  // Apply reflector jj (v, t) to this wave's register column slot q2.
+  auto update = [&](int jj, int q2, const double (&v)[RCH], double t) {
+    const int c = wave + NWAVES * q2;
+    double d = 0.0;
+#pragma unroll
+    for (int u = 0; u < RCH; ++u) d += v[u] * pc[q2][u];
+    d = wave_sum(d);
+    d += PAIR ? Rs[jj + c * IB] : lane_d(pc[q2][0], jj);
+    d *= t;
+#pragma unroll
+    for (int u = 0; u < RCH; ++u) {
+      pc[q2][u] -= v[u] * d;
+      if (!PAIR && u == 0 && lane == jj) pc[q2][u] -= d;
+    }
+    if (PAIR && lane == 0) Rs[jj + c * IB] -= d;
+  };
+
+  if (wave == 0) reflector(0, pc[0]);
+  // Column jj = 8 q + w: slot q of wave w.  The owner of column jj + 1
+  // (wave w + 1, slot q; or wave 0, slot q + 1) updates it first, computes
+  // its reflector at raised priority, then updates its other columns.
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+#pragma unroll 1
+    for (int w = 0; w < NWAVES; ++w) {
+      const int jj = NWAVES * q + w;
+      __syncthreads();
+      const double t = uniform_d(tau[jj]);
+      const int nxt = jj + 1;
+      const int nq = (w + 1 < NWAVES) ? q : q + 1;  // slot of column nxt
+      const bool own_next = nxt < IB && wave == (nxt & 7);
       double v[RCH];
 #pragma unroll
       for (int u = 0; u < RCH; ++u) {
         const int r = lane + 64 * u;
-        v[u] = r < NB ? vb[r] : 0.0;
+        v[u] = r < NB ? vbuf[(jj & 1) * NB + r] : 0.0;
       }
-#pragma unroll
-      for (int q2 = 0; q2 < 4; ++q2) {
-        const int c = wave + NWAVES * q2;
-        if (c <= jj) continue;
-        double d = 0.0;
-#pragma unroll
-        for (int u = 0; u < RCH; ++u) d += v[u] * pc[q2][u];
-        d = wave_sum(d);
-        if (PAIR) {
-          d += Rs[jj + c * IB];
-        } else {
-          double top = pc[q2][0];
-#pragma unroll
-          for (int u = 1; u < RCH; ++u)
-            if ((jj >> 6) == u) top = pc[q2][u];
-          d += lane_d(top, jj & 63);
+      if (own_next) {
+        __builtin_amdgcn_s_setprio(3);
+        if (nq == q) {
+          if (t != 0.0) update(jj, q, v, t);
+          reflector(nxt, pc[q]);
+        } else if (q + 1 < 4) {
+          if (t != 0.0) update(jj, (q + 1 < 4) ? q + 1 : q, v, t);
+          reflector(nxt, pc[(q + 1 < 4) ? q + 1 : q]);
         }
-        d *= t;
+        __builtin_amdgcn_s_setprio(0);
+      }
+      if (t != 0.0) {
 #pragma unroll
-        for (int u = 0; u < RCH; ++u) {
-          pc[q2][u] -= v[u] * d;
-          if (!PAIR && lane + 64 * u == jj) pc[q2][u] -= d;
+        for (int q2 = q; q2 < 4; ++q2) {
+          const int c = wave + NWAVES * q2;
+          if (c > nxt) update(jj, q2, v, t);
         }
-        if (PAIR && lane == 0) Rs[jj + c * IB] -= d;
       }
     }
   }
