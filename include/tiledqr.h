@@ -171,12 +171,16 @@ typedef struct {      /* host memory, filled by tiledqr_lstsq */
  * unchanged until the call returns.  Square systems use classical
  * refinement x <- x + R^{-1} Q^T (b - A0 x); tall systems refine the
  * augmented system [I A0; A0^T 0][r; x] = [b; 0] (Bjorck 1967) with the same
- * factors.  The backward error is ||b - A x|| / (||A||_F ||x|| + ||b||)
- * for square systems and ||A^T r|| / (||A||_F ||r||) for tall ones.
+ * factors: residuals f = b - r - A0 x and g = -A0^T r in FP64, corrections
+ * h = R^{-T} g, d = Q^T f, dx = R^{-1}(d(1:n) - h), dr = Q [h; d(n+1:m)].
+ * method 2 selects the augmented system for square systems too.  The
+ * backward error of x (r = b - A0 x, norms 2-norms per column, ||A0||_F) is
+ * ||r|| / (||A0|| ||x|| + ||b||) for classical refinement; the augmented
+ * refinement takes the smaller of that and ||A0^T r|| / (||A0|| ||r||).
  * Synchronizes the stream once per refinement iteration.  Returns
- * TQR_ENOTCONV (info filled, X holding the best iterate) if the tolerance is
+ * TQR_ENOTCONV (info filled, X holding the last iterate) if the tolerance is
  * not reached within max_iter or the error stops halving over three
- * iterations.  Errors: TQR_EINVAL, TQR_ENOMEM, TQR_EHIP. */
+ * iterations.  Errors: TQR_EINVAL, TQR_ENOMEM, TQR_EHIP, TQR_EEXEC. */
 int tiledqr_lstsq(const tqr_factors* F, const double* A0, int64_t lda,
                   const double* B, int64_t ldb, int64_t nrhs,
                   double* X, int64_t ldx, const tqr_refine* r,

@@ -366,6 +366,118 @@ int apply_tiles(const tqr_factors* Fc, int trans, double* Bt, int ncolB, hipStre
   return run_plan(F, *d, a, s);
 }
 
+// Least-squares refinement on the augmented system (Bjorck, 1967):
+//   [I A; A^T 0] [r; x] = [b; 0],
+// with residuals f = b - r - A x and g = -A^T r in FP64 and corrections from
+// the QR factors: h = R^{-T} g, d = Q^T f, dx = R^{-1}(d_1 - h),
+// dr = Q [h; d_2].  Stops when the backward error of x, the smaller of
+// ||b - A x|| / (||A||_F ||x|| + ||b||) and ||A^T (b - A x)|| / (||A||_F
+// ||b - A x||), is at most tol in every column, after max_iter iterations,
+// or when it has not halved in three iterations (TQR_ENOTCONV).  X holds the
+// initial solution on entry.  Bt: packed scratch of p row tiles x ncolB.
+int refine_augmented(const tqr_factors* F, const double* A0, int64_t lda, const double* B, int64_t ldb,
+                     int64_t nrhs, double* X, int64_t ldx, double tol, int max_iter, double* Bt, int ncolB,
+                     tqr_refine_info* info, hipStream_t s) {
+  const int64_t m = F->o.m, n = F->o.n;
+  double *Rv = nullptr, *Rr = nullptr, *Z = nullptr, *H = nullptr, *D = nullptr, *nrm = nullptr, *ca = nullptr;
+  auto done = [&](int code) {
+    for (double* ptr : {Rv, Rr, Z, H, D, nrm, ca})
+      if (ptr) (void)hipFreeAsync(ptr, s);
+    return code;
+  };
+  const size_t mb = static_cast<size_t>(m) * nrhs * sizeof(double), nbytes = static_cast<size_t>(n) * nrhs * sizeof(double);
+  if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Rv), mb, s)) ||
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Rr), mb, s)) ||
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Z), mb, s)) ||
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&H), nbytes, s)) ||
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&D), nbytes, s)) ||
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&nrm), 4 * nrhs * sizeof(double), s)) ||
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&ca), n * sizeof(double), s)))
+    return done(TQR_ENOMEM);
+  // ||A||_F and ||b|| once.
+  std::vector<double> colA(static_cast<size_t>(n)), hb(nrhs);
+  if (!hip_ok(hipMemsetAsync(ca, 0, n * sizeof(double), s)) ||
+      !hip_ok(hipMemsetAsync(nrm, 0, 4 * nrhs * sizeof(double), s)) ||
+      !hip_ok(tqr::launch_colnorms2(A0, lda, m, n, ca, s)) ||
+      !hip_ok(tqr::launch_colnorms2(B, ldb, m, nrhs, nrm + 3 * nrhs, s)) ||
+      !hip_ok(hipMemcpyAsync(colA.data(), ca, n * sizeof(double), hipMemcpyDeviceToHost, s)) ||
+      !hip_ok(hipMemcpyAsync(hb.data(), nrm + 3 * nrhs, nrhs * sizeof(double), hipMemcpyDeviceToHost, s)) ||
+      !hip_ok(hipStreamSynchronize(s)))
+    return done(TQR_EHIP);
+  double fa = 0.0;
+  for (double v : colA) fa += v;
+  fa = std::sqrt(fa);
+  // r = b - A x
+  if (!hip_ok(tqr::launch_residual(A0, lda, m, n, X, ldx, B, ldb, nrhs, Rr, m, s))) return done(TQR_EHIP);
+  std::vector<double> h(3 * nrhs);
+  std::vector<double> hist;
+  double eta = INFINITY;
+  int it = 0;
+  bool conv = false;
+  for (;; ++it) {
+    // Rv = b - A x; backward error of x.
+    if (!hip_ok(tqr::launch_residual(A0, lda, m, n, X, ldx, B, ldb, nrhs, Rv, m, s)) ||
+        !hip_ok(tqr::launch_gemv_t(A0, lda, m, n, Rv, m, nrhs, D, n, 1.0, s)) ||
+        !hip_ok(hipMemsetAsync(nrm, 0, 3 * nrhs * sizeof(double), s)) ||
+        !hip_ok(tqr::launch_colnorms2(Rv, m, m, nrhs, nrm, s)) ||
+        !hip_ok(tqr::launch_colnorms2(D, n, n, nrhs, nrm + nrhs, s)) ||
+        !hip_ok(tqr::launch_colnorms2(X, ldx, n, nrhs, nrm + 2 * nrhs, s)))
+      return done(TQR_EHIP);
+    int32_t serr = 0;
+    if (!hip_ok(hipMemcpyAsync(h.data(), nrm, 3 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s)) ||
+        !hip_ok(hipMemcpyAsync(&serr, F->ctl + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s)) ||
+        !hip_ok(hipStreamSynchronize(s)))
+      return done(TQR_EHIP);
+    if (serr) return done(TQR_EEXEC);
+    eta = 0.0;
+    for (int64_t c = 0; c < nrhs; ++c) {
+      const double nr = std::sqrt(h[c]), natr = std::sqrt(h[nrhs + c]), nx = std::sqrt(h[2 * nrhs + c]);
+      const double den_sq = fa * nx + std::sqrt(hb[c]);
+      const double e_sq = den_sq > 0 ? nr / den_sq : 0.0;
+      const double e_ls = (nr > 0 && fa > 0) ? natr / (fa * nr) : 0.0;
+      eta = std::max(eta, std::min(e_sq, e_ls));
+    }
+    hist.push_back(eta);
+    if (eta <= tol) {
+      conv = true;
+      break;
+    }
+    if (it >= max_iter) break;
+    if (hist.size() > 3 && hist.back() > 0.5 * hist[hist.size() - 4]) break;
+    // f = b - A x - r (in Rv), h = R^{-T} (-A^T r)
+    if (!hip_ok(tqr::launch_axpy_cols(Rv, m, Rr, m, m, nrhs, s, -1.0)) ||
+        !hip_ok(tqr::launch_gemv_t(A0, lda, m, n, Rr, m, nrhs, H, n, -1.0, s)) ||
+        !hip_ok(tqr::launch_trsm_upper_t(F->tiles, F->p, F->q, F->nb, H, n, nrhs, F->ctl + 3, &F->solve_epoch,
+                                         F->ctl + 2, 4 * wall_ticks_per_second(), s)))
+      return done(TQR_EHIP);
+    // d = Q^T f (packed), Z = d
+    if (!hip_ok(tqr::launch_pack_b(Rv, m, nrhs, Bt, F->p, F->nb, ncolB, s))) return done(TQR_EHIP);
+    int st = apply_tiles(F, 1, Bt, ncolB, s);
+    if (st != TQR_OK) return done(st);
+    if (!hip_ok(tqr::launch_unpack_b(Bt, Z, m, nrhs, static_cast<int>(m), F->nb, ncolB, s))) return done(TQR_EHIP);
+    // dx = R^{-1} (d_1 - h); x += dx
+    if (!hip_ok(tqr::launch_copy_cols(Z, m, D, n, n, nrhs, s)) ||
+        !hip_ok(tqr::launch_axpy_cols(D, n, H, n, n, nrhs, s, -1.0)) || !hip_ok(solve_r(F, D, n, nrhs, s)) ||
+        !hip_ok(tqr::launch_axpy_cols(X, ldx, D, n, n, nrhs, s)))
+      return done(TQR_EHIP);
+    // dr = Q [h; d_2]; r += dr
+    if (!hip_ok(tqr::launch_copy_cols(H, n, Z, m, n, nrhs, s)) ||
+        !hip_ok(tqr::launch_pack_b(Z, m, nrhs, Bt, F->p, F->nb, ncolB, s)))
+      return done(TQR_EHIP);
+    st = apply_tiles(F, 0, Bt, ncolB, s);
+    if (st != TQR_OK) return done(st);
+    if (!hip_ok(tqr::launch_unpack_b(Bt, Z, m, nrhs, static_cast<int>(m), F->nb, ncolB, s)) ||
+        !hip_ok(tqr::launch_axpy_cols(Rr, m, Z, m, m, nrhs, s)))
+      return done(TQR_EHIP);
+  }
+  if (info) {
+    info->iters = it;
+    info->converged = conv ? 1 : 0;
+    info->backward_err = eta;
+  }
+  return done(conv ? TQR_OK : TQR_ENOTCONV);
+}
+
 }  // namespace
 
 extern "C" {
@@ -591,8 +703,11 @@ int tiledqr_lstsq(const tqr_factors* F, const double* A0, int64_t lda, const dou
     }
     return fail(TQR_OK);
   }
-  if (m != n) return fail(TQR_EUNSUPPORTED);  // augmented-system refinement: tall systems
   const int max_iter = r->max_iter > 0 ? r->max_iter : 30;
+  if (m != n || r->method == 2) {
+    st = refine_augmented(F, A0, lda, B, ldb, nrhs, X, ldx, r->tol, max_iter, Bt, ncolB, info, s);
+    return fail(st);
+  }
   const size_t rv_elems = static_cast<size_t>(m) * nrhs;
   if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Rv), rv_elems * sizeof(double), s)) ||
       !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&D), static_cast<size_t>(n) * nrhs * sizeof(double), s)) ||

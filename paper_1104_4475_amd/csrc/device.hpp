@@ -85,10 +85,19 @@ hipError_t launch_unpack_b(const double* Bt, double* B, int64_t ldb, int64_t nrh
 // err: set when a wait exceeds spin_ticks.
 hipError_t launch_trsm_upper(const double* tiles, int p, int q, int nb, double* Y, int64_t ldy, int64_t nrhs,
                              int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks, hipStream_t s);
+// X = R^{-T} Y in place (same conventions).
+hipError_t launch_trsm_upper_t(const double* tiles, int p, int q, int nb, double* Y, int64_t ldy, int64_t nrhs,
+                               int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks, hipStream_t s);
+// out (n x nrhs, ldo) = sign * A^T Y for A m x n (lda), Y m x nrhs (ldy).
+hipError_t launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* Y, int64_t ldy,
+                         int64_t nrhs, double* out, int64_t ldo, double sign, hipStream_t s);
 hipError_t launch_residual(const double* A, int64_t lda, int64_t m, int64_t n, const double* X, int64_t ldx,
                            const double* B, int64_t ldb, int64_t nrhs, double* Rv, int64_t ldr, hipStream_t s);
 hipError_t launch_colnorms2(const double* M, int64_t ld, int64_t rows, int64_t cols, double* out, hipStream_t s);
+// X += alpha D (rows x cols); D -> copy of S.
 hipError_t launch_axpy_cols(double* X, int64_t ldx, const double* D, int64_t ldd, int64_t rows, int64_t cols,
+                            hipStream_t s, double alpha = 1.0);
+hipError_t launch_copy_cols(const double* S, int64_t lds, double* D, int64_t ldd, int64_t rows, int64_t cols,
                             hipStream_t s);
 int persistent_occupancy(int nb, int upd);
 hipError_t launch_batch_reset(int32_t* ctl, hipStream_t s);

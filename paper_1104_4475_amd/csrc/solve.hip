@@ -39,26 +39,32 @@ __device__ __forceinline__ double readlane_d(double v, int src) {
   return __longlong_as_double((static_cast<long long>(hi) << 32) | static_cast<unsigned int>(lo));
 }
 
-// ys[c * NB + row] -= sum_l M[(l0 + l) * NB + row] * xs[c * NB + l0 + l] for
-// rows < nrow, l < nl, columns < nc.  Thread t handles row t % NB and the
+// ys[c * NB + row] -= sum_l op(M)[row][l0 + l] * xs[c * NB + l0 + l] for
+// rows in [rlo, rhi), l < nl, columns < nc, with op(M) = M (element (r, c)
+// at c * NB + r) or, with TRANS, M^T.  Thread t handles row t % NB and the
 // l-range part t / NB of G = TR_THREADS / NB parts (loads issued 16 at a
 // time); the G partial sums meet in ps and are added in a fixed order.
 // Contains barriers: every thread calls it.
-template <int NB>
-__device__ __forceinline__ void tr_update(double* ys, const double* xs, const double* M, int l0, int nl, int nrow,
-                                          int nc, double* ps) {
+template <int NB, bool TRANS>
+__device__ __forceinline__ void tr_update(double* ys, const double* xs, const double* M, int l0, int nl, int rlo,
+                                          int rhi, int nc, double* ps) {
   constexpr int G = TR_THREADS / NB;
   const int row = threadIdx.x % NB, part = threadIdx.x / NB;
   const int per = (nl + G - 1) / G;
   const int la = part * per, lb = (la + per < nl) ? la + per : nl;
+  const bool live = row >= rlo && row < rhi;
   double acc[TR_COLS];
 #pragma unroll
   for (int c = 0; c < TR_COLS; ++c) acc[c] = 0.0;
-  if (row < nrow) {
+  if (live) {
     for (int l = la; l < lb; l += 16) {
       double m[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) m[u] = (l + u < lb) ? M[static_cast<size_t>(l0 + l + u) * NB + row] : 0.0;
+      for (int u = 0; u < 16; ++u) {
+        const size_t idx = TRANS ? static_cast<size_t>(row) * NB + l0 + l + u
+                                 : static_cast<size_t>(l0 + l + u) * NB + row;
+        m[u] = (l + u < lb) ? M[idx] : 0.0;
+      }
 #pragma unroll
       for (int u = 0; u < 16; ++u) {
         if (l + u < lb) {
@@ -75,7 +81,7 @@ __device__ __forceinline__ void tr_update(double* ys, const double* xs, const do
   __syncthreads();
   for (int e = threadIdx.x; e < TR_COLS * NB; e += TR_THREADS) {
     const int c = e / NB, r = e % NB;
-    if (c < nc && r < nrow) {
+    if (c < nc && r >= rlo && r < rhi) {
       double t = 0.0;
       for (int g = 0; g < G; ++g) t += ps[(g * TR_COLS + c) * NB + r];
       ys[c * NB + r] -= t;
@@ -83,15 +89,27 @@ __device__ __forceinline__ void tr_update(double* ys, const double* xs, const do
   }
 }
 
-template <int NB>
+// X = R^{-1} Y (TRANS = false) or X = R^{-T} Y (TRANS = true) in place in Y
+// (rows i nb .. i nb + nb - 1 of tile row i), with the tiled upper
+// triangular R (tiles (i, k), i <= k < q).  One workgroup per tile row,
+// ordered so that a workgroup only waits for workgroups with smaller
+// indices (already running): block b takes row q - 1 - b (back
+// substitution) or row b (forward substitution with R^T).  Row i applies
+// Y_i -= op(R)_ik X_k for every solved X_k (flag k set to the launch's
+// epoch), then solves its diagonal tile: 32-row blocks, each multiplied by
+// the inverse of its 32 x 32 diagonal block (computed by wave b before any
+// wait, by back substitution on the identity) and subtracted from the rest
+// of the tile by all waves.  Up to TR_COLS right-hand sides per launch.  A
+// wait longer than spin_ticks sets *err and the workgroup leaves.
+template <int NB, bool TRANS>
 __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* tiles, int p, int q, double* Y,
                                                                int64_t ldy, int nc, int32_t* flags, int32_t epoch,
                                                                int64_t spin_ticks, int32_t* err) {
   __shared__ double ys[NB * TR_COLS];
   __shared__ double xs[NB * TR_COLS];
-  __shared__ double ps[TR_THREADS * TR_COLS];  // partial sums of tr_update
+  __shared__ double ps[TR_THREADS * TR_COLS];  // partial sums of tr_update; block inverses for TRANS
   __shared__ int s_abort;
-  const int i = q - 1 - static_cast<int>(blockIdx.x);
+  const int i = TRANS ? static_cast<int>(blockIdx.x) : q - 1 - static_cast<int>(blockIdx.x);
   const int tid = threadIdx.x;
   const int64_t r0 = static_cast<int64_t>(i) * NB;
   for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
@@ -100,8 +118,8 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
   }
   if (tid == 0) s_abort = 0;
   // Inverse of diagonal block w (32 x 32, upper triangular) of R_ii on wave
-  // w, by back substitution on the identity: lane (rr, half) ends with row rr
-  // of the inverse (both halves alike).
+  // w: lane (rr, half) ends with row rr of the inverse (both halves alike);
+  // with TRANS, with row rr of the inverse's transpose.
   const double* Rd = tiles + (static_cast<size_t>(i) * p + i) * NB * NB;
   const int lane = tid & 63, rr = lane & 31, half = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -126,9 +144,21 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
         if (rr < st) xinv[c] -= ur[st] * v;
       }
     }
+    if (TRANS) {
+      double* tb = ps + wave * 32 * 32;
+      if (half == 0) {
+#pragma unroll
+        for (int c = 0; c < 32; ++c) tb[c * 32 + rr] = xinv[c];  // tb[c][rr] = inv[rr][c]
+      }
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int c = 0; c < 32; ++c) xinv[c] = tb[rr * 32 + c];  // inv[c][rr]
+    }
   }
   __syncthreads();
-  for (int k = q - 1; k > i; --k) {
+  const int k_first = TRANS ? 0 : q - 1;
+  const int k_end = TRANS ? i : i;
+  for (int k = k_first; TRANS ? (k < k_end) : (k > k_end); k += TRANS ? 1 : -1) {
     if (tid == 0) {
       const uint64_t t0 = wall_clock64();
       while (__hip_atomic_load(flags + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
@@ -149,14 +179,17 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
       xs[e] = c < nc ? ld_coh(Y + c * ldy + k0 + r) : 0.0;
     }
     __syncthreads();
-    const double* R = tiles + (static_cast<size_t>(k) * p + i) * NB * NB;
-    tr_update<NB>(ys, xs, R, 0, NB, NB, nc, ps);
+    // op(R)_ik: R_ik = tile (i, k) for the upper solve; (R_ki)^T for R^T.
+    const double* R = TRANS ? tiles + (static_cast<size_t>(i) * p + k) * NB * NB
+                            : tiles + (static_cast<size_t>(k) * p + i) * NB * NB;
+    tr_update<NB, TRANS>(ys, xs, R, 0, NB, 0, NB, nc, ps);
     __syncthreads();
   }
-  // Diagonal tile, 32-row blocks from the bottom: x_b = inv(R_bb) y_b on
-  // wave b (the inverse computed before the waits), then y_a -= R_ab x_b for
-  // the blocks above.
-  for (int b = NB / 32 - 1; b >= 0; --b) {
+  // Diagonal tile, 32-row blocks (from the bottom for R, from the top for
+  // R^T): x_b = inv(op(R_bb)) y_b on wave b, then subtracted from the rows
+  // still to solve.
+  for (int s = 0; s < NB / 32; ++s) {
+    const int b = TRANS ? s : NB / 32 - 1 - s;
     const int base = 32 * b;
     if (wave == b) {
       double xv[TR_COLS / 2];
@@ -173,8 +206,11 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
         if (half + 2 * u < nc) ys[(half + 2 * u) * NB + base + rr] = xv[u];
     }
     __syncthreads();
-    if (b > 0) {
-      tr_update<NB>(ys, ys, Rd, base, 32, base, nc, ps);
+    if (s + 1 < NB / 32) {
+      if (TRANS)
+        tr_update<NB, true>(ys, ys, Rd, base, 32, base + 32, NB, nc, ps);
+      else
+        tr_update<NB, false>(ys, ys, Rd, base, 32, 0, base, nc, ps);
       __syncthreads();
     }
   }
@@ -185,6 +221,23 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (tid == 0) __hip_atomic_store(flags + i, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Aty[c * n + j] = sign * sum_r A[j * lda + r] Y[c * ldy + r] for j < n,
+// c < nrhs: one wave per (column j, right-hand side c), lanes over rows.
+__global__ __launch_bounds__(256) void gemv_t_kernel(const double* A, int64_t lda, int64_t m, int64_t n,
+                                                     const double* Y, int64_t ldy, int64_t nrhs, double* out,
+                                                     int64_t ldo, double sign) {
+  const int64_t w = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (w >= n * nrhs) return;
+  const int64_t j = w % n, c = w / n;
+  const double* a = A + j * lda;
+  const double* y = Y + c * ldy;
+  double s = 0.0;
+  for (int64_t r = lane; r < m; r += 64) s += a[r] * y[r];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) out[c * ldo + j] = sign * s;
 }
 
 // Rv = B - A X for m x n A; grid (row blocks, column chunks), partial sums
@@ -240,12 +293,12 @@ __global__ __launch_bounds__(256) void colnorms2_kernel(const double* M, int64_t
 }
 
 __global__ __launch_bounds__(256) void axpy_cols_kernel(double* X, int64_t ldx, const double* D, int64_t ldd,
-                                                        int64_t rows, int64_t cols) {
+                                                        int64_t rows, int64_t cols, double alpha) {
   const int64_t total = rows * cols;
   for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
        e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
     const int64_t c = e / rows, r = e - c * rows;
-    X[c * ldx + r] += D[c * ldd + r];
+    X[c * ldx + r] += alpha * D[c * ldd + r];
   }
 }
 
@@ -257,20 +310,40 @@ int grid_of(int64_t total) {
 
 }  // namespace
 
-hipError_t launch_trsm_upper(const double* tiles, int p, int q, int nb, double* Y, int64_t ldy, int64_t nrhs,
-                             int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks, hipStream_t s) {
+template <bool TRANS>
+static hipError_t trsm_launch(const double* tiles, int p, int q, int nb, double* Y, int64_t ldy, int64_t nrhs,
+                              int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks, hipStream_t s) {
   for (int64_t c0 = 0; c0 < nrhs; c0 += TR_COLS) {
     const int nc = static_cast<int>(nrhs - c0 < TR_COLS ? nrhs - c0 : TR_COLS);
     const int32_t ep = ++*epoch;
     double* Yc = Y + c0 * ldy;
     switch (nb) {
-      case 32: hipLaunchKernelGGL(trsm_wave_kernel<32>, dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
-      case 64: hipLaunchKernelGGL(trsm_wave_kernel<64>, dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
-      case 128: hipLaunchKernelGGL(trsm_wave_kernel<128>, dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
-      case 256: hipLaunchKernelGGL(trsm_wave_kernel<256>, dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
+      case 32: hipLaunchKernelGGL((trsm_wave_kernel<32, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
+      case 64: hipLaunchKernelGGL((trsm_wave_kernel<64, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
+      case 128: hipLaunchKernelGGL((trsm_wave_kernel<128, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
+      case 256: hipLaunchKernelGGL((trsm_wave_kernel<256, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
       default: return hipErrorInvalidValue;
     }
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm_upper(const double* tiles, int p, int q, int nb, double* Y, int64_t ldy, int64_t nrhs,
+                             int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks, hipStream_t s) {
+  return trsm_launch<false>(tiles, p, q, nb, Y, ldy, nrhs, flags, epoch, err, spin_ticks, s);
+}
+
+hipError_t launch_trsm_upper_t(const double* tiles, int p, int q, int nb, double* Y, int64_t ldy, int64_t nrhs,
+                               int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks, hipStream_t s) {
+  return trsm_launch<true>(tiles, p, q, nb, Y, ldy, nrhs, flags, epoch, err, spin_ticks, s);
+}
+
+hipError_t launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* Y, int64_t ldy,
+                         int64_t nrhs, double* out, int64_t ldo, double sign, hipStream_t s) {
+  const int64_t threads = n * nrhs * 64;
+  if (threads == 0) return hipSuccess;
+  hipLaunchKernelGGL(gemv_t_kernel, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256), 0, s, A, lda, m,
+                     n, Y, ldy, nrhs, out, ldo, sign);
   return hipGetLastError();
 }
 
@@ -291,8 +364,16 @@ hipError_t launch_colnorms2(const double* M, int64_t ld, int64_t rows, int64_t c
 }
 
 hipError_t launch_axpy_cols(double* X, int64_t ldx, const double* D, int64_t ldd, int64_t rows, int64_t cols,
+                            hipStream_t s, double alpha) {
+  if (rows * cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(axpy_cols_kernel, dim3(grid_of(rows * cols)), dim3(256), 0, s, X, ldx, D, ldd, rows, cols, alpha);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_cols(const double* S, int64_t lds, double* D, int64_t ldd, int64_t rows, int64_t cols,
                             hipStream_t s) {
-  hipLaunchKernelGGL(axpy_cols_kernel, dim3(grid_of(rows * cols)), dim3(256), 0, s, X, ldx, D, ldd, rows, cols);
+  if (rows * cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(copy_cols_kernel, dim3(grid_of(rows * cols)), dim3(256), 0, s, S, lds, D, ldd, rows, cols);
   return hipGetLastError();
 }
 

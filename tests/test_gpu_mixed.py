@@ -144,3 +144,38 @@ def test_mixed_full_size_square(torch_cuda, upd):
     # sigma_max = 1 and sigma_min = 1 / kappa by construction
     bound = 2 * kappa * 1e-12 * torch.linalg.norm(A).item()
     assert d64 <= bound and dtrue <= bound
+
+
+def _tall_conditioned(m, n, kappa, seed):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    s = kappa ** (-np.arange(n) / (n - 1))
+    return (U * s) @ V.T
+
+
+@pytest.mark.parametrize("upd,kappa", [(0, 1e4), (1, 1e2), (1, 1e4), (2, 1e2)])
+def test_tall_augmented_refinement_matches_oracle(torch_cuda, upd, kappa):
+    """Tall least squares (2048 x 512, nb 64, an inconsistent right-hand
+    side): augmented-system refinement reaches a backward error of 1e-12
+    and the solution agrees with the FP64 oracle within the least-squares
+    perturbation bound 10 (kappa + kappa^2 ||r|| / (||A|| ||x||)) 1e-12."""
+    import paper_1104_4475_amd as tqr
+    torch = torch_cuda
+    m, n, nb, nrhs = 2048, 512, 64, 3
+    _say("tall augmented %s kappa %g" % (NAME.get(upd, "f64"), kappa))
+    A = _tall_conditioned(m, n, kappa, 61)
+    rng = np.random.default_rng(62)
+    B = A @ rng.standard_normal((n, nrhs)) + 1e-3 * rng.standard_normal((m, nrhs))
+    F = tqr.factor(_gpu(torch, A), nb, trees.GREEDY, 1, dag.KERN_DEFAULT, upd)
+    X, info = F.lstsq(_gpu(torch, B), A0=_gpu(torch, A), tol=1e-12, raise_on_noconv=True)
+    X = X.cpu().numpy()
+    eta = tiled.backward_error(A, X, B)
+    Xo = tiled.lstsq(tiled.tiled_qr(A, nb, trees.GREEDY, 1), B)
+    fwd = np.linalg.norm(X - Xo) / np.linalg.norm(Xo)
+    r = B - A @ Xo
+    bound = 10 * (kappa + kappa ** 2 * np.linalg.norm(r) / (np.linalg.norm(A, 2) * np.linalg.norm(Xo))) * 1e-12
+    _say("  iters %d backward %.2e (ls %.2e)  ||x - x_oracle||/||x_oracle|| %.2e (bound %.2e)"
+         % (info["iters"], info["backward_err"], max(eta), fwd, bound))
+    assert info["converged"] and info["backward_err"] <= 1e-12
+    assert fwd <= bound
