@@ -245,6 +245,12 @@ ExecArgs base_args(const tqr_factors* F, const DevPlan& d) {
   a.upd = F->o.upd;
   a.spin_ticks = 4 * wall_ticks_per_second();
   a.trace = (&d == &F->exec) ? F->trace : nullptr;
+  // Diagnostics: TQR_TRACE_APPLY=1 records Q-application subtasks into the
+  // same trace buffer (rows 0 .. nsub - 1 of that plan).
+  if (!a.trace && F->trace && d.nsub <= F->exec.nsub) {
+    const char* ta = std::getenv("TQR_TRACE_APPLY");
+    if (ta && ta[0] == '1') a.trace = F->trace;
+  }
   const char* dbg = std::getenv("TQR_DEBUG");
   a.debug = dbg ? std::atoi(dbg) : 0;
   return a;

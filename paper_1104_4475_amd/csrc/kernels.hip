@@ -972,6 +972,168 @@ __device__ __forceinline__ void unmqr_task(const double* V, const double* T, dou
   }
 }
 
+// ---- Q application to narrow right-hand sides (16 columns) ----------------
+// With only 16 columns the four column groups of the update kernels would
+// leave three quarters of the waves idle, so here every wave takes the same
+// 16 columns and its own 16-row blocks rb = wave + 8 j (FP64 accumulator
+// layout).  The eight partial W = V^T B are added through LDS by every wave,
+// each wave forms W' = op(T) W itself, and B -= V W' on its rows.
+template <int NB>
+constexpr int narrow_nj() { return (NB / 16 + NWAVES - 1) / NWAVES; }
+
+template <int NB>
+__device__ __forceinline__ void load_rows_narrow(d4 (&acc)[narrow_nj<NB>()], const double* Bc, int lo, int hi) {
+  const int lane = lane_id(), g = lane >> 4, wave = wave_id();
+#pragma unroll
+  for (int j = 0; j < narrow_nj<NB>(); ++j) {
+    const int rb = wave + NWAVES * j;
+    if (rb >= NB / 16 || rb < lo || rb >= hi) {
+      acc[j] = zero4();
+      continue;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) acc[j][i] = gld(Bc + rb * 16 + 4 * i + g);
+  }
+}
+template <int NB>
+__device__ __forceinline__ void store_rows_narrow(const d4 (&acc)[narrow_nj<NB>()], double* Bc, int lo, int hi) {
+  const int lane = lane_id(), g = lane >> 4, wave = wave_id();
+#pragma unroll
+  for (int j = 0; j < narrow_nj<NB>(); ++j) {
+    const int rb = wave + NWAVES * j;
+    if (rb >= NB / 16 || rb < lo || rb >= hi) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) gst(Bc + rb * 16 + 4 * i + g, acc[j][i]);
+  }
+}
+
+// One ib-block (first column c0) applied to the narrow B; c1 (pairs): the
+// lane's column of B1 (read by every wave before the barrier, written by
+// wave 0 after it).  wx: 8 x 8 x 64 doubles.  Contains a barrier.
+template <int NB, int VAR>
+__device__ __forceinline__ void apply_block_narrow(const double* Vs, int ldv, const double* Ts, int c0,
+                                                   d4 (&acc)[narrow_nj<NB>()], double* c1, int trans, double* wx) {
+  const int lane = lane_id(), g = lane >> 4, n = lane & 15, wave = wave_id();
+  const int rb_lo = (VAR == V_UNM) ? (c0 >> 4) : 0;
+  const int rb_hi = (VAR == V_TT) ? ((c0 + IB) >> 4) : (NB >> 4);
+  const int vbase = (VAR == V_UNM) ? c0 : 0;
+  d4 w[2] = {zero4(), zero4()};
+  {
+    const double* va = Vs + (g - vbase) + n * ldv;
+#pragma unroll
+    for (int j = 0; j < narrow_nj<NB>(); ++j) {
+      const int rb = wave + NWAVES * j;
+      if (rb >= NB / 16 || rb < rb_lo || rb >= rb_hi) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) w[mb] = mfma(va[rb * 16 + 4 * i + mb * 16 * ldv], acc[j][i], w[mb]);
+    }
+  }
+  d4 c1v[2] = {zero4(), zero4()};
+  if (VAR != V_UNM) {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) c1v[mb][i] = gld(c1 + c0 + mb * 16 + 4 * i + g);
+  }
+  double* mine = wx + wave * 8 * 64;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) mine[(mb * 4 + i) * 64 + lane] = w[mb][i];
+  __syncthreads();
+  d4 ws[2] = {c1v[0], c1v[1]};
+#pragma unroll
+  for (int o = 0; o < NWAVES; ++o) {
+    const double* part = wx + o * 8 * 64;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ws[mb][i] += part[(mb * 4 + i) * 64 + lane];
+  }
+  d4 wt[2] = {zero4(), zero4()};
+#pragma unroll
+  for (int ab = 0; ab < 2; ++ab) {
+#pragma unroll
+    for (int jb = 0; jb < 2; ++jb) {
+      if (trans ? (jb > ab) : (jb < ab)) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int jj = jb * 16 + 4 * i + g, aa = ab * 16 + n;
+        const double t = trans ? Ts[jj + aa * IB] : Ts[aa + jj * IB];
+        wt[ab] = mfma(t, ws[jb][i], wt[ab]);
+      }
+    }
+  }
+  if (VAR != V_UNM && wave == 0) {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) gst(c1 + c0 + mb * 16 + 4 * i + g, c1v[mb][i] - wt[mb][i]);
+  }
+  wt[0] = -wt[0];
+  wt[1] = -wt[1];
+  const double* vb = Vs + (n - vbase) + g * ldv;
+#pragma unroll
+  for (int j = 0; j < narrow_nj<NB>(); ++j) {
+    const int rb = wave + NWAVES * j;
+    if (rb >= NB / 16 || rb < rb_lo || rb >= rb_hi) continue;
+    d4 c = acc[j];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) c = mfma(vb[rb * 16 + (mb * 16 + 4 * i) * ldv], wt[mb][i], c);
+    acc[j] = c;
+  }
+}
+
+// Reflector block c (first column) of a Q application task into registers.
+template <int NB>
+__device__ __forceinline__ void apply_load_block(Prefetch<NB>& pf, int kind, const double* V, const double* T, int c) {
+  if (kind == D_APPLY_GE)
+    prefetch_load<NB, ST_UNIT_LOWER>(pf, V + c * NB + c, NB - c, c, T + (c / IB) * IB * IB);
+  else if (kind == D_APPLY_TT)
+    prefetch_load<NB, ST_UPPER>(pf, V + c * NB, c + IB, c, T + (c / IB) * IB * IB);
+  else
+    prefetch_load<NB, ST_FULL>(pf, V + c * NB, NB, c, T + (c / IB) * IB * IB);
+}
+
+// Q application task on 16-column row tiles: kind D_APPLY_GE (B1 unused),
+// D_APPLY_TS or D_APPLY_TT.  V: the factored (GE) or zeroed (TS/TT) tile.
+// pf holds the first reflector block on entry (apply_load_block with
+// c = 0 for Q^T, nb - ib for Q).
+template <int NB>
+__device__ __forceinline__ void apply_narrow_task(int kind, const double* V, const double* T, double* B1, double* B2,
+                                                  double* sm, int trans, Prefetch<NB>& pf) {
+  constexpr int ldv = Smem<NB>::LDP;
+  double* Vs = sm + Smem<NB>::PS;
+  double* Ts = sm + Smem<NB>::TS;
+  double* wx = sm + Smem<NB>::WX;
+  const int lane = lane_id();
+  const bool ge = kind == D_APPLY_GE, tt = kind == D_APPLY_TT;
+  double* c1 = ge ? nullptr : B1 + (lane & 15) * NB;
+  double* Bc = B2 + (lane & 15) * NB;
+  d4 acc[narrow_nj<NB>()];
+  load_rows_narrow<NB>(acc, Bc, 0, NB / 16);
+#pragma unroll 1
+  for (int step = 0; step < NB / IB; ++step) {
+    const int c0 = trans ? step * IB : NB - IB - step * IB;
+    const int K = ge ? NB - c0 : (tt ? c0 + IB : NB);
+    prefetch_store<NB>(pf, Vs, ldv, K, Ts);
+    __syncthreads();
+    if (step + 1 < NB / IB) apply_load_block<NB>(pf, kind, V, T, trans ? c0 + IB : c0 - IB);
+    if (ge)
+      apply_block_narrow<NB, V_UNM>(Vs, ldv, Ts, c0, acc, c1, trans, wx);
+    else if (tt)
+      apply_block_narrow<NB, V_TT>(Vs, ldv, Ts, c0, acc, c1, trans, wx);
+    else
+      apply_block_narrow<NB, V_TS>(Vs, ldv, Ts, c0, acc, c1, trans, wx);
+    __syncthreads();
+  }
+  store_rows_narrow<NB>(acc, Bc, 0, NB / 16);
+}
+
 // ---- TSMQR / TTMQR (and application of a pair set to B) --------------------
 template <int NB, int P>
 __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T, double* C1, double* C2, int col0,
@@ -1098,6 +1260,45 @@ struct LoopCtl {
   int64_t* trace;
 };
 
+// Wave 0 of a workgroup waits until every predecessor of subtask t has
+// published its flag; returns t, or c.nsub after a timeout (which sets
+// *err) or when another workgroup has set *err.
+__device__ __forceinline__ int wait_deps(const LoopCtl& c, int t, int lane) {
+  const int db = c.sub[t].dep_begin, de = c.sub[t].dep_end;
+  const uint64_t t0 = wall_clock64();
+  if (c.trace && lane == 0) c.trace[4 * static_cast<int64_t>(t)] = static_cast<int64_t>(t0);
+  for (int e = db; e < de && t < c.nsub; ++e) {
+    int32_t* f = c.flags + c.deps[e];
+    for (;;) {
+      const int v = __builtin_amdgcn_readfirstlane(__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (v == c.epoch) break;
+      const int err = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (err != 0 || static_cast<int64_t>(wall_clock64() - t0) > c.spin_ticks) {
+        if (lane == 0) __hip_atomic_store(c.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t = c.nsub;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+  }
+  return t;
+}
+
+// After run(t): every data store of the task is device-coherent, so once
+// each wave has seen its stores complete the flag can be published.
+__device__ __forceinline__ void finish_task(const LoopCtl& c, int t, int wave, int lane) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (wave == 0 && lane == 0) {
+    __hip_atomic_store(c.flags + t, c.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (c.trace) {
+      c.trace[4 * static_cast<int64_t>(t) + 2] = static_cast<int64_t>(wall_clock64());
+      c.trace[4 * static_cast<int64_t>(t) + 3] = blockIdx.x;
+    }
+  }
+}
+
 template <class Run>
 __device__ __forceinline__ void exec_loop(const LoopCtl& c, Run run) {
   __shared__ int s_t;
@@ -1117,27 +1318,7 @@ __device__ __forceinline__ void exec_loop(const LoopCtl& c, Run run) {
         if (lane == 0) tk = atomicAdd(c.ticket, 1);
         t = __builtin_amdgcn_readfirstlane(tk);
       }
-      if (t < c.nsub) {
-        const int db = c.sub[t].dep_begin, de = c.sub[t].dep_end;
-        const uint64_t t0 = wall_clock64();
-        if (c.trace && lane == 0) c.trace[4 * static_cast<int64_t>(t)] = static_cast<int64_t>(t0);
-        for (int e = db; e < de && t < c.nsub; ++e) {
-          int32_t* f = c.flags + c.deps[e];
-          for (;;) {
-            const int v = __builtin_amdgcn_readfirstlane(
-                __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            if (v == c.epoch) break;
-            const int err = __builtin_amdgcn_readfirstlane(
-                __hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-            if (err != 0 || static_cast<int64_t>(wall_clock64() - t0) > c.spin_ticks) {
-              if (lane == 0) __hip_atomic_store(c.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              t = c.nsub;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(1);
-          }
-        }
-      }
+      if (t < c.nsub) t = wait_deps(c, t, lane);
       if (lane == 0) s_t = t;
     }
     __syncthreads();
@@ -1147,17 +1328,43 @@ __device__ __forceinline__ void exec_loop(const LoopCtl& c, Run run) {
     if (t >= c.nsub) break;
     if (c.trace && threadIdx.x == 0) c.trace[4 * static_cast<int64_t>(t) + 1] = static_cast<int64_t>(wall_clock64());
     run(t);
-    // Every data store of the task is device-coherent: once each wave has
-    // seen its stores complete the flag can be published.
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
-    if (wave == 0 && lane == 0) {
-      __hip_atomic_store(c.flags + t, c.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (c.trace) {
-        c.trace[4 * static_cast<int64_t>(t) + 2] = static_cast<int64_t>(wall_clock64());
-        c.trace[4 * static_cast<int64_t>(t) + 3] = blockIdx.x;
+    finish_task(c, t, wave, lane);
+  }
+}
+
+// The same loop, with pre(t) run by every wave after the ticket is known and
+// before the predecessors are waited for (for loads of data that no
+// predecessor writes, so their latency overlaps the wait).
+template <class Pre, class Run>
+__device__ __forceinline__ void exec_loop_pre(const LoopCtl& c, Pre pre, Run run) {
+  __shared__ int s_t, s_go;
+  const int lane = lane_id();
+  const int wave = wave_id();
+  for (;;) {
+    if (wave == 0) {
+      int t = c.nsub;
+      const int err0 = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (err0 == 0) {
+        int tk = 0;
+        if (lane == 0) tk = atomicAdd(c.ticket, 1);
+        t = __builtin_amdgcn_readfirstlane(tk);
       }
+      if (lane == 0) s_t = t;
     }
+    __syncthreads();
+    const int t = __builtin_amdgcn_readfirstlane(s_t);
+    if (t >= c.nsub) break;
+    pre(t);
+    if (wave == 0) {
+      const int tw = wait_deps(c, t, lane);
+      if (lane == 0) s_go = (tw == t) ? 1 : 0;
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_go) == 0) break;
+    if (c.trace && threadIdx.x == 0) c.trace[4 * static_cast<int64_t>(t) + 1] = static_cast<int64_t>(wall_clock64());
+    run(t);
+    finish_task(c, t, wave, lane);
   }
 }
 
@@ -1179,7 +1386,33 @@ __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
 template <int NB>
 __global__ __launch_bounds__(NTHREADS) void exec_apply(ExecArgs a) {
   __shared__ double sm[Smem<NB>::TOTAL];
-  const LoopCtl c{a.sub, a.deps, a.flags, a.ticket, a.err, a.nsub, a.epoch, a.spin_ticks, nullptr};
+  const LoopCtl c{a.sub, a.deps, a.flags, a.ticket, a.err, a.nsub, a.epoch, a.spin_ticks, a.trace};
+  if (a.ncolB == 16) {
+    // Narrow right-hand sides: the first reflector block (written by the
+    // factorization, never by a predecessor) is loaded before the wait.
+    Prefetch<NB> pf;
+    auto tk = [&](int t) {
+      const DevSub& s = a.sub[t];
+      const int kind = __builtin_amdgcn_readfirstlane(s.kind);
+      const double* Tk = (kind == D_APPLY_GE) ? tg_ptr(a, s.i, s.k) : tp_ptr(a, s.i, s.k);
+      return Tk;
+    };
+    exec_loop_pre(
+        c,
+        [&](int t) {
+          const DevSub& s = a.sub[t];
+          const int kind = __builtin_amdgcn_readfirstlane(s.kind);
+          apply_load_block<NB>(pf, kind, tile_ptr(a, s.i, s.k), tk(t), a.transB ? 0 : NB - IB);
+        },
+        [&](int t) {
+          const DevSub& s = a.sub[t];
+          const int kind = __builtin_amdgcn_readfirstlane(s.kind);
+          double* Bp = (kind == D_APPLY_GE) ? nullptr : a.B + static_cast<size_t>(s.piv) * NB * a.ncolB;
+          double* Bi = a.B + static_cast<size_t>(s.i) * NB * a.ncolB;
+          apply_narrow_task<NB>(kind, tile_ptr(a, s.i, s.k), tk(t), Bp, Bi, sm, a.transB, pf);
+        });
+    return;
+  }
   exec_loop(c, [&](int t) {
     const DevSub& s = a.sub[t];
     const int kind = __builtin_amdgcn_readfirstlane(s.kind);
