@@ -1,0 +1,123 @@
+"""Measurement sweeps on the current GPU, printed as Markdown tables.
+
+  python -m paper_1104_4475_amd.measure trees    [--m 16384 --n 2048 --nb 256]
+      every reduction tree (PlasmaTree with BS 1..64) on an N(0,1) matrix:
+      executor time against the critical path of the task graph (Sec. 2.3)
+      in Table 1 units and in measured time (each kind weighted by its
+      mean measured duration from the executor trace)
+  python -m paper_1104_4475_amd.measure batched  [--count 512]
+      the batched launch of tall-skinny problems, FP64 and FP32 updates
+"""
+
+import argparse
+import sys
+
+import numpy as np
+
+from . import _lib
+from .api import Batch, factor
+
+KIND = ["GEQRT", "UNMQR", "TSQRT", "TSMQR", "TTQRT", "TTMQR"]
+
+
+def _cp(tasks, ptr, idx, w):
+    fin = np.zeros(len(tasks))
+    for t in range(len(tasks)):
+        s = 0.0
+        for e in range(ptr[t], ptr[t + 1]):
+            s = max(s, fin[idx[e]])
+        fin[t] = s + w[tasks[t, 0]]
+    return fin.max() if len(fin) else 0.0
+
+
+def trees(m, n, nb, reps=3):
+    import torch
+    p, q = m // nb, n // nb
+    g = torch.Generator(device="cuda")
+    g.manual_seed(1)
+    A = torch.randn((n, m), generator=g, dtype=torch.float64, device="cuda").t()
+    cases = [("FlatTree (TS)", _lib.TREE_FLAT, 1, _lib.KERN_TS), ("Sameh-Kuck (TT flat)", _lib.TREE_SAMEH_KUCK, 1,
+                                                                  _lib.KERN_TT),
+             ("BinaryTree", _lib.TREE_BINARY, 1, _lib.KERN_TT), ("Fibonacci", _lib.TREE_FIBONACCI, 1, _lib.KERN_TT),
+             ("Greedy", _lib.TREE_GREEDY, 1, _lib.KERN_TT)]
+    cases += [("PlasmaTree BS=%d" % bs, _lib.TREE_PLASMA, bs, _lib.KERN_TT) for bs in (1, 2, 4, 8, 16, 32, 64)
+              if bs <= p]
+    flops = 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
+    print("| tree | tasks | CP (units) | makespan (ms) | GFLOP/s | CP with measured task times (ms) | makespan / CP |")
+    print("|---|---|---|---|---|---|---|")
+    for name, tree, bs, kern in cases:
+        tasks, cp_units = _lib.schedule(p, q, tree, bs, kern)
+        ptr, idx = _lib.task_preds(p, q, tree, bs, kern)
+        F = factor(A, nb, tree, bs, kern, 0)
+        F.sync()
+        best = np.inf
+        for _ in range(reps):
+            F.refactor(A)
+            F.sync()
+            best = min(best, F.exec_ms())
+        F.set_trace(True)
+        F.refactor(A)
+        F.sync()
+        tr, rate = F.trace()
+        tr = np.asarray(tr)
+        dur = (tr[:, 8] - tr[:, 7]) * 1e3 / rate  # ms per subtask
+        w = np.zeros(6)
+        for k in range(6):
+            sel = tr[:, 0] == k
+            if sel.any():
+                # a task's column slabs run side by side: its time is one slab's
+                w[k] = dur[sel].mean()
+        cpt = _cp(tasks, ptr, idx, w)
+        print("| %s | %d | %d | %.2f | %.0f | %.2f | %.2f |" % (name, len(tasks), cp_units, best, flops / best / 1e6,
+                                                                cpt, best / cpt if cpt > 0 else float("nan")))
+        sys.stdout.flush()
+        del F
+
+
+def batched(count, seed=6):
+    import torch
+    rng = np.random.default_rng(seed)
+    shapes = []
+    for _ in range(count):
+        nn = int(rng.choice([32, 64, 128]))
+        nb = 32 if nn == 32 else 64
+        u = int(rng.integers(1024, 16385))
+        shapes.append((max(nb * int(round(u / nb)), nn), nn, nb))
+    mats = []
+    for i, (m, n, nb) in enumerate(shapes):
+        g = torch.Generator(device="cuda")
+        g.manual_seed(1000 + i)
+        mats.append(torch.randn((n, m), generator=g, dtype=torch.float64, device="cuda").t())
+    flops = sum(2.0 * m * n * n - 2.0 * n ** 3 / 3.0 for m, n, _ in shapes)
+    print("| updates | problems | total flops | graph time (ms) | GFLOP/s |")
+    print("|---|---|---|---|---|")
+    for upd, name in ((0, "FP64"), (1, "FP32")):
+        B = Batch([(m, n) for m, n, _ in shapes], [nb for _, _, nb in shapes], upd=upd)
+        ts = []
+        for _ in range(4):
+            B.run(mats)
+            B.sync()
+            ts.append(B.time_ms())
+        t = min(ts[1:])
+        print("| %s | %d | %.3e | %.2f | %.0f |" % (name, count, flops, t, flops / t / 1e6))
+        sys.stdout.flush()
+        del B
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("what", choices=["trees", "batched"])
+    ap.add_argument("--m", type=int, default=16384)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--nb", type=int, default=256)
+    ap.add_argument("--count", type=int, default=512)
+    a = ap.parse_args(argv)
+    if a.what == "trees":
+        trees(a.m, a.n, a.nb)
+    else:
+        batched(a.count)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
