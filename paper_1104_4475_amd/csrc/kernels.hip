@@ -327,6 +327,16 @@ __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const dou
   const int rb_lo = (VAR == V_UNM) ? (c0 >> 4) : 0;
   const int rb_hi = (VAR == V_TT) ? ((c0 + IB) >> 4) : (NB >> 4);
   const int vbase = (VAR == V_UNM) ? c0 : 0;
+  // C1 rows (pairs) are loaded first so that their latency overlaps GEMM1.
+  // Both waves of the group read them before the exchange barrier; the
+  // h = 0 wave writes them back only after it, so no read sees the update.
+  d4 c1v[2] = {zero4(), zero4()};
+  if (VAR != V_UNM && active) {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) c1v[mb][i] = gld(c1 + c0 + mb * 16 + 4 * i + g);
+  }
   // Partial W over this wave's row blocks: lane (n, g) supplies
   // V[16 rb + 4 i + g][16 mb + n]; two accumulators per mb.
   d4 w[2][2] = {{zero4(), zero4()}, {zero4(), zero4()}};
@@ -347,15 +357,6 @@ __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const dou
     }
   }
   d4 ws[2] = {w[0][0] + w[0][1], w[1][0] + w[1][1]};
-  // Both waves of the group read their C1 rows before the barrier; the h = 0
-  // wave writes them back only after it, so no read sees the update.
-  d4 c1v[2] = {zero4(), zero4()};
-  if (VAR != V_UNM && active) {
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) c1v[mb][i] = gld(c1 + c0 + mb * 16 + 4 * i + g);
-  }
   double* mine = wx + h * 8 * 64;
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
@@ -500,6 +501,19 @@ __device__ __forceinline__ void apply_block_lp(const unsigned char* vl, const do
   const int rb_hi = (VAR == V_TT) ? ((c0 + IB) >> 4) : (NB >> 4);
   const int vbase = (VAR == V_UNM) ? c0 : 0;
   constexpr int NJ = NB / 32;
+  // C1 rows c0 + 16 mb + 4 g + r (pairs), loaded first so that their
+  // latency overlaps GEMM1; read by both waves before the barrier and
+  // written by the h = 0 wave after it.
+  d4 c1v[2] = {zero4(), zero4()};
+  const auto c1r = rsrc(c1g, 16 * NB * 8);
+  if (VAR != V_UNM && active) {
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      const int off = (n * NB + c0 + mb * 16 + 4 * g) * 8;
+      const d2 a = gld2(c1r, off), b = gld2(c1r, off + 16);
+      c1v[mb] = d4{a[0], a[1], b[0], b[1]};
+    }
+  }
   // Partial W = V^T C over this wave's row blocks: w[mb] holds rows
   // 16 mb + 4 g + r of W.
   f4 w[2] = {zero4f(), zero4f()};
@@ -553,18 +567,6 @@ __device__ __forceinline__ void apply_block_lp(const unsigned char* vl, const do
           w[mb] = mfmabf(__builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7), b, w[mb]);
         }
       }
-    }
-  }
-  // C1 rows c0 + 16 mb + 4 g + r (pairs), read by both waves before the
-  // barrier and written by the h = 0 wave after it.
-  d4 c1v[2] = {zero4(), zero4()};
-  const auto c1r = rsrc(c1g, 16 * NB * 8);
-  if (VAR != V_UNM && active) {
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-      const int off = (n * NB + c0 + mb * 16 + 4 * g) * 8;
-      const d2 a = gld2(c1r, off), b = gld2(c1r, off + 16);
-      c1v[mb] = d4{a[0], a[1], b[0], b[1]};
     }
   }
   float* mine = wx + h * 8 * 64;
