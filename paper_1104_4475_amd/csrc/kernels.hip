@@ -785,8 +785,10 @@ __device__ __forceinline__ void panel_factor(double* Ps, int ldp, int K, double*
 // T factor of the block (forward, columnwise, as LAPACK dlarft):
 // T[j][j] = tau_j and T[0:j, j] = -tau_j T[0:j, 0:j] (V^T v_j)[0:j].
 // Ps holds the block's reflectors explicitly (K rows); the Gram matrix
-// G = V^T V comes from FP64 MFMAs on waves 0..2 (upper 16 x 16 blocks), the
-// recurrence runs on wave 0 with one row of T per lane in registers.
+// G = V^T V comes from FP64 MFMAs on waves 0..2 (upper 16 x 16 blocks).  The
+// two diagonal 16 x 16 blocks of T follow the recurrence on their own
+// reflectors (waves 0 and 1 side by side, one row of T per lane), and the
+// coupling block is T12 = -T11 (V1^T V2) T22, two 16 x 16 MFMA products.
 template <int NB>
 __device__ __forceinline__ void build_t(const double* Ps, int ldp, int K, const double* tau, double* Gs, double* Ts) {
   const int lane = lane_id(), wave = wave_id(), g = lane >> 4, n = lane & 15;
@@ -803,19 +805,35 @@ __device__ __forceinline__ void build_t(const double* Ps, int ldp, int K, const 
     for (int i = 0; i < 4; ++i) Gs[(ab * 16 + 4 * i + g) + (jb * 16 + n) * IB] = a0[i] + a1[i];
   }
   __syncthreads();
-  if (wave == 0 && lane < IB) {
-    const int a = lane;
-    double trow[IB];
+  if (wave < 2 && lane < 16) {
+    const int off = 16 * wave, a = lane;
+    double trow[16];
 #pragma unroll
-    for (int j = 0; j < IB; ++j) {
+    for (int j = 0; j < 16; ++j) {
       double s = 0.0;
 #pragma unroll
-      for (int b = 0; b < j; ++b) s += trow[b] * Gs[b + j * IB];
-      const double tj = tau[j];
+      for (int b = 0; b < j; ++b) s += trow[b] * Gs[(off + b) + (off + j) * IB];
+      const double tj = tau[off + j];
       trow[j] = (a < j) ? -tj * s : (a == j ? tj : 0.0);
     }
 #pragma unroll
-    for (int j = 0; j < IB; ++j) Ts[a + j * IB] = trow[j];
+    for (int j = 0; j < 16; ++j) Ts[(off + a) + (off + j) * IB] = trow[j];
+    if (wave == 1) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) Ts[(16 + a) + j * IB] = 0.0;  // T21 = 0
+    }
+  }
+  __syncthreads();
+  if (wave == 0) {
+    // P = G12 T22 (D layout: P[4 i + g][n] in p[i]), then T12 = -T11 P.
+    d4 pm = zero4(), e = zero4();
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+      pm = mfma(Gs[n + (16 + 4 * st + g) * IB], Ts[(16 + 4 * st + g) + (16 + n) * IB], pm);
+#pragma unroll
+    for (int st = 0; st < 4; ++st) e = mfma(Ts[n + (4 * st + g) * IB], pm[st], e);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Ts[(4 * i + g) + (16 + n) * IB] = -e[i];
   }
   __syncthreads();
 }
