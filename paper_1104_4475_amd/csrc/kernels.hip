@@ -838,8 +838,33 @@ __device__ __forceinline__ void build_t(const double* Ps, int ldp, int K, const 
   __syncthreads();
 }
 
+// The reflectors of an ib-block, explicit in the FP64 LDS panel Ps (K rows),
+// rewritten in place as the low-precision LDS copies of LpV<NB, P> (via
+// registers; contains barriers).  The T block in Ts is kept.
+template <int NB, int P>
+__device__ __forceinline__ void panel_to_lp(double* Ps, int ldp, int K, double* Ts) {
+  const int lane = lane_id(), wave = wave_id();
+  Prefetch<NB> pf;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int m = wave + NWAVES * c;
+#pragma unroll
+    for (int u = 0; u < Prefetch<NB>::RCH; ++u) {
+      const int kk = lane + 64 * u;
+      pf.v[c][u] = kk < K ? Ps[kk + m * ldp] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < Prefetch<NB>::TPER; ++u) pf.t[u] = Ts[threadIdx.x + NTHREADS * u];
+  __syncthreads();
+  prefetch_store_lp<NB, P>(pf, reinterpret_cast<unsigned char*>(Ps), K, Ts);
+  __syncthreads();
+}
+
 // ---- GEQRT ---------------------------------------------------------------
-template <int NB>
+// P: precision of the block update of the rest of the tile (the reflector
+// generation, norms, scaling and T, is FP64 in every mode).
+template <int NB, int P>
 __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm) {
   constexpr int ldp = Smem<NB>::LDP;
   double* Ps = sm + Smem<NB>::PS;
@@ -866,15 +891,26 @@ __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm) {
     build_t<NB>(Ps, ldp, K, tau, Gs, Ts);
     for (int e = tid; e < IB * IB; e += NTHREADS) gst(T + (c0 / IB) * IB * IB + e, Ts[e]);
     const int nch = (NB - c0 - IB) / 16;
+    if constexpr (P != P_F64) {
+      if (nch > 0) panel_to_lp<NB, P>(Ps, ldp, K, Ts);
+    }
 #pragma unroll 1
     for (int base = 0; base < nch; base += 4) {
       const int ch = base + gw;
       const bool active = ch < nch;
-      double* C = A + (c0 + IB + ch * 16 + (lane & 15)) * NB;
       d4 acc[NB / 32];
-      if (active) load_cols<NB>(acc, C, c0 / 16, NB / 16);
-      apply_block<NB, V_UNM>(Ps, ldp, Ts, c0, acc, nullptr, active, 1, wx);
-      if (active) store_cols<NB>(acc, C, c0 / 16, NB / 16);
+      if constexpr (P == P_F64) {
+        double* C = A + (c0 + IB + ch * 16 + (lane & 15)) * NB;
+        if (active) load_cols<NB>(acc, C, c0 / 16, NB / 16);
+        apply_block<NB, V_UNM>(Ps, ldp, Ts, c0, acc, nullptr, active, 1, wx);
+        if (active) store_cols<NB>(acc, C, c0 / 16, NB / 16);
+      } else {
+        double* Cg = A + static_cast<size_t>(c0 + IB + ch * 16) * NB;
+        if (active) load_cols_lp<NB>(acc, Cg, c0 / 16, NB / 16);
+        apply_block_lp<NB, V_UNM, P>(reinterpret_cast<const unsigned char*>(Ps), Ts, c0, acc, nullptr, active, 1,
+                                     reinterpret_cast<float*>(wx));
+        if (active) store_cols_lp<NB>(acc, Cg, c0 / 16, NB / 16);
+      }
       __syncthreads();
     }
     __syncthreads();
@@ -883,7 +919,7 @@ __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm) {
 
 // ---- TSQRT / TTQRT ----------------------------------------------------------
 // R1: the pivot tile (upper triangle holds R), A2: the tile to zero.
-template <int NB>
+template <int NB, int P>
 __device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T, double* sm, int tt) {
   constexpr int ldp = Smem<NB>::LDP;
   double* Ps = sm + Smem<NB>::PS;
@@ -919,19 +955,34 @@ __device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T,
     for (int e = tid; e < IB * IB; e += NTHREADS) gst(T + (c0 / IB) * IB * IB + e, Ts[e]);
     const int nch = (NB - c0 - IB) / 16;
     const int hi = tt ? (c0 + IB) / 16 : NB / 16;
+    if constexpr (P != P_F64) {
+      if (nch > 0) panel_to_lp<NB, P>(Ps, ldp, K, Ts);
+    }
 #pragma unroll 1
     for (int base = 0; base < nch; base += 4) {
       const int ch = base + gw;
       const bool active = ch < nch;
-      const int col = c0 + IB + ch * 16 + (lane & 15);
-      double* C2 = A2 + col * NB;
       d4 acc[NB / 32];
-      if (active) load_cols<NB>(acc, C2, 0, hi);
-      if (tt)
-        apply_block<NB, V_TT>(Ps, ldp, Ts, c0, acc, R1 + col * NB, active, 1, wx);
-      else
-        apply_block<NB, V_TS>(Ps, ldp, Ts, c0, acc, R1 + col * NB, active, 1, wx);
-      if (active) store_cols<NB>(acc, C2, 0, hi);
+      if constexpr (P == P_F64) {
+        const int col = c0 + IB + ch * 16 + (lane & 15);
+        double* C2 = A2 + col * NB;
+        if (active) load_cols<NB>(acc, C2, 0, hi);
+        if (tt)
+          apply_block<NB, V_TT>(Ps, ldp, Ts, c0, acc, R1 + col * NB, active, 1, wx);
+        else
+          apply_block<NB, V_TS>(Ps, ldp, Ts, c0, acc, R1 + col * NB, active, 1, wx);
+        if (active) store_cols<NB>(acc, C2, 0, hi);
+      } else {
+        const size_t colg = static_cast<size_t>(c0 + IB + ch * 16) * NB;
+        const unsigned char* vl = reinterpret_cast<const unsigned char*>(Ps);
+        float* wxf = reinterpret_cast<float*>(wx);
+        if (active) load_cols_lp<NB>(acc, A2 + colg, 0, hi);
+        if (tt)
+          apply_block_lp<NB, V_TT, P>(vl, Ts, c0, acc, R1 + colg, active, 1, wxf);
+        else
+          apply_block_lp<NB, V_TS, P>(vl, Ts, c0, acc, R1 + colg, active, 1, wxf);
+        if (active) store_cols_lp<NB>(acc, A2 + colg, 0, hi);
+      }
       __syncthreads();
     }
     __syncthreads();
@@ -1227,14 +1278,15 @@ template <int NB, int P>
 __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, double* sm) {
   switch (s.kind) {
     case D_GEQRT:
-      geqrt_task<NB>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), sm);
+      geqrt_task<NB, P>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), sm);
       break;
     case D_UNMQR:
       unmqr_task<NB, P>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), tile_ptr(a, s.i, s.j), s.slab * SLAB, NB, sm, 1);
       break;
     case D_TSQRT:
     case D_TTQRT:
-      pair_qrt_task<NB>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm, s.kind == D_TTQRT);
+      pair_qrt_task<NB, P>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm,
+                           s.kind == D_TTQRT);
       break;
     case D_TSMQR:
     case D_TTMQR:
