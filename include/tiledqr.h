@@ -186,6 +186,26 @@ int tiledqr_lstsq(const tqr_factors* F, const double* A0, int64_t lda,
                   double* X, int64_t ldx, const tqr_refine* r,
                   tqr_refine_info* info, void* stream);
 
+/* Factorization and Q^T B in one executor launch: re-factor A (device,
+ * lda >= m) into the existing handle F and overwrite B (device, m x nrhs,
+ * ldb >= m, 1 <= nrhs <= 16) with Q^T B (Sec. 1), the application of each
+ * reflector set to B running as soon as the panel task that produces it
+ * (Sec. 2.3) has finished, in the same persistent launch.  The handle's
+ * executor time (tiledqr_exec_time) then covers both.  The joint plan is
+ * built on the first call and kept in the handle.
+ * Errors: TQR_EINVAL, TQR_ENOMEM, TQR_EHIP. */
+int tiledqr_refactor_qtb(tqr_factors* F, const double* A, int64_t lda, double* B, int64_t ldb,
+                         int64_t nrhs, void* stream);
+
+/* tiledqr_lstsq with Q^T B already computed (QtB: device, ldq >= n, its
+ * first n rows used, e.g. from tiledqr_refactor_qtb); B (the original
+ * right-hand sides) and A0 serve the refinement as in tiledqr_lstsq.
+ * Errors: as tiledqr_lstsq, and TQR_EINVAL for QtB == NULL or ldq < n. */
+int tiledqr_lstsq_qtb(const tqr_factors* F, const double* A0, int64_t lda,
+                      const double* B, int64_t ldb, const double* QtB, int64_t ldq, int64_t nrhs,
+                      double* X, int64_t ldx, const tqr_refine* r,
+                      tqr_refine_info* info, void* stream);
+
 /* ---- batched ------------------------------------------------------------ */
 
 /* Many independent factorizations in one persistent launch.  The task

@@ -70,6 +70,9 @@ _sigs = {
     "tiledqr_lstsq": (ctypes.c_int, [_vp, _dp, _i64, _dp, _i64, _i64, _dp, _i64, _P(RefineOpts), _P(RefineInfo),
                                      _vp]),
     "tiledqr_factor_batched": (ctypes.c_int, [_i32, _P(Opts), _P(_vp), _P(_i64), _P(_vp), _vp]),
+    "tiledqr_refactor_qtb": (ctypes.c_int, [_vp, _dp, _i64, _dp, _i64, _i64, _vp]),
+    "tiledqr_lstsq_qtb": (ctypes.c_int, [_vp, _dp, _i64, _dp, _i64, _dp, _i64, _i64, _dp, _i64, _P(RefineOpts),
+                                         _P(RefineInfo), _vp]),
     "tiledqr_batch_create": (ctypes.c_int, [_i32, _P(Opts), _P(_i64), _P(_vp)]),
     "tiledqr_batch_run": (ctypes.c_int, [_vp, _P(_vp), _vp]),
     "tiledqr_batch_sync": (ctypes.c_int, [_vp]),

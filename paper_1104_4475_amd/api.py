@@ -118,9 +118,19 @@ class Factors:
         check(_lib.tiledqr_apply_q(self.handle, b"N", E.data_ptr(), self.m, self.n, _stream()), "tiledqr_apply_q")
         return E
 
-    def lstsq(self, B, A0=None, tol=0.0, max_iter=30, method=0, raise_on_noconv=False):
+    def refactor_qtb(self, A, B):
+        """Re-factor A and compute Q^T B in the same executor launch
+        (tiledqr_refactor_qtb); returns Q^T B as a new column-major tensor."""
+        A = colmajor(A)
+        QtB = colmajor(B).clone().t().contiguous().t() if B.dim() == 2 else colmajor(B).clone()
+        check(_lib.tiledqr_refactor_qtb(self.handle, A.data_ptr(), _ld(A), QtB.data_ptr(), _ld(QtB), QtB.shape[1],
+                                        _stream()), "tiledqr_refactor_qtb")
+        return QtB
+
+    def lstsq(self, B, A0=None, tol=0.0, max_iter=30, method=0, raise_on_noconv=False, QtB=None):
         """Solve min ||B - A X||.  With tol > 0 the solution is refined
-        against A0 (the original matrix).  Returns (X, info dict)."""
+        against A0 (the original matrix).  QtB: Q^T B already computed (from
+        refactor_qtb).  Returns (X, info dict)."""
         torch = _torch()
         B = colmajor(B)
         nrhs = B.shape[1]
@@ -131,8 +141,13 @@ class Factors:
         if A0 is not None:
             A0 = colmajor(A0)
             a0p, lda = A0.data_ptr(), _ld(A0)
-        st = _lib.tiledqr_lstsq(self.handle, a0p, lda, B.data_ptr(), _ld(B), nrhs, X.data_ptr(), self.n,
-                                ctypes.byref(ref), ctypes.byref(info), _stream())
+        if QtB is not None:
+            QtB = colmajor(QtB)
+            st = _lib.tiledqr_lstsq_qtb(self.handle, a0p, lda, B.data_ptr(), _ld(B), QtB.data_ptr(), _ld(QtB), nrhs,
+                                        X.data_ptr(), self.n, ctypes.byref(ref), ctypes.byref(info), _stream())
+        else:
+            st = _lib.tiledqr_lstsq(self.handle, a0p, lda, B.data_ptr(), _ld(B), nrhs, X.data_ptr(), self.n,
+                                    ctypes.byref(ref), ctypes.byref(info), _stream())
         if st != _lib.TQR_OK and not (st == _lib.TQR_ENOTCONV and not raise_on_noconv):
             raise _lib.TiledQRError(st, "tiledqr_lstsq")
         return X, {"iters": info.iters, "converged": bool(info.converged),

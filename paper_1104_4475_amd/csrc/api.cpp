@@ -163,6 +163,9 @@ struct tqr_factors {
   double* Tg = nullptr;
   double* Tp = nullptr;
   int32_t* ctl = nullptr;  // [0] ticket, [1] executor err, [2] solve err, [3..3+q) solve flags
+  ExecPlan exec_host;      // host copy of the factorization plan (joint plans are built from it)
+  DevPlan fused;           // factorization + Q^T B (16 columns) in one executor plan
+  double* Bt16 = nullptr;  // packed right-hand sides of the joint plan (p row tiles of nb x 16)
   mutable int32_t solve_epoch = 0;  // advanced by every triangular solve launch
   hipStream_t stream = nullptr;
   int grid = 1;
@@ -175,6 +178,8 @@ struct tqr_factors {
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     exec.release();
+    fused.release();
+    if (Bt16) (void)hipFree(Bt16);
     for (auto& kv : apply) kv.second.release();
     if (tiles) (void)hipFree(tiles);
     if (Tg) (void)hipFree(Tg);
@@ -316,6 +321,7 @@ int create(const tqr_opts* o, tqr_factors** out, ExecPlan* keep = nullptr) {
   int st = upload(ex, F->exec);
   if (st != TQR_OK) return st;
   if (keep) *keep = ex;
+  F->exec_host = std::move(ex);
   const size_t ntile = static_cast<size_t>(F->p) * F->q;
   const size_t nbb = static_cast<size_t>(F->nb);
   if (!hip_ok(hipMalloc(&F->tiles, ntile * nbb * nbb * sizeof(double))) ||
@@ -483,6 +489,10 @@ int refine_augmented(const tqr_factors* F, const double* A0, int64_t lda, const 
   }
   return done(conv ? TQR_OK : TQR_ENOTCONV);
 }
+
+int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double* B, int64_t ldb,
+               const double* QtB, int64_t ldq, int64_t nrhs, double* X, int64_t ldx, const tqr_refine* r,
+               tqr_refine_info* info, void* stream);
 
 }  // namespace
 
@@ -677,6 +687,58 @@ int tiledqr_task_preds(int32_t p, int32_t q, int32_t tree, int32_t bs, int32_t k
 
 int tiledqr_lstsq(const tqr_factors* F, const double* A0, int64_t lda, const double* B, int64_t ldb, int64_t nrhs,
                   double* X, int64_t ldx, const tqr_refine* r, tqr_refine_info* info, void* stream) {
+  return lstsq_impl(F, A0, lda, B, ldb, nullptr, 0, nrhs, X, ldx, r, info, stream);
+}
+
+int tiledqr_lstsq_qtb(const tqr_factors* F, const double* A0, int64_t lda, const double* B, int64_t ldb,
+                      const double* QtB, int64_t ldq, int64_t nrhs, double* X, int64_t ldx, const tqr_refine* r,
+                      tqr_refine_info* info, void* stream) {
+  if (!F || !QtB || ldq < F->o.n) return TQR_EINVAL;
+  return lstsq_impl(F, A0, lda, B, ldb, QtB, ldq, nrhs, X, ldx, r, info, stream);
+}
+
+int tiledqr_refactor_qtb(tqr_factors* F, const double* A, int64_t lda, double* B, int64_t ldb, int64_t nrhs,
+                         void* stream) {
+  if (!F || !A || lda < F->o.m || !B || ldb < F->o.m || nrhs < 1 || nrhs > 16) return TQR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!F->fused.sub) {
+    double w[6];
+    exec_weights(F->nb, F->o.upd, w);
+    const int nslab = std::max(1, F->nb / tqr::SLAB);
+    ExecPlan ex;
+    tqr::make_factor_apply_plan(F->plan, F->exec_host, nslab, w, 1, 0.1 * w[1], ex);
+    const int st = upload(ex, F->fused);
+    if (st != TQR_OK) return st;
+    if (!hip_ok(hipMalloc(&F->Bt16, static_cast<size_t>(F->p) * F->nb * 16 * sizeof(double)))) return TQR_ENOMEM;
+  }
+  F->stream = s;
+  HIP_TRY(tqr::launch_pack(A, lda, F->tiles, F->p, F->q, F->nb, s));
+  HIP_TRY(tqr::launch_pack_b(B, ldb, nrhs, F->Bt16, F->p, F->nb, 16, s));
+  if (!F->ev0) {
+    HIP_TRY(hipEventCreate(&F->ev0));
+    HIP_TRY(hipEventCreate(&F->ev1));
+  }
+  ExecArgs a = base_args(F, F->fused);
+  a.B = F->Bt16;
+  a.ncolB = 16;
+  a.transB = 1;
+  a.fused = 1;
+  HIP_TRY(hipEventRecord(F->ev0, s));
+  const int st = run_plan(F, F->fused, a, s);
+  if (st != TQR_OK) return st;
+  HIP_TRY(hipEventRecord(F->ev1, s));
+  F->timed = true;
+  HIP_TRY(tqr::launch_unpack_b(F->Bt16, B, ldb, nrhs, static_cast<int>(F->o.m), F->nb, 16, s));
+  return TQR_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double* B, int64_t ldb,
+               const double* QtB, int64_t ldq, int64_t nrhs, double* X, int64_t ldx, const tqr_refine* r,
+               tqr_refine_info* info, void* stream) {
   if (!F || !B || !X || nrhs < 1 || ldb < F->o.m || ldx < F->o.n) return TQR_EINVAL;
   const bool refine = r && r->tol > 0.0;
   if (refine && (!A0 || lda < F->o.m)) return TQR_EINVAL;
@@ -696,10 +758,14 @@ int tiledqr_lstsq(const tqr_factors* F, const double* A0, int64_t lda, const dou
   };
   if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Bt), bt_elems * sizeof(double), s))) return fail(TQR_ENOMEM);
   // X = R^{-1} (Q^T B)(1:n)
-  if (!hip_ok(tqr::launch_pack_b(B, ldb, nrhs, Bt, F->p, F->nb, ncolB, s))) return fail(TQR_EHIP);
-  st = apply_tiles(F, 1, Bt, ncolB, s);
-  if (st != TQR_OK) return fail(st);
-  if (!hip_ok(tqr::launch_unpack_b(Bt, X, ldx, nrhs, static_cast<int>(n), F->nb, ncolB, s))) return fail(TQR_EHIP);
+  if (QtB) {
+    if (!hip_ok(tqr::launch_copy_cols(QtB, ldq, X, ldx, n, nrhs, s))) return fail(TQR_EHIP);
+  } else {
+    if (!hip_ok(tqr::launch_pack_b(B, ldb, nrhs, Bt, F->p, F->nb, ncolB, s))) return fail(TQR_EHIP);
+    st = apply_tiles(F, 1, Bt, ncolB, s);
+    if (st != TQR_OK) return fail(st);
+    if (!hip_ok(tqr::launch_unpack_b(Bt, X, ldx, nrhs, static_cast<int>(n), F->nb, ncolB, s))) return fail(TQR_EHIP);
+  }
   if (!hip_ok(solve_r(F, X, ldx, nrhs, s))) return fail(TQR_EHIP);
   if (!refine) {
     if (info) {
@@ -784,6 +850,10 @@ int tiledqr_lstsq(const tqr_factors* F, const double* A0, int64_t lda, const dou
   }
   return fail(conv ? TQR_OK : TQR_ENOTCONV);
 }
+
+}  // namespace
+
+extern "C" {
 
 int tiledqr_batch_create(int32_t nprob, const tqr_opts* opts, const int64_t* lda, tqr_batch** out) {
   if (!out || nprob < 1 || !opts || !lda) return TQR_EINVAL;

@@ -42,6 +42,7 @@ struct ExecArgs {
   int64_t spin_ticks;   // wall-clock ticks a wait may last before giving up
   int64_t* trace;       // optional: per subtask (ticket, ready, end, workgroup)
   int32_t debug;        // diagnostics: bit 0 = clear the workgroup's LDS before each task
+  int32_t fused;        // B set and the plan mixes factorization and Q^T B subtasks
 };
 
 // One problem of a batched launch: its tile storage and shape.

@@ -1293,19 +1293,21 @@ __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, doub
       pair_mqr_task<NB, P>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), tile_ptr(a, s.piv, s.j), tile_ptr(a, s.i, s.j),
                         s.slab * SLAB, NB, sm, s.kind == D_TTMQR, 1);
       break;
-    case D_APPLY_GE: {
-      double* Bi = a.B + static_cast<size_t>(s.i) * NB * a.ncolB;
-      unmqr_task<NB, P_F64>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), Bi, s.slab * SLAB, a.ncolB, sm, a.transB);
-      break;
-    }
+    case D_APPLY_GE:
     case D_APPLY_TS:
-    case D_APPLY_TT: {
-      double* Bp = a.B + static_cast<size_t>(s.piv) * NB * a.ncolB;
-      double* Bi = a.B + static_cast<size_t>(s.i) * NB * a.ncolB;
-      pair_mqr_task<NB, P_F64>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), Bp, Bi, s.slab * SLAB, a.ncolB, sm,
-                        s.kind == D_APPLY_TT, a.transB);
+    case D_APPLY_TT:
+      if (s.kind == D_APPLY_GE) {
+        double* Bi = a.B + static_cast<size_t>(s.i) * NB * a.ncolB;
+        unmqr_task<NB, P_F64>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), Bi, s.slab * SLAB, a.ncolB, sm, a.transB);
+        break;
+      }
+      {
+        double* Bp = a.B + static_cast<size_t>(s.piv) * NB * a.ncolB;
+        double* Bi = a.B + static_cast<size_t>(s.i) * NB * a.ncolB;
+        pair_mqr_task<NB, P_F64>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), Bp, Bi, s.slab * SLAB, a.ncolB, sm,
+                                 s.kind == D_APPLY_TT, a.transB);
+      }
       break;
-    }
     default:
       break;
   }
@@ -1579,7 +1581,7 @@ hipError_t launch_reset(int32_t* ticket, int32_t* err, hipStream_t s) {
 
 template <int NB>
 static hipError_t launch_persistent_nb(const ExecArgs& a, int grid, hipStream_t s) {
-  if (a.B) {
+  if (a.B && !a.fused) {
     hipLaunchKernelGGL((exec_apply<NB>), dim3(grid), dim3(NTHREADS), 0, s, a);
     return hipGetLastError();
   }

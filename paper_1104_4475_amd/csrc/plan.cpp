@@ -10,7 +10,9 @@
 
 #include <algorithm>
 #include <cmath>
+#include <map>
 #include <numeric>
+#include <tuple>
 
 namespace tqr {
 
@@ -447,6 +449,93 @@ void make_apply_plan(const Plan& plan, int trans, int nslab, ExecPlan& ex) {
   ex.level_order.assign(n, 0);
   std::vector<int32_t> fill(ex.level_ptr.begin(), ex.level_ptr.end() - 1);
   for (size_t r = 0; r < n; ++r) ex.level_order[fill[depth[r]]++] = static_cast<int32_t>(r);
+}
+
+void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, const double w[6], int nslab_b,
+                            double w_apply, ExecPlan& out) {
+  ExecPlan ap;
+  make_apply_plan(plan, 1, nslab_b, ap);
+  const size_t nf = fac.sub.size(), na = ap.sub.size(), n = nf + na;
+  // Panel subtask of each (kind, i, k).
+  std::map<std::tuple<int, int, int>, int32_t> panel;
+  for (size_t t = 0; t < nf; ++t) {
+    const SubTask& s = fac.sub[t];
+    if (s.kind == K_GEQRT || s.kind == K_TSQRT || s.kind == K_TTQRT) panel[{s.kind, s.i, s.k}] = static_cast<int32_t>(t);
+  }
+  std::vector<std::vector<int32_t>> pre(n);
+  for (size_t t = 0; t < nf; ++t)
+    for (int32_t e = fac.sub[t].dep_begin; e < fac.sub[t].dep_end; ++e) pre[t].push_back(fac.deps[e]);
+  for (size_t a = 0; a < na; ++a) {
+    const SubTask& s = ap.sub[a];
+    for (int32_t e = s.dep_begin; e < s.dep_end; ++e) pre[nf + a].push_back(static_cast<int32_t>(nf) + ap.deps[e]);
+    const int fk = s.kind == 6 ? K_GEQRT : (s.kind == 7 ? K_TSQRT : K_TTQRT);
+    auto it = panel.find({fk, s.i, s.k});
+    if (it != panel.end()) pre[nf + a].push_back(it->second);
+  }
+  std::vector<double> wt(n);
+  const double S = static_cast<double>(nslab);
+  for (size_t t = 0; t < nf; ++t) {
+    const int kd = fac.sub[t].kind;
+    const bool is_upd = (kd == K_UNMQR || kd == K_TSMQR || kd == K_TTMQR);
+    wt[t] = is_upd ? w[kd] / S : w[kd];
+  }
+  for (size_t a = 0; a < na; ++a) wt[nf + a] = w_apply;
+  // Bottom levels: successors have larger indices in this numbering
+  // (factorization subtasks first, in their own topological order, then the
+  // application subtasks in theirs), so one backward sweep suffices.
+  std::vector<std::vector<int32_t>> succ(n);
+  for (size_t t = 0; t < n; ++t)
+    for (int32_t d : pre[t]) succ[d].push_back(static_cast<int32_t>(t));
+  std::vector<double> bl(n, 0.0);
+  for (size_t t = n; t-- > 0;) {
+    double m = 0.0;
+    for (int32_t c : succ[t]) m = std::max(m, bl[c]);
+    bl[t] = m + wt[t];
+  }
+  // An application subtask is dispatched right behind the last of its
+  // predecessors (its panel subtask, the previous application on its rows):
+  // its key is just below theirs, so the Q^T B chain advances with the
+  // factorization instead of trailing it.
+  for (size_t a = 0; a < na; ++a) {
+    double k = INFINITY;
+    for (int32_t d : pre[nf + a]) k = std::min(k, bl[d]);
+    bl[nf + a] = (k == INFINITY ? 0.0 : std::nextafter(k, -INFINITY));
+  }
+  std::vector<int32_t> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+    if (bl[a] != bl[b]) return bl[a] > bl[b];
+    return a < b;
+  });
+  std::vector<int32_t> pos(n);
+  for (size_t r = 0; r < n; ++r) pos[perm[r]] = static_cast<int32_t>(r);
+  out = ExecPlan();
+  out.nslab = nslab;
+  out.sub.resize(n);
+  out.key.resize(n);
+  for (size_t r = 0; r < n; ++r) {
+    const int32_t t = perm[r];
+    SubTask st = t < static_cast<int32_t>(nf) ? fac.sub[t] : ap.sub[t - nf];
+    st.dep_begin = static_cast<int32_t>(out.deps.size());
+    for (int32_t d : pre[t]) out.deps.push_back(pos[d]);
+    st.dep_end = static_cast<int32_t>(out.deps.size());
+    out.sub[r] = st;
+    out.key[r] = -bl[t];
+  }
+  std::vector<int32_t> depth(n, 0);
+  int32_t maxd = 0;
+  for (size_t r = 0; r < n; ++r) {
+    int32_t dd = 0;
+    for (int32_t e = out.sub[r].dep_begin; e < out.sub[r].dep_end; ++e) dd = std::max(dd, depth[out.deps[e]] + 1);
+    depth[r] = dd;
+    maxd = std::max(maxd, dd);
+  }
+  out.level_ptr.assign(maxd + 2, 0);
+  for (size_t r = 0; r < n; ++r) out.level_ptr[depth[r] + 1]++;
+  for (int32_t l = 0; l <= maxd; ++l) out.level_ptr[l + 1] += out.level_ptr[l];
+  out.level_order.assign(n, 0);
+  std::vector<int32_t> fill(out.level_ptr.begin(), out.level_ptr.end() - 1);
+  for (size_t r = 0; r < n; ++r) out.level_order[fill[depth[r]]++] = static_cast<int32_t>(r);
 }
 
 }  // namespace tqr

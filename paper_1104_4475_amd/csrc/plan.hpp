@@ -56,6 +56,15 @@ struct ExecPlan {
 // w: per-kind weights used for the priority (any positive values).
 void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex);
 
+// One executor plan for the factorization and Q^T B together: the
+// subtasks of fac (built by make_exec_plan with the same nslab and weights
+// w) and those of the Q^T application plan (make_apply_plan, trans = 1,
+// nslab_b slabs of B), each application subtask also depending on the panel
+// subtask that produces its reflectors.  Ordered by largest bottom level in
+// the joint graph (application subtasks weigh w_apply).
+void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, const double w[6], int nslab_b,
+                            double w_apply, ExecPlan& out);
+
 // Application of Q^T (trans = 1) or Q (trans = 0) to p row tiles of a
 // right-hand side with nslab column slabs: the reflector set of every panel
 // task, in task order for Q^T and in reverse for Q, with dependencies on the

@@ -144,6 +144,10 @@ def test_apply_q_matches_oracle(torch_cuda):
             got = F.apply_q(_gpu(torch, B), trans).cpu().numpy()
             want = tiled.apply_q(O, B, trans)
             assert np.max(np.abs(got - want)) <= 50 * 192 * EPS * np.linalg.norm(B), (tree, trans)
+        # more than 16 right-hand sides (four column groups per slab)
+        Bw = tqr_inputs.gaussian(320, 21, seed=13)
+        got = F.apply_q(_gpu(torch, Bw), "T").cpu().numpy()
+        assert np.max(np.abs(got - tiled.apply_q(O, Bw, "T"))) <= 50 * 192 * EPS * np.linalg.norm(Bw), tree
         # empty right-hand side is a no-op
         E = torch.zeros((320, 0), dtype=torch.float64, device="cuda")
         assert F.apply_q(E, "T").shape == (320, 0)
@@ -172,3 +176,29 @@ def test_square_refinement_fp64(torch_cuda):
     assert info["converged"] and info["backward_err"] <= 1e-12
     eta = tiled.backward_error(A, X.cpu().numpy(), B)
     assert np.max(eta) <= 1e-12
+
+
+@pytest.mark.parametrize("upd", [0, 1])
+def test_joint_factor_and_qtb(torch_cuda, upd):
+    """tiledqr_refactor_qtb: the factors are bit-identical to a plain
+    factorization (every subtask is deterministic) and Q^T B matches the
+    separate application within 50 n eps ||B||; the least-squares solution
+    from the joint Q^T B matches the plain one."""
+    import paper_1104_4475_amd as tqr
+    torch = torch_cuda
+    _say("joint factor + Q^T B, upd %d" % upd)
+    m, n, nb, nrhs = 1024, 768, 256, 4
+    A = tqr_inputs.gaussian(m, n, 71)
+    B = np.random.default_rng(72).standard_normal((m, nrhs))
+    Ad, Bd = _gpu(torch, A), _gpu(torch, B)
+    F = tqr.factor(Ad, nb, trees.GREEDY, 1, dag.KERN_DEFAULT, upd)
+    P0 = F.packed().clone()
+    Y0 = F.apply_q(Bd, "T")
+    QtB = F.refactor_qtb(Ad, Bd)
+    torch.cuda.synchronize()
+    assert torch.equal(F.packed(), P0)
+    err = (QtB - Y0).abs().max().item()
+    assert err <= 50 * m * EPS * np.linalg.norm(B), err
+    X1, _ = F.lstsq(Bd)
+    X2, _ = F.lstsq(Bd, QtB=QtB)
+    assert (X1 - X2).abs().max().item() <= 1e-10 * X1.abs().max().item()
