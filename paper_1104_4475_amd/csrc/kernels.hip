@@ -309,6 +309,30 @@ __device__ __forceinline__ void store_cols(const d4 (&acc)[NB / 32], double* C, 
   }
 }
 
+// Rows c0 + 16 mb + 4 i + g of the lane's column c1 of C1, the pair
+// operand of apply_block.  The caller issues these loads before those of
+// the next reflector block: vector memory loads complete in order, so the
+// wait for C1 then leaves the prefetch in flight.  Both waves of a group
+// read the rows before the exchange barrier of apply_block; the h = 0 wave
+// writes them back only after it, so no read sees the update.
+__device__ __forceinline__ void load_c1(d4 (&c1v)[2], const double* c1, int c0, bool active) {
+  const int g = lane_id() >> 4;
+  c1v[0] = zero4();
+  c1v[1] = zero4();
+  if (!active) return;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) c1v[mb][i] = gld(c1 + c0 + mb * 16 + 4 * i + g);
+}
+
+// Wait for every outstanding vector memory access of the wave.  Issued once
+// after a task's C is loaded into registers: the compiler's wait placement
+// otherwise carries those loads as possibly outstanding into the reflector
+// loop and waits for all loads (the prefetched next block included) at the
+// first use of C in every step.
+__device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
+
 // Apply one ib-block of reflectors (first column c0) to the column group's
 // 16 columns.  Vs (leading dimension ldv) holds the block's reflectors
 // explicitly (zeros and unit diagonal included):
@@ -316,27 +340,18 @@ __device__ __forceinline__ void store_cols(const d4 (&acc)[NB / 32], double* C, 
 //   V_TS   all nb rows of V2;
 //   V_TT   rows 0..c0+ib-1 of V2, zero below each reflector's support.
 // c1 points at the lane's column of C1 (pairs only); rows c0..c0+ib-1 of
-// C1 take part.  wx is the group's W exchange area.  Every thread must call
-// this (it contains a barrier); active says whether the group has columns.
-// trans: 1 applies Q^T (T^T), 0 applies Q (T).
+// C1 take part, read beforehand into c1v by load_c1.  wx is the group's W
+// exchange area.  Every thread must call this (it contains a barrier);
+// active says whether the group has columns.  trans: 1 applies Q^T (T^T),
+// 0 applies Q (T).
 template <int NB, int VAR>
 __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const double* Ts, int c0, d4 (&acc)[NB / 32],
-                                            double* c1, bool active, int trans, double* wx) {
+                                            double* c1, const d4 (&c1v)[2], bool active, int trans, double* wx) {
   const int lane = lane_id(), g = lane >> 4, n = lane & 15;
   const int h = wave_id() >> 2;
   const int rb_lo = (VAR == V_UNM) ? (c0 >> 4) : 0;
   const int rb_hi = (VAR == V_TT) ? ((c0 + IB) >> 4) : (NB >> 4);
   const int vbase = (VAR == V_UNM) ? c0 : 0;
-  // C1 rows (pairs) are loaded first so that their latency overlaps GEMM1.
-  // Both waves of the group read them before the exchange barrier; the
-  // h = 0 wave writes them back only after it, so no read sees the update.
-  d4 c1v[2] = {zero4(), zero4()};
-  if (VAR != V_UNM && active) {
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int i = 0; i < 4; ++i) c1v[mb][i] = gld(c1 + c0 + mb * 16 + 4 * i + g);
-  }
   // Partial W over this wave's row blocks: lane (n, g) supplies
   // V[16 rb + 4 i + g][16 mb + n]; two accumulators per mb.
   d4 w[2][2] = {{zero4(), zero4()}, {zero4(), zero4()}};
@@ -419,9 +434,18 @@ __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const dou
 // (BF16 via FP32), products accumulate in FP32, and each correction is
 // subtracted from the FP64 C.  The T-apply (W' = T^T W, 1/16 of the flops)
 // runs in FP32 in both modes.
+// Within each 16-row block the low-precision path keeps rows in the order
+// lp_row(q) (q = 4 g + r, r = 0..3 the accumulator element of lane (g, n)):
+// rows 2 g, 2 g + 1, 2 g + 8, 2 g + 9.  Each 16-byte access of a lane then
+// holds two adjacent rows and the four lanes of a column cover 64
+// contiguous bytes per instruction.  The reflectors of a block are kept in
+// the same order within 16, so every contraction sees matching indices.
+__device__ __forceinline__ int lp_row(int q) { return ((q >> 2) << 1) | (q & 1) | ((q & 2) << 2); }
+__device__ __forceinline__ int lp_pos(int x) { return (((x >> 1) & 3) << 2) | (x & 1) | ((x >> 3) << 1); }
+
 // Cg: first column of the wave's 16-column group (wave-uniform); lane
-// (g, n) moves rows 16 rb + 4 g .. 16 rb + 4 g + 3 of column n as two
-// 16-byte accesses.
+// (g, n) moves rows 16 rb + lp_row(4 g + r) of column n as two 16-byte
+// accesses.
 template <int NB>
 __device__ __forceinline__ void load_cols_lp(d4 (&acc)[NB / 32], const double* Cg, int lo, int hi) {
   const int lane = lane_id(), g = lane >> 4, n = lane & 15, h = wave_id() >> 2;
@@ -433,8 +457,8 @@ __device__ __forceinline__ void load_cols_lp(d4 (&acc)[NB / 32], const double* C
       acc[j] = zero4();
       continue;
     }
-    const int off = (n * NB + rb * 16 + 4 * g) * 8;
-    const d2 a = gld2(r, off), b = gld2(r, off + 16);
+    const int off = (n * NB + rb * 16 + 2 * g) * 8;
+    const d2 a = gld2(r, off), b = gld2(r, off + 64);
     acc[j] = d4{a[0], a[1], b[0], b[1]};
   }
 }
@@ -446,9 +470,9 @@ __device__ __forceinline__ void store_cols_lp(const d4 (&acc)[NB / 32], double* 
   for (int j = 0; j < NB / 32; ++j) {
     const int rb = 2 * j + h;
     if (rb < lo || rb >= hi) continue;
-    const int off = (n * NB + rb * 16 + 4 * g) * 8;
+    const int off = (n * NB + rb * 16 + 2 * g) * 8;
     gst2(r, off, d2{acc[j][0], acc[j][1]});
-    gst2(r, off + 16, d2{acc[j][2], acc[j][3]});
+    gst2(r, off + 64, d2{acc[j][2], acc[j][3]});
   }
 }
 
@@ -461,7 +485,8 @@ __device__ __forceinline__ typename LpV<32, P>::T to_lp(double x) {
 }
 
 // Prefetched reflector block (FP64 registers) into both low-precision LDS
-// copies; the T block stays FP64.
+// copies, rows and reflectors in lp_row order within each 16-block; the T
+// block stays FP64 in natural order.
 template <int NB, int P>
 __device__ __forceinline__ void prefetch_store_lp(const Prefetch<NB>& pf, unsigned char* vl, int K, double* Ts) {
   using L = LpV<NB, P>;
@@ -472,13 +497,15 @@ __device__ __forceinline__ void prefetch_store_lp(const Prefetch<NB>& pf, unsign
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int m = wave + NWAVES * c;
+    const int mp = (m & ~15) | lp_pos(m & 15);
 #pragma unroll
     for (int u = 0; u < Prefetch<NB>::RCH; ++u) {
       const int kk = lane + 64 * u;
+      const int kp = (kk & ~15) | lp_pos(kk & 15);
       if (kk < K) {
         const T v = to_lp<P>(pf.v[c][u]);
-        cm[m * L::LCM + kk] = v;
-        rm[kk * L::SRM + m] = v;
+        cm[mp * L::LCM + kp] = v;
+        rm[kp * L::SRM + mp] = v;
       }
     }
   }
@@ -486,11 +513,29 @@ __device__ __forceinline__ void prefetch_store_lp(const Prefetch<NB>& pf, unsign
   for (int u = 0; u < Prefetch<NB>::TPER; ++u) Ts[threadIdx.x + NTHREADS * u] = pf.t[u];
 }
 
+// C1 rows c0 + 16 mb + lp_row(4 g + r) of the group's 16 columns (first
+// column c1g) for apply_block_lp; issued before the next block's loads as
+// for load_c1.
+template <int NB>
+__device__ __forceinline__ void load_c1_lp(d4 (&c1v)[2], const double* c1g, int c0, bool active) {
+  const int lane = lane_id(), g = lane >> 4, n = lane & 15;
+  c1v[0] = zero4();
+  c1v[1] = zero4();
+  if (!active) return;
+  const auto c1r = rsrc(c1g, 16 * NB * 8);
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb) {
+    const int off = (n * NB + c0 + mb * 16 + 2 * g) * 8;
+    const d2 a = gld2(c1r, off), b = gld2(c1r, off + 64);
+    c1v[mb] = d4{a[0], a[1], b[0], b[1]};
+  }
+}
+
 // Same contract as apply_block (rows, c1, barrier, trans); vl holds the
 // LpV copies of the block's reflectors, wx is the group's exchange area.
 template <int NB, int VAR, int P>
 __device__ __forceinline__ void apply_block_lp(const unsigned char* vl, const double* Ts, int c0, d4 (&acc)[NB / 32],
-                                               double* c1g, bool active, int trans, float* wx) {
+                                               double* c1g, const d4 (&c1v)[2], bool active, int trans, float* wx) {
   using L = LpV<NB, P>;
   using T = typename L::T;
   const T* cm = reinterpret_cast<const T*>(vl) + L::CM;
@@ -501,25 +546,16 @@ __device__ __forceinline__ void apply_block_lp(const unsigned char* vl, const do
   const int rb_hi = (VAR == V_TT) ? ((c0 + IB) >> 4) : (NB >> 4);
   const int vbase = (VAR == V_UNM) ? c0 : 0;
   constexpr int NJ = NB / 32;
-  // C1 rows c0 + 16 mb + 4 g + r (pairs), loaded first so that their
-  // latency overlaps GEMM1; read by both waves before the barrier and
-  // written by the h = 0 wave after it.
-  d4 c1v[2] = {zero4(), zero4()};
+  // c1v: C1 rows c0 + 16 mb + lp_row(4 g + r) (pairs), from load_c1_lp.
+  // In LDS position order (lp_row within 16) every index below reads as in
+  // the natural order.
   const auto c1r = rsrc(c1g, 16 * NB * 8);
-  if (VAR != V_UNM && active) {
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-      const int off = (n * NB + c0 + mb * 16 + 4 * g) * 8;
-      const d2 a = gld2(c1r, off), b = gld2(c1r, off + 16);
-      c1v[mb] = d4{a[0], a[1], b[0], b[1]};
-    }
-  }
-  // Partial W = V^T C over this wave's row blocks: w[mb] holds rows
+  // Partial W = V^T C over this wave's row blocks: w[mb] holds positions
   // 16 mb + 4 g + r of W.
   f4 w[2] = {zero4f(), zero4f()};
   if (active) {
     if constexpr (P == P_F32) {
-      // k-slice r of row block rb: rows 16 rb + 4 g + r.
+      // k-slice r of row block rb: positions 16 rb + 4 g + r.
       f4 w1[2] = {zero4f(), zero4f()};
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
@@ -587,7 +623,8 @@ __device__ __forceinline__ void apply_block_lp(const unsigned char* vl, const do
 #pragma unroll
       for (int r = 0; r < 4; ++r) w[mb][r] += static_cast<float>(c1v[mb][r]);
   }
-  // W' = op(T) W in FP32: wt[ab] holds rows 16 ab + 4 g + r.
+  // W' = op(T) W in FP32: wt[ab] holds positions 16 ab + 4 g + r (T is
+  // read at the reflectors those positions hold).
   f4 wt[2] = {zero4f(), zero4f()};
 #pragma unroll
   for (int ab = 0; ab < 2; ++ab) {
@@ -596,7 +633,7 @@ __device__ __forceinline__ void apply_block_lp(const unsigned char* vl, const do
       if (trans ? (jb > ab) : (jb < ab)) continue;  // T is upper triangular
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int kk = jb * 16 + 4 * g + r, aa = ab * 16 + n;
+        const int kk = jb * 16 + lp_row(4 * g + r), aa = ab * 16 + lp_row(n);
         const double t = trans ? Ts[kk + aa * IB] : Ts[aa + kk * IB];
         wt[ab] = mfma32(static_cast<float>(t), w[jb][r], wt[ab]);
       }
@@ -605,9 +642,9 @@ __device__ __forceinline__ void apply_block_lp(const unsigned char* vl, const do
   if (VAR != V_UNM && h == 0) {
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
-      const int off = (n * NB + c0 + mb * 16 + 4 * g) * 8;
+      const int off = (n * NB + c0 + mb * 16 + 2 * g) * 8;
       gst2(c1r, off, d2{c1v[mb][0] - static_cast<double>(wt[mb][0]), c1v[mb][1] - static_cast<double>(wt[mb][1])});
-      gst2(c1r, off + 16,
+      gst2(c1r, off + 64,
            d2{c1v[mb][2] - static_cast<double>(wt[mb][2]), c1v[mb][3] - static_cast<double>(wt[mb][3])});
     }
   }
@@ -899,15 +936,16 @@ __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm) {
       const int ch = base + gw;
       const bool active = ch < nch;
       d4 acc[NB / 32];
+      const d4 none[2] = {zero4(), zero4()};
       if constexpr (P == P_F64) {
         double* C = A + (c0 + IB + ch * 16 + (lane & 15)) * NB;
         if (active) load_cols<NB>(acc, C, c0 / 16, NB / 16);
-        apply_block<NB, V_UNM>(Ps, ldp, Ts, c0, acc, nullptr, active, 1, wx);
+        apply_block<NB, V_UNM>(Ps, ldp, Ts, c0, acc, nullptr, none, active, 1, wx);
         if (active) store_cols<NB>(acc, C, c0 / 16, NB / 16);
       } else {
         double* Cg = A + static_cast<size_t>(c0 + IB + ch * 16) * NB;
         if (active) load_cols_lp<NB>(acc, Cg, c0 / 16, NB / 16);
-        apply_block_lp<NB, V_UNM, P>(reinterpret_cast<const unsigned char*>(Ps), Ts, c0, acc, nullptr, active, 1,
+        apply_block_lp<NB, V_UNM, P>(reinterpret_cast<const unsigned char*>(Ps), Ts, c0, acc, nullptr, none, active, 1,
                                      reinterpret_cast<float*>(wx));
         if (active) store_cols_lp<NB>(acc, Cg, c0 / 16, NB / 16);
       }
@@ -919,8 +957,10 @@ __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm) {
 
 // ---- TSQRT / TTQRT ----------------------------------------------------------
 // R1: the pivot tile (upper triangle holds R), A2: the tile to zero.
-template <int NB, int P>
-__device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T, double* sm, int tt) {
+// TT: 1 for TTQRT (A2 upper triangular), 0 for TSQRT.
+template <int NB, int P, int TT>
+__device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T, double* sm) {
+  constexpr int tt = TT;
   constexpr int ldp = Smem<NB>::LDP;
   double* Ps = sm + Smem<NB>::PS;
   double* Ts = sm + Smem<NB>::TS;
@@ -962,25 +1002,27 @@ __device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T,
     for (int base = 0; base < nch; base += 4) {
       const int ch = base + gw;
       const bool active = ch < nch;
-      d4 acc[NB / 32];
+      d4 acc[NB / 32], c1v[2];
       if constexpr (P == P_F64) {
         const int col = c0 + IB + ch * 16 + (lane & 15);
         double* C2 = A2 + col * NB;
+        load_c1(c1v, R1 + col * NB, c0, active);
         if (active) load_cols<NB>(acc, C2, 0, hi);
         if (tt)
-          apply_block<NB, V_TT>(Ps, ldp, Ts, c0, acc, R1 + col * NB, active, 1, wx);
+          apply_block<NB, V_TT>(Ps, ldp, Ts, c0, acc, R1 + col * NB, c1v, active, 1, wx);
         else
-          apply_block<NB, V_TS>(Ps, ldp, Ts, c0, acc, R1 + col * NB, active, 1, wx);
+          apply_block<NB, V_TS>(Ps, ldp, Ts, c0, acc, R1 + col * NB, c1v, active, 1, wx);
         if (active) store_cols<NB>(acc, C2, 0, hi);
       } else {
         const size_t colg = static_cast<size_t>(c0 + IB + ch * 16) * NB;
         const unsigned char* vl = reinterpret_cast<const unsigned char*>(Ps);
         float* wxf = reinterpret_cast<float*>(wx);
+        load_c1_lp<NB>(c1v, R1 + colg, c0, active);
         if (active) load_cols_lp<NB>(acc, A2 + colg, 0, hi);
         if (tt)
-          apply_block_lp<NB, V_TT, P>(vl, Ts, c0, acc, R1 + colg, active, 1, wxf);
+          apply_block_lp<NB, V_TT, P>(vl, Ts, c0, acc, R1 + colg, c1v, active, 1, wxf);
         else
-          apply_block_lp<NB, V_TS, P>(vl, Ts, c0, acc, R1 + colg, active, 1, wxf);
+          apply_block_lp<NB, V_TS, P>(vl, Ts, c0, acc, R1 + colg, c1v, active, 1, wxf);
         if (active) store_cols_lp<NB>(acc, A2 + colg, 0, hi);
       }
       __syncthreads();
@@ -1010,12 +1052,14 @@ __device__ __forceinline__ void unmqr_task(const double* V, const double* T, dou
   }
   unsigned char* vl = reinterpret_cast<unsigned char*>(sm + Smem<NB>::PS);
   d4 acc[NB / 32];
+  const d4 none[2] = {zero4(), zero4()};
   if (active) {
     if constexpr (P == P_F64)
       load_cols<NB>(acc, Cw, 0, NB / 16);
     else
       load_cols_lp<NB>(acc, C + static_cast<size_t>(mycol) * NB, 0, NB / 16);
   }
+  wait_vm();
 #pragma unroll 1
   for (int step = 0; step < NB / IB; ++step) {
     const int c0 = trans ? step * IB : NB - IB - step * IB;
@@ -1030,9 +1074,9 @@ __device__ __forceinline__ void unmqr_task(const double* V, const double* T, dou
       prefetch_load<NB, ST_UNIT_LOWER>(pf, V + n0 * NB + n0, NB - n0, n0, T + (n0 / IB) * IB * IB);
     }
     if constexpr (P == P_F64)
-      apply_block<NB, V_UNM>(Vs, ldv, Ts, c0, acc, nullptr, active, trans, wx);
+      apply_block<NB, V_UNM>(Vs, ldv, Ts, c0, acc, nullptr, none, active, trans, wx);
     else
-      apply_block_lp<NB, V_UNM, P>(vl, Ts, c0, acc, nullptr, active, trans, reinterpret_cast<float*>(wx));
+      apply_block_lp<NB, V_UNM, P>(vl, Ts, c0, acc, nullptr, none, active, trans, reinterpret_cast<float*>(wx));
     __syncthreads();
   }
   if (active) {
@@ -1206,9 +1250,12 @@ __device__ __forceinline__ void apply_narrow_task(int kind, const double* V, con
 }
 
 // ---- TSMQR / TTMQR (and application of a pair set to B) --------------------
-template <int NB, int P>
+// TT: 1 for a TT set (triangular V2), 0 for a TS set; a compile-time
+// parameter so that each loop holds the registers of one variant only.
+template <int NB, int P, int TT>
 __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T, double* C1, double* C2, int col0,
-                                              int ncol, double* sm, int tt, int trans) {
+                                              int ncol, double* sm, int trans) {
+  constexpr bool tt = TT != 0;
   constexpr int ldv = Smem<NB>::LDP;
   double* Vs = sm + Smem<NB>::PS;
   double* Ts = sm + Smem<NB>::TS;
@@ -1226,13 +1273,15 @@ __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T,
       prefetch_load<NB, ST_FULL>(pf, V2 + c0 * NB, NB, c0, T + (c0 / IB) * IB * IB);
   }
   unsigned char* vl = reinterpret_cast<unsigned char*>(sm + Smem<NB>::PS);
-  d4 acc[NB / 32];
+  d4 acc[NB / 32], c1v[2];
+  double* c1g = C1 + static_cast<size_t>(mycol) * NB;
   if (active) {
     if constexpr (P == P_F64)
       load_cols<NB>(acc, C2 + off, 0, NB / 16);
     else
       load_cols_lp<NB>(acc, C2 + static_cast<size_t>(mycol) * NB, 0, NB / 16);
   }
+  wait_vm();
 #pragma unroll 1
   for (int step = 0; step < NB / IB; ++step) {
     const int c0 = trans ? step * IB : NB - IB - step * IB;
@@ -1242,6 +1291,12 @@ __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T,
     else
       prefetch_store_lp<NB, P>(pf, vl, K, Ts);
     __syncthreads();
+    // This block's C1 rows before the next block's reflectors (in-order
+    // completion: the C1 wait leaves the prefetch in flight).
+    if constexpr (P == P_F64)
+      load_c1(c1v, C1 + off, c0, active);
+    else
+      load_c1_lp<NB>(c1v, c1g, c0, active);
     if (step + 1 < NB / IB) {
       const int n0 = trans ? c0 + IB : c0 - IB;
       if (tt)
@@ -1251,16 +1306,15 @@ __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T,
     }
     if constexpr (P == P_F64) {
       if (tt)
-        apply_block<NB, V_TT>(Vs, ldv, Ts, c0, acc, C1 + off, active, trans, wx);
+        apply_block<NB, V_TT>(Vs, ldv, Ts, c0, acc, C1 + off, c1v, active, trans, wx);
       else
-        apply_block<NB, V_TS>(Vs, ldv, Ts, c0, acc, C1 + off, active, trans, wx);
+        apply_block<NB, V_TS>(Vs, ldv, Ts, c0, acc, C1 + off, c1v, active, trans, wx);
     } else {
       float* wxf = reinterpret_cast<float*>(wx);
-      double* c1g = C1 + static_cast<size_t>(mycol) * NB;
       if (tt)
-        apply_block_lp<NB, V_TT, P>(vl, Ts, c0, acc, c1g, active, trans, wxf);
+        apply_block_lp<NB, V_TT, P>(vl, Ts, c0, acc, c1g, c1v, active, trans, wxf);
       else
-        apply_block_lp<NB, V_TS, P>(vl, Ts, c0, acc, c1g, active, trans, wxf);
+        apply_block_lp<NB, V_TS, P>(vl, Ts, c0, acc, c1g, c1v, active, trans, wxf);
     }
     __syncthreads();
   }
@@ -1285,13 +1339,19 @@ __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, doub
       break;
     case D_TSQRT:
     case D_TTQRT:
-      pair_qrt_task<NB, P>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm,
-                           s.kind == D_TTQRT);
+      if (s.kind == D_TTQRT)
+        pair_qrt_task<NB, P, 1>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm);
+      else
+        pair_qrt_task<NB, P, 0>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm);
       break;
     case D_TSMQR:
     case D_TTMQR:
-      pair_mqr_task<NB, P>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), tile_ptr(a, s.piv, s.j), tile_ptr(a, s.i, s.j),
-                        s.slab * SLAB, NB, sm, s.kind == D_TTMQR, 1);
+      if (s.kind == D_TTMQR)
+        pair_mqr_task<NB, P, 1>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), tile_ptr(a, s.piv, s.j),
+                                tile_ptr(a, s.i, s.j), s.slab * SLAB, NB, sm, 1);
+      else
+        pair_mqr_task<NB, P, 0>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), tile_ptr(a, s.piv, s.j),
+                                tile_ptr(a, s.i, s.j), s.slab * SLAB, NB, sm, 1);
       break;
     case D_APPLY_GE:
     case D_APPLY_TS:
@@ -1304,8 +1364,12 @@ __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, doub
       {
         double* Bp = a.B + static_cast<size_t>(s.piv) * NB * a.ncolB;
         double* Bi = a.B + static_cast<size_t>(s.i) * NB * a.ncolB;
-        pair_mqr_task<NB, P_F64>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), Bp, Bi, s.slab * SLAB, a.ncolB, sm,
-                                 s.kind == D_APPLY_TT, a.transB);
+        if (s.kind == D_APPLY_TT)
+          pair_mqr_task<NB, P_F64, 1>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), Bp, Bi, s.slab * SLAB, a.ncolB, sm,
+                                      a.transB);
+        else
+          pair_mqr_task<NB, P_F64, 0>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), Bp, Bi, s.slab * SLAB, a.ncolB, sm,
+                                      a.transB);
       }
       break;
     default:
@@ -1496,8 +1560,12 @@ __global__ __launch_bounds__(NTHREADS) void exec_apply(ExecArgs a) {
     } else {
       double* Bp = a.B + static_cast<size_t>(s.piv) * NB * a.ncolB;
       double* Bi = a.B + static_cast<size_t>(s.i) * NB * a.ncolB;
-      pair_mqr_task<NB, P_F64>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), Bp, Bi, s.slab * SLAB, a.ncolB, sm,
-                               kind == D_APPLY_TT, a.transB);
+      if (kind == D_APPLY_TT)
+        pair_mqr_task<NB, P_F64, 1>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), Bp, Bi, s.slab * SLAB, a.ncolB, sm,
+                                    a.transB);
+      else
+        pair_mqr_task<NB, P_F64, 0>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), Bp, Bi, s.slab * SLAB, a.ncolB, sm,
+                                    a.transB);
     }
   });
 }
