@@ -9,12 +9,19 @@ executor launch + triangular solve + iterative refinement to a backward error
 of 1e-12 (the hot path).  The plain FP64 path (the same step without
 refinement) is timed beside it on the same input.
 
+With --tree auto (the default) each precision first runs the exhaustive
+autotuner over a fixed candidate list of (tree, BS, kernel family) at the
+given nb, timing whole steps on the bench input (untimed for the result),
+and the timed region then uses each precision's winner; the FP64 path gets
+the same search.
+
 Throughput counts 2 m n^2 - 2 n^3 / 3 flops per factorization (the
 Householder count, Sec. 2.2 of the paper) per step.  Inputs are resident in
 HBM before the timed region.
 
 Usage: python bench.py [--steps K] [--warmup W] [--upd f32|bf16|f64]
-                       [--workload square|tall] [--kappa K] [--tree greedy]
+                       [--workload square|tall] [--kappa K]
+                       [--tree auto|flat|greedy|...] [--bs BS] [--kern default|tt|ts]
 """
 
 import argparse
@@ -27,6 +34,12 @@ METRIC = "tiled-QR GFLOP/s & % MFMA peak: mixed+refined vs FP64 at equal LS accu
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
 TREES = {"flat": 0, "sameh-kuck": 1, "binary": 2, "fibonacci": 3, "greedy": 4, "plasma": 5}
 UPD = {"f64": 0, "f32": 1, "bf16": 2}
+KERNS = {"default": 0, "tt": 1, "ts": 2}
+# Candidates of the bench's exhaustive autotuner: (tree, BS, kernel family).
+TUNE_CANDIDATES = [("flat", 1, "ts"), ("plasma", 8, "ts"), ("plasma", 16, "ts"), ("plasma", 32, "ts"),
+                   ("greedy", 1, "tt"), ("greedy", 1, "ts"), ("fibonacci", 1, "ts")]
+# Table 1 weights by task kind (GEQRT, UNMQR, TSQRT, TSMQR, TTQRT, TTMQR).
+UNITS = (4, 6, 6, 12, 2, 6)
 
 
 def parse():
@@ -39,7 +52,8 @@ def parse():
     ap.add_argument("--matrix", choices=["conditioned", "gaussian"], default="conditioned",
                     help="square workload: U diag(s) V^T with condition number kappa, or N(0,1) entries")
     ap.add_argument("--upd", choices=list(UPD), default="f32")
-    ap.add_argument("--tree", choices=list(TREES), default="greedy")
+    ap.add_argument("--tree", choices=["auto"] + list(TREES), default="auto")
+    ap.add_argument("--kern", choices=list(KERNS), default="default")
     ap.add_argument("--bs", type=int, default=1)
     ap.add_argument("--nb", type=int, default=256)
     ap.add_argument("--nrhs", type=int, default=4)
@@ -54,16 +68,17 @@ def flops(m, n):
     return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
 
 
-def update_flop_fraction(p, q):
+def update_flop_fraction(p, q, tree, bs, kern):
     """Share of the Table 1 work units spent in update kernels (UNMQR, TSMQR,
-    TTMQR) for TT kernels: total 6pq^2 - 2q^3, panel units GEQRT 4 per
-    triangularized tile and TTQRT 2 per zeroed tile."""
-    total = 6 * p * q * q - 2 * q ** 3
-    panel = sum(4 * (p - k + 1) + 2 * (p - k) for k in range(1, q + 1))
-    return (total - panel) / total
+    TTMQR) in the task list of (tree, BS, kernel family)."""
+    from paper_1104_4475_amd import _lib
+    tasks, _ = _lib.schedule(p, q, tree, bs, kern)
+    units = [UNITS[k] for k in tasks[:, 0]]
+    upd = [UNITS[k] for k in tasks[:, 0] if k in (1, 3, 5)]
+    return sum(upd) / sum(units)
 
 
-def cpu_baseline(nb, tree, bs, kappa):
+def cpu_baseline(nb, tree, bs, kern, kappa):
     """The FP64 oracle (plain NumPy tiled QR) on a bounded sample of the same
     workload: the conditioned matrix at 1792 x 1792 (p = q = 7 tiles of the
     same nb), BLAS limited to one thread."""
@@ -76,10 +91,10 @@ def cpu_baseline(nb, tree, bs, kappa):
     A = tqr_inputs.conditioned(n, kappa, 102, 103)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        tiled.tiled_qr(A, nb, tree, bs)
+        tiled.tiled_qr(A, nb, tree, bs, kern)
         dt = time.perf_counter() - t0
     return {"value": flops(n, n) / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle tiled QR of a %dx%d conditioned matrix (kappa %g), nb=%d, same tree, "
+            "sample": "oracle tiled QR of a %dx%d conditioned matrix (kappa %g), nb=%d, same tree and kernels, "
                       "1 BLAS thread, %.1f s" % (n, n, kappa, nb, dt),
             "seconds": dt, "host_cpus": len(os.sched_getaffinity(0))}
 
@@ -122,26 +137,53 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    tree = TREES[args.tree]
     p, q = m // nb, n // nb
     F = flops(m, n)
 
-    def run(upd, refine):
-        Fh = tqr.factor(A, nb, tree, args.bs, tqr.KERN_DEFAULT, UPD[upd])
-        Fh.sync()
-        tol = args.tol if refine else 0.0
+    def step(Fh, tol):
         # One step: factorization with Q^T B in the same executor launch, then
         # the triangular solve and (mixed) refinement against A.
+        QtB = Fh.refactor_qtb(A, B)
+        return Fh.lstsq(B, A0=A, tol=tol, QtB=QtB)
+
+    def tune(upd, refine):
+        """Exhaustive autotuner over TUNE_CANDIDATES: the best of two timed
+        steps after one warm-up, per candidate."""
+        if args.tree != "auto":
+            return (args.tree, args.bs, args.kern), []
+        tol = args.tol if refine else 0.0
+        table = []
+        for tname, bs, kname in TUNE_CANDIDATES:
+            if bs > p:
+                continue
+            Fh = tqr.factor(A, nb, TREES[tname], bs, KERNS[kname], UPD[upd])
+            step(Fh, tol)
+            best = float("inf")
+            for _ in range(2):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                step(Fh, tol)
+                torch.cuda.synchronize()
+                best = min(best, time.perf_counter() - t0)
+            Fh.sync()
+            del Fh
+            table.append(((tname, bs, kname), round(1e3 * best, 3)))
+        return min(table, key=lambda e: e[1])[0], table
+
+    def run(upd, refine):
+        choice, table = tune(upd, refine)
+        tname, bs, kname = choice
+        Fh = tqr.factor(A, nb, TREES[tname], bs, KERNS[kname], UPD[upd])
+        Fh.sync()
+        tol = args.tol if refine else 0.0
         for _ in range(args.warmup):
-            QtB = Fh.refactor_qtb(A, B)
-            X, info = Fh.lstsq(B, A0=A, tol=tol, QtB=QtB)
+            X, info = step(Fh, tol)
         torch.cuda.synchronize()
         times, execs, infos = [], [], []
         for _ in range(args.steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            QtB = Fh.refactor_qtb(A, B)
-            X, info = Fh.lstsq(B, A0=A, tol=tol, QtB=QtB)
+            X, info = step(Fh, tol)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             execs.append(Fh.exec_ms())
@@ -152,7 +194,8 @@ def main():
                (torch.linalg.norm(A) * torch.linalg.norm(X, dim=0) + torch.linalg.norm(B, dim=0))).max().item()
         return {"ms_per_step": 1e3 * sum(times) / len(times), "exec_ms": sum(execs) / len(execs),
                 "gflops": F / (sum(times) / len(times)) / 1e9, "backward_err": eta,
-                "refine_iters": infos[-1]["iters"], "converged": infos[-1]["converged"], "X": X}
+                "refine_iters": infos[-1]["iters"], "converged": infos[-1]["converged"], "X": X,
+                "choice": choice, "tune": table}
 
     fp64 = run("f64", refine=False)
     main_res = fp64 if args.upd == "f64" else run(args.upd, refine=True)
@@ -160,10 +203,11 @@ def main():
 
     # Dominant kernel: the executor (all tile kernels of the factorization).
     exec_s = main_res["exec_ms"] / 1e3
+    tname, bs, kname = main_res["choice"]
     if args.upd == "f64":
         peak = PEAK_TFLOPS["f64"]
     else:
-        fu = update_flop_fraction(p, q)
+        fu = update_flop_fraction(p, q, TREES[tname], bs, KERNS[kname])
         peak = 1.0 / (fu / PEAK_TFLOPS[args.upd] + (1.0 - fu) / PEAK_TFLOPS["f64"])
     achieved = F / exec_s / 1e12
     line = {
@@ -179,20 +223,26 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.upd == "f64" else "f64 panels/residuals + %s MFMA updates" % args.upd,
         "data": "synthetic",
-        "config": {"workload": workload, "tree": args.tree, "bs": args.bs, "nb": nb, "m": m, "n": n,
-                   "upd": args.upd, "refine_tol": args.tol if args.upd != "f64" else None},
+        "config": {"workload": workload, "tree": tname, "bs": bs, "kernels": kname, "nb": nb, "m": m, "n": n,
+                   "upd": args.upd, "refine_tol": args.tol if args.upd != "f64" else None,
+                   "tuned": args.tree == "auto"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4), "traffic": None,
                      "kernel": "exec_persistent<%d>" % nb, "kernel_ms": round(main_res["exec_ms"], 3)},
         "fp64": {"gflops": round(fp64["gflops"], 2), "ms_per_step": round(fp64["ms_per_step"], 3),
                  "exec_ms": round(fp64["exec_ms"], 3), "backward_err": fp64["backward_err"],
+                 "tree": "%s bs %d %s" % fp64["choice"],
                  "frac_fp64_peak": round(F / (fp64["exec_ms"] / 1e3) / 1e12 / PEAK_TFLOPS["f64"], 4)},
         "speedup_vs_fp64": round(main_res["gflops"] / fp64["gflops"], 3),
         "accuracy": {"backward_err": main_res["backward_err"], "refine_iters": main_res["refine_iters"],
                      "converged": main_res["converged"], "fwd_diff_vs_fp64": fwd},
     }
+    if args.tree == "auto":
+        line["autotune_ms_per_step"] = {"fp64": {"%s bs %d %s" % c: t for c, t in fp64["tune"]}}
+        if args.upd != "f64":
+            line["autotune_ms_per_step"][args.upd] = {"%s bs %d %s" % c: t for c, t in main_res["tune"]}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(nb, tree, args.bs, args.kappa)
+        line["cpu_baseline"] = cpu_baseline(nb, TREES[tname], bs, KERNS[kname], args.kappa)
     print(json.dumps(line), flush=True)
 
 

@@ -155,7 +155,8 @@ int tiledqr_destroy(tqr_factors* F);
 typedef struct {
   double tol;        /* target backward error (e.g. 1e-12); <= 0: no refinement */
   int32_t max_iter;  /* refinement iterations (default 30 if <= 0)          */
-  int32_t method;    /* 0 auto, 1 classical (square), 2 augmented system    */
+  int32_t method;    /* 0 auto, 1 classical (square), 2 augmented system,
+                        3 semi-normal corrections (square)                  */
 } tqr_refine;
 
 typedef struct {      /* host memory, filled by tiledqr_lstsq */
@@ -168,8 +169,13 @@ typedef struct {      /* host memory, filled by tiledqr_lstsq */
  * (Sec. 1: x = R^{-1} (Q^T b)(1:n)).  When r != NULL and r->tol > 0 the
  * solution is refined with FP64 residuals computed on the GPU against the
  * original matrix A0 (device, m x n, lda >= m), which the caller keeps
- * unchanged until the call returns.  Square systems use classical
- * refinement x <- x + R^{-1} Q^T (b - A0 x); tall systems refine the
+ * unchanged until the call returns.  Square systems refine
+ * x <- x + R^{-1} c with c = Q^T (b - A0 x) (classical, method 1) or
+ * c = R^{-T} A0^T (b - A0 x) (semi-normal, method 3: R^{-T} A0^T equals Q^T
+ * for A0 = QR and costs two products with A0 and one more triangular solve
+ * instead of an application of Q^T); method 0 takes semi-normal steps
+ * while each one cuts the backward error at least fourfold, then (after
+ * undoing a step that raised it) classical ones.  Tall systems refine the
  * augmented system [I A0; A0^T 0][r; x] = [b; 0] (Bjorck 1967) with the same
  * factors: residuals f = b - r - A0 x and g = -A0^T r in FP64, corrections
  * h = R^{-T} g, d = Q^T f, dx = R^{-1}(d(1:n) - h), dr = Q [h; d(n+1:m)].

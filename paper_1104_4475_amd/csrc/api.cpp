@@ -167,6 +167,11 @@ struct tqr_factors {
   DevPlan fused;           // factorization + Q^T B (16 columns) in one executor plan
   double* Bt16 = nullptr;  // packed right-hand sides of the joint plan (p row tiles of nb x 16)
   mutable int32_t solve_epoch = 0;  // advanced by every triangular solve launch
+  mutable double* rinv = nullptr;   // inverses of the q diagonal tiles of R
+  mutable bool rinv_ok = false;     // rinv matches the current factors
+  mutable double* rt = nullptr;     // tiles of R^T (q x q grid, lower part)
+  mutable double* rinvt = nullptr;  // transposes of the diagonal-tile inverses
+  mutable bool rt_ok = false;       // rt, rinvt match the current factors
   hipStream_t stream = nullptr;
   int grid = 1;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -180,6 +185,9 @@ struct tqr_factors {
     exec.release();
     fused.release();
     if (Bt16) (void)hipFree(Bt16);
+    if (rinv) (void)hipFree(rinv);
+    if (rt) (void)hipFree(rt);
+    if (rinvt) (void)hipFree(rinvt);
     for (auto& kv : apply) kv.second.release();
     if (tiles) (void)hipFree(tiles);
     if (Tg) (void)hipFree(Tg);
@@ -261,13 +269,68 @@ ExecArgs base_args(const tqr_factors* F, const DevPlan& d) {
   return a;
 }
 
+// Inverses of the diagonal tiles of R for the triangular solves, computed
+// once per factorization (nullptr with TQR_TRSM_SUBST=1: substitution inside
+// the diagonal tiles).
+const double* diag_inverses(const tqr_factors* F, hipStream_t s, hipError_t* e) {
+  *e = hipSuccess;
+  const char* sub = std::getenv("TQR_TRSM_SUBST");
+  if (sub && sub[0] == '1') return nullptr;
+  if (F->rinv_ok) return F->rinv;
+  if (!F->rinv) {
+    *e = hipMalloc(&F->rinv, static_cast<size_t>(F->q) * F->nb * F->nb * sizeof(double));
+    if (*e != hipSuccess) {
+      F->rinv = nullptr;
+      return nullptr;
+    }
+  }
+  *e = tqr::launch_trinv(F->tiles, F->p, F->q, F->nb, F->rinv, s);
+  F->rinv_ok = *e == hipSuccess;
+  return F->rinv;
+}
+
 // X <- R^{-1} X (n x nrhs, in place) with the handle's tiled R.
 hipError_t solve_r(const tqr_factors* F, double* X, int64_t ldx, int64_t nrhs, hipStream_t s) {
-  return tqr::launch_trsm_upper(F->tiles, F->p, F->q, F->nb, X, ldx, nrhs, F->ctl + 3, &F->solve_epoch, F->ctl + 2,
-                                4 * wall_ticks_per_second(), s);
+  hipError_t e;
+  const double* ri = diag_inverses(F, s, &e);
+  if (e != hipSuccess) return e;
+  return tqr::launch_trsm_upper(F->tiles, ri, F->p, F->q, F->nb, X, ldx, nrhs, F->ctl + 3, &F->solve_epoch,
+                                F->ctl + 2, 4 * wall_ticks_per_second(), s);
+}
+
+// X <- R^{-T} X (n x nrhs, in place), from the transposed tiles of R and
+// of the diagonal inverses (made once per factorization) so that every
+// load of the solve is coalesced.
+hipError_t solve_rt(const tqr_factors* F, double* X, int64_t ldx, int64_t nrhs, hipStream_t s) {
+  hipError_t e;
+  const double* ri = diag_inverses(F, s, &e);
+  if (e != hipSuccess) return e;
+  if (ri && !F->rt_ok) {
+    const size_t tile = static_cast<size_t>(F->nb) * F->nb;
+    if (!F->rt) {
+      e = hipMalloc(&F->rt, static_cast<size_t>(F->q) * F->q * tile * sizeof(double));
+      if (e != hipSuccess) {
+        F->rt = nullptr;
+        return e;
+      }
+    }
+    if (!F->rinvt) {
+      e = hipMalloc(&F->rinvt, static_cast<size_t>(F->q) * tile * sizeof(double));
+      if (e != hipSuccess) {
+        F->rinvt = nullptr;
+        return e;
+      }
+    }
+    e = tqr::launch_transpose_r(F->tiles, ri, F->p, F->q, F->nb, F->rt, F->rinvt, s);
+    if (e != hipSuccess) return e;
+    F->rt_ok = true;
+  }
+  return tqr::launch_trsm_upper_t(F->tiles, ri ? F->rt : nullptr, ri ? F->rinvt : nullptr, F->p, F->q, F->nb, X, ldx,
+                                  nrhs, F->ctl + 3, &F->solve_epoch, F->ctl + 2, 4 * wall_ticks_per_second(), s);
 }
 
 int run_plan(tqr_factors* F, DevPlan& d, ExecArgs a, hipStream_t s) {
+  if (&d == &F->exec || &d == &F->fused) F->rinv_ok = F->rt_ok = false;  // the factors change
   if (d.nsub == 0) return TQR_OK;
   a.epoch = ++d.epoch;
   if (use_level_path()) {
@@ -459,8 +522,7 @@ int refine_augmented(const tqr_factors* F, const double* A0, int64_t lda, const 
     // f = b - A x - r (in Rv), h = R^{-T} (-A^T r)
     if (!hip_ok(tqr::launch_axpy_cols(Rv, m, Rr, m, m, nrhs, s, -1.0)) ||
         !hip_ok(tqr::launch_gemv_t(A0, lda, m, n, Rr, m, nrhs, H, n, -1.0, s)) ||
-        !hip_ok(tqr::launch_trsm_upper_t(F->tiles, F->p, F->q, F->nb, H, n, nrhs, F->ctl + 3, &F->solve_epoch,
-                                         F->ctl + 2, 4 * wall_ticks_per_second(), s)))
+        !hip_ok(solve_rt(F, H, n, nrhs, s)))
       return done(TQR_EHIP);
     // d = Q^T f (packed), Z = d
     if (!hip_ok(tqr::launch_pack_b(Rv, m, nrhs, Bt, F->p, F->nb, ncolB, s))) return done(TQR_EHIP);
@@ -747,13 +809,14 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
   const int64_t m = F->o.m, n = F->o.n;
   const int ncolB = static_cast<int>((nrhs + 15) / 16 * 16);
   const size_t bt_elems = static_cast<size_t>(F->p) * F->nb * ncolB;
-  double *Bt = nullptr, *Rv = nullptr, *D = nullptr, *nrm = nullptr;
+  double *Bt = nullptr, *Rv = nullptr, *D = nullptr, *nrm = nullptr, *Xp = nullptr;
   int st = TQR_OK;
   auto fail = [&](int code) {
     if (Bt) (void)hipFreeAsync(Bt, s);
     if (Rv) (void)hipFreeAsync(Rv, s);
     if (D) (void)hipFreeAsync(D, s);
     if (nrm) (void)hipFreeAsync(nrm, s);
+    if (Xp) (void)hipFreeAsync(Xp, s);
     return code;
   };
   if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Bt), bt_elems * sizeof(double), s))) return fail(TQR_ENOMEM);
@@ -783,8 +846,13 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
   const size_t rv_elems = static_cast<size_t>(m) * nrhs;
   if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Rv), rv_elems * sizeof(double), s)) ||
       !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&D), static_cast<size_t>(n) * nrhs * sizeof(double), s)) ||
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Xp), static_cast<size_t>(n) * nrhs * sizeof(double), s)) ||
       !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&nrm), (3 * nrhs + 1) * sizeof(double), s)))
     return fail(TQR_ENOMEM);
+  // Corrections: semi-normal (method 3, and method 0 while each one cuts
+  // the backward error at least fourfold) or classical with Q (method 1,
+  // and method 0 from then on).
+  bool semi = r->method == 0 || r->method == 3;
   // ||A||_F^2 and ||b||^2 once.
   double* nA = nrm + 3 * nrhs;
   if (!hip_ok(hipMemsetAsync(nrm, 0, (3 * nrhs + 1) * sizeof(double), s))) return fail(TQR_EHIP);
@@ -832,8 +900,29 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
       conv = true;
       break;
     }
+    if (semi && r->method == 0 && hist.size() >= 2 && eta > 0.25 * hist[hist.size() - 2]) {
+      semi = false;
+      if (eta > hist[hist.size() - 2]) {
+        // The last semi-normal step did not help: back to its starting
+        // point, then classical corrections.
+        hist.pop_back();
+        eta = hist.back();
+        if (!hip_ok(tqr::launch_copy_cols(Xp, n, X, ldx, n, nrhs, s))) return fail(TQR_EHIP);
+        continue;
+      }
+    }
     if (it >= max_iter) break;
     if (hist.size() > 3 && hist.back() > 0.5 * hist[hist.size() - 4]) break;
+    if (semi) {
+      // Semi-normal correction D = R^{-1} R^{-T} A^T Rv (A = QR gives
+      // R^{-T} A^T = Q^T); X += D.
+      if (r->method == 0 && !hip_ok(tqr::launch_copy_cols(X, ldx, Xp, n, n, nrhs, s))) return fail(TQR_EHIP);
+      if (!hip_ok(tqr::launch_gemv_t(A0, lda, m, n, Rv, m, nrhs, D, n, 1.0, s)) ||
+          !hip_ok(solve_rt(F, D, n, nrhs, s)) || !hip_ok(solve_r(F, D, n, nrhs, s)) ||
+          !hip_ok(tqr::launch_axpy_cols(X, ldx, D, n, n, nrhs, s)))
+        return fail(TQR_EHIP);
+      continue;
+    }
     // correction D = R^{-1} (Q^T Rv)(1:n); X += D
     if (!hip_ok(tqr::launch_pack_b(Rv, m, nrhs, Bt, F->p, F->nb, ncolB, s))) return fail(TQR_EHIP);
     st = apply_tiles(F, 1, Bt, ncolB, s);

@@ -81,14 +81,27 @@ hipError_t launch_pack_b(const double* B, int64_t ldb, int64_t nrhs, double* Bt,
                          hipStream_t s);
 hipError_t launch_unpack_b(const double* Bt, double* B, int64_t ldb, int64_t nrhs, int rows, int nb, int ncolB,
                            hipStream_t s);
-// X = R^{-1} Y in place (Y: n x nrhs, column-major).  flags: q int32 owned
-// by the caller, compared with the per-launch epoch (*epoch is advanced);
-// err: set when a wait exceeds spin_ticks.
-hipError_t launch_trsm_upper(const double* tiles, int p, int q, int nb, double* Y, int64_t ldy, int64_t nrhs,
-                             int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks, hipStream_t s);
-// X = R^{-T} Y in place (same conventions).
-hipError_t launch_trsm_upper_t(const double* tiles, int p, int q, int nb, double* Y, int64_t ldy, int64_t nrhs,
-                               int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks, hipStream_t s);
+// X = R^{-1} Y in place (Y: n x nrhs, column-major).  Rinv: inverses of
+// the q diagonal tiles from launch_trinv, or null (substitution inside the
+// diagonal tiles).  flags: q int32 owned by the caller, compared with the
+// per-launch epoch (*epoch is advanced); err: set when a wait exceeds
+// spin_ticks.
+hipError_t launch_trsm_upper(const double* tiles, const double* Rinv, int p, int q, int nb, double* Y, int64_t ldy,
+                             int64_t nrhs, int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks,
+                             hipStream_t s);
+// X = R^{-T} Y in place (same conventions).  Rt: the tiles of R^T from
+// launch_transpose_r with Rinv then the transposed inverses, or null
+// (transposed reads of R and Rinv).
+hipError_t launch_trsm_upper_t(const double* tiles, const double* Rt, const double* Rinv, int p, int q, int nb,
+                               double* Y, int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch, int32_t* err,
+                               int64_t spin_ticks, hipStream_t s);
+// Rt (q x q tile grid, tiles (i, k) with k <= i) = tiles of R^T, and RinvT
+// (q tiles) = transposes of the diagonal-tile inverses Rinv.
+hipError_t launch_transpose_r(const double* tiles, const double* Rinv, int p, int q, int nb, double* Rt,
+                              double* RinvT, hipStream_t s);
+// Rinv (q tiles of nb x nb, column-major) = inverses of the diagonal tiles
+// R_ii of the tiled R.
+hipError_t launch_trinv(const double* tiles, int p, int q, int nb, double* Rinv, hipStream_t s);
 // out (n x nrhs, ldo) = sign * A^T Y for A m x n (lda), Y m x nrhs (ldy).
 hipError_t launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* Y, int64_t ldy,
                          int64_t nrhs, double* out, int64_t ldo, double sign, hipStream_t s);

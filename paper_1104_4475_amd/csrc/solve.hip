@@ -89,105 +89,147 @@ __device__ __forceinline__ void tr_update(double* ys, const double* xs, const do
   }
 }
 
-// X = R^{-1} Y (TRANS = false) or X = R^{-T} Y (TRANS = true) in place in Y
-// (rows i nb .. i nb + nb - 1 of tile row i), with the tiled upper
-// triangular R (tiles (i, k), i <= k < q).  One workgroup per tile row,
-// ordered so that a workgroup only waits for workgroups with smaller
-// indices (already running): block b takes row q - 1 - b (back
-// substitution) or row b (forward substitution with R^T).  Row i applies
-// Y_i -= op(R)_ik X_k for every solved X_k (flag k set to the launch's
-// epoch), then solves its diagonal tile: 32-row blocks, each multiplied by
-// the inverse of its 32 x 32 diagonal block (computed by wave b before any
-// wait, by back substitution on the identity) and subtracted from the rest
-// of the tile by all waves.  Up to TR_COLS right-hand sides per launch.  A
-// wait longer than spin_ticks sets *err and the workgroup leaves.
+// Whole-tile product ys[c * NB + r] -= sum_l op(M)[r][l] xs[c * NB + l]
+// for all NB rows and columns c < nc, with coalesced loads of M:
+//   op(M) = M:   wave w takes the tile columns l = w + 8 t (contiguous in
+//                memory, lanes over rows), accumulates its partial sums for
+//                every row and the 8 partials meet in ps (4 right-hand sides
+//                per pass);
+//   op(M) = M^T: wave w takes the output rows r = w + 8 t, whose entries are
+//                tile column r (lanes over l), and reduces across the wave.
+// Loads are issued TB columns at a time before their use.  Contains
+// barriers: every thread calls it.
 template <int NB, bool TRANS>
-__global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* tiles, int p, int q, double* Y,
-                                                               int64_t ldy, int nc, int32_t* flags, int32_t epoch,
-                                                               int64_t spin_ticks, int32_t* err) {
-  __shared__ double ys[NB * TR_COLS];
-  __shared__ double xs[NB * TR_COLS];
-  __shared__ double ps[TR_THREADS * TR_COLS];  // partial sums of tr_update; block inverses for TRANS
-  __shared__ int s_abort;
-  const int i = TRANS ? static_cast<int>(blockIdx.x) : q - 1 - static_cast<int>(blockIdx.x);
-  const int tid = threadIdx.x;
-  const int64_t r0 = static_cast<int64_t>(i) * NB;
-  for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
-    const int c = e / NB, r = e % NB;
-    ys[e] = c < nc ? Y[c * ldy + r0 + r] : 0.0;
+__device__ __forceinline__ void tile_gemv(double* ys, const double* xs, const double* M, int nc, double* ps) {
+  constexpr int RJ = NB >= 64 ? NB / 64 : 1;  // entries of a column per lane
+  constexpr int NW = TR_THREADS / 64;         // waves
+  constexpr int PER = NB / NW;                // columns (rows for M^T) per wave
+  constexpr int TB = PER < 8 ? PER : 8;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  for (int c0 = 0; c0 < nc; c0 += 4) {
+    if (!TRANS) {
+      double acc[RJ][4];
+#pragma unroll
+      for (int j = 0; j < RJ; ++j)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[j][c] = 0.0;
+      for (int t0 = 0; t0 < PER; t0 += TB) {
+        double m[TB][RJ];
+#pragma unroll
+        for (int b = 0; b < TB; ++b)
+#pragma unroll
+          for (int j = 0; j < RJ; ++j) {
+            const int r = lane + 64 * j;
+            m[b][j] = r < NB ? M[static_cast<size_t>(w + NW * (t0 + b)) * NB + r] : 0.0;
+          }
+#pragma unroll
+        for (int b = 0; b < TB; ++b) {
+          const int l = w + NW * (t0 + b);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const double x = (c0 + c < nc) ? xs[(c0 + c) * NB + l] : 0.0;
+#pragma unroll
+            for (int j = 0; j < RJ; ++j) acc[j][c] += m[b][j] * x;
+          }
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < RJ; ++j) {
+        const int r = lane + 64 * j;
+        if (r < NB) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) ps[(w * 4 + c) * NB + r] = acc[j][c];
+        }
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < 4 * NB; e += TR_THREADS) {
+        const int c = e / NB, r = e % NB;
+        if (c0 + c < nc) {
+          double t = 0.0;
+#pragma unroll
+          for (int v = 0; v < NW; ++v) t += ps[(v * 4 + c) * NB + r];
+          ys[(c0 + c) * NB + r] -= t;
+        }
+      }
+      __syncthreads();
+    } else {
+      for (int t0 = 0; t0 < PER; t0 += TB) {
+        double m[TB][RJ];
+#pragma unroll
+        for (int b = 0; b < TB; ++b)
+#pragma unroll
+          for (int j = 0; j < RJ; ++j) {
+            const int l = lane + 64 * j;
+            m[b][j] = l < NB ? M[static_cast<size_t>(w + NW * (t0 + b)) * NB + l] : 0.0;
+          }
+#pragma unroll
+        for (int b = 0; b < TB; ++b) {
+          const int r = w + NW * (t0 + b);
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            if (c0 + c >= nc) continue;
+            double part = 0.0;
+#pragma unroll
+            for (int j = 0; j < RJ; ++j) {
+              const int l = lane + 64 * j;
+              if (l < NB) part += m[b][j] * xs[(c0 + c) * NB + l];
+            }
+            for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+            if (lane == 0) ys[(c0 + c) * NB + r] -= part;
+          }
+        }
+      }
+      __syncthreads();
+    }
   }
-  if (tid == 0) s_abort = 0;
-  // Inverse of diagonal block w (32 x 32, upper triangular) of R_ii on wave
-  // w: lane (rr, half) ends with row rr of the inverse (both halves alike);
-  // with TRANS, with row rr of the inverse's transpose.
-  const double* Rd = tiles + (static_cast<size_t>(i) * p + i) * NB * NB;
-  const int lane = tid & 63, rr = lane & 31, half = lane >> 5;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  double xinv[32];
+}
+
+// Inverse of diagonal block w (32 x 32, upper triangular) of the tile Rd
+// on wave w < NB / 32: lane (rr, half) ends with row rr of the inverse
+// (both halves alike); with TRANS, with row rr of the inverse's transpose
+// (tb: 32 x 32 doubles of LDS per wave for the transposition).  Other waves
+// keep the identity.
+template <int NB, bool TRANS>
+__device__ __forceinline__ void block_inverse(const double* Rd, int wave, int rr, int half, double (&xinv)[32],
+                                              double* tb) {
 #pragma unroll
   for (int c = 0; c < 32; ++c) xinv[c] = (c == rr) ? 1.0 : 0.0;
-  if (wave < NB / 32) {
-    const int base = 32 * wave;
-    double ur[32];
+  if (wave >= NB / 32) return;
+  const int base = 32 * wave;
+  double ur[32];
 #pragma unroll
-    for (int l = 0; l < 32; ++l) ur[l] = Rd[static_cast<size_t>(base + l) * NB + base + rr];
+  for (int l = 0; l < 32; ++l) ur[l] = Rd[static_cast<size_t>(base + l) * NB + base + rr];
 #pragma unroll
-    for (int st = 31; st >= 0; --st) {
-      if (rr == st) {
-        const double d = 1.0 / ur[st];
+  for (int st = 31; st >= 0; --st) {
+    if (rr == st) {
+      const double d = 1.0 / ur[st];
 #pragma unroll
-        for (int c = st; c < 32; ++c) xinv[c] *= d;
-      }
-#pragma unroll
-      for (int c = st; c < 32; ++c) {
-        const double v = readlane_d(xinv[c], st);
-        if (rr < st) xinv[c] -= ur[st] * v;
-      }
+      for (int c = st; c < 32; ++c) xinv[c] *= d;
     }
-    if (TRANS) {
-      double* tb = ps + wave * 32 * 32;
-      if (half == 0) {
 #pragma unroll
-        for (int c = 0; c < 32; ++c) tb[c * 32 + rr] = xinv[c];  // tb[c][rr] = inv[rr][c]
-      }
-      __builtin_amdgcn_wave_barrier();
-#pragma unroll
-      for (int c = 0; c < 32; ++c) xinv[c] = tb[rr * 32 + c];  // inv[c][rr]
+    for (int c = st; c < 32; ++c) {
+      const double v = readlane_d(xinv[c], st);
+      if (rr < st) xinv[c] -= ur[st] * v;
     }
   }
-  __syncthreads();
-  const int k_first = TRANS ? 0 : q - 1;
-  const int k_end = TRANS ? i : i;
-  for (int k = k_first; TRANS ? (k < k_end) : (k > k_end); k += TRANS ? 1 : -1) {
-    if (tid == 0) {
-      const uint64_t t0 = wall_clock64();
-      while (__hip_atomic_load(flags + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-            static_cast<int64_t>(wall_clock64() - t0) > spin_ticks) {
-          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          s_abort = 1;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
+  if (TRANS) {
+    if (half == 0) {
+#pragma unroll
+      for (int c = 0; c < 32; ++c) tb[c * 32 + rr] = xinv[c];  // tb[c][rr] = inv[rr][c]
     }
-    __syncthreads();
-    if (__builtin_amdgcn_readfirstlane(s_abort)) return;
-    const int64_t k0 = static_cast<int64_t>(k) * NB;
-    for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
-      const int c = e / NB, r = e % NB;
-      xs[e] = c < nc ? ld_coh(Y + c * ldy + k0 + r) : 0.0;
-    }
-    __syncthreads();
-    // op(R)_ik: R_ik = tile (i, k) for the upper solve; (R_ki)^T for R^T.
-    const double* R = TRANS ? tiles + (static_cast<size_t>(i) * p + k) * NB * NB
-                            : tiles + (static_cast<size_t>(k) * p + i) * NB * NB;
-    tr_update<NB, TRANS>(ys, xs, R, 0, NB, 0, NB, nc, ps);
-    __syncthreads();
+    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int c = 0; c < 32; ++c) xinv[c] = tb[rr * 32 + c];  // inv[c][rr]
   }
-  // Diagonal tile, 32-row blocks (from the bottom for R, from the top for
-  // R^T): x_b = inv(op(R_bb)) y_b on wave b, then subtracted from the rows
-  // still to solve.
+}
+
+// Solve op(R_d) X = Y in place in ys (nc columns, NB rows) with the block
+// inverses of block_inverse: 32-row blocks from the bottom for R, from the
+// top for R^T; x_b = inv(op(R_bb)) y_b on wave b, then subtracted from the
+// rows still to solve by all waves.  Contains barriers.
+template <int NB, bool TRANS>
+__device__ __forceinline__ void diag_solve(double* ys, const double* Rd, const double (&xinv)[32], double* ps, int nc,
+                                           int wave, int rr, int half) {
   for (int s = 0; s < NB / 32; ++s) {
     const int b = TRANS ? s : NB / 32 - 1 - s;
     const int base = 32 * b;
@@ -214,30 +256,184 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
       __syncthreads();
     }
   }
+}
+
+// Inverses of the diagonal tiles of the tiled upper triangular R: block
+// (i, c) writes columns 16 c .. 16 c + 15 of inv(R_ii) (zero below the
+// diagonal) into tile i of Rinv (q tiles of NB x NB, column-major), by the
+// solve of R_ii X = I restricted to those columns.
+template <int NB>
+__global__ __launch_bounds__(TR_THREADS) void trinv_kernel(const double* tiles, int p, double* Rinv) {
+  __shared__ double ys[NB * TR_COLS];
+  __shared__ double ps[TR_THREADS * TR_COLS];
+  const int i = blockIdx.x, c0 = blockIdx.y * TR_COLS;
+  const int tid = threadIdx.x, lane = tid & 63, rr = lane & 31, half = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
     const int c = e / NB, r = e % NB;
-    if (c < nc) st_coh(Y + c * ldy + r0 + r, ys[e]);
+    ys[e] = (r == c0 + c) ? 1.0 : 0.0;
+  }
+  const double* Rd = tiles + (static_cast<size_t>(i) * p + i) * NB * NB;
+  double xinv[32];
+  block_inverse<NB, false>(Rd, wave, rr, half, xinv, ps + wave * 32 * 32);
+  __syncthreads();
+  diag_solve<NB, false>(ys, Rd, xinv, ps, TR_COLS, wave, rr, half);
+  double* out = Rinv + static_cast<size_t>(i) * NB * NB + static_cast<size_t>(c0) * NB;
+  for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) out[e] = ys[e];
+}
+
+// X = R^{-1} Y (TRANS = false) or X = R^{-T} Y (TRANS = true) in place in Y
+// (rows i nb .. i nb + nb - 1 of tile row i), with the tiled upper
+// triangular R (tiles (i, k), i <= k < q).  One workgroup per tile row,
+// ordered so that a workgroup only waits for workgroups with smaller
+// indices (already running): block b takes row q - 1 - b (back
+// substitution) or row b (forward substitution with R^T).  Row i applies
+// Y_i -= op(R)_ik X_k for every solved X_k (flag k set to the launch's
+// epoch), then solves its diagonal tile: with Rinv (the inverses of the
+// diagonal tiles from trinv_kernel) as one product X_i = op(inv(R_ii)) Y_i,
+// else by diag_solve.  With TRANS and Rt (the tiles of R^T, from
+// launch_transpose_r: tile (i, k), k <= i, of a q x q tile grid) the
+// products read Rt and Rinv = the transposed inverses without transposition,
+// so every load is coalesced.  Up to TR_COLS right-hand sides per launch.  A
+// wait longer than spin_ticks sets *err and the workgroup leaves.
+template <int NB, bool TRANS>
+__global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* tiles, const double* Rt,
+                                                               const double* Rinv, int p, int q, double* Y,
+                                                               int64_t ldy, int nc, int32_t* flags, int32_t epoch,
+                                                               int64_t spin_ticks, int32_t* err) {
+  __shared__ double ys[NB * TR_COLS];
+  __shared__ double xs[NB * TR_COLS];
+  __shared__ double ps[TR_THREADS * TR_COLS];  // partial sums of tr_update; block inverses for TRANS
+  __shared__ int s_abort;
+  const int i = TRANS ? static_cast<int>(blockIdx.x) : q - 1 - static_cast<int>(blockIdx.x);
+  const int tid = threadIdx.x;
+  const int64_t r0 = static_cast<int64_t>(i) * NB;
+  for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
+    const int c = e / NB, r = e % NB;
+    ys[e] = c < nc ? Y[c * ldy + r0 + r] : 0.0;
+  }
+  if (tid == 0) s_abort = 0;
+  const double* Rd = tiles + (static_cast<size_t>(i) * p + i) * NB * NB;
+  const int lane = tid & 63, rr = lane & 31, half = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double xinv[32];
+  if (!Rinv) block_inverse<NB, TRANS>(Rd, wave, rr, half, xinv, ps + wave * 32 * 32);
+  __syncthreads();
+  const int k_first = TRANS ? 0 : q - 1;
+  const int k_end = TRANS ? i : i;
+  for (int k = k_first; TRANS ? (k < k_end) : (k > k_end); k += TRANS ? 1 : -1) {
+    if (tid == 0) {
+      const uint64_t t0 = wall_clock64();
+      while (__hip_atomic_load(flags + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            static_cast<int64_t>(wall_clock64() - t0) > spin_ticks) {
+          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_abort = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_abort)) return;
+    const int64_t k0 = static_cast<int64_t>(k) * NB;
+    for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
+      const int c = e / NB, r = e % NB;
+      xs[e] = c < nc ? ld_coh(Y + c * ldy + k0 + r) : 0.0;
+    }
+    __syncthreads();
+    // op(R)_ik: R_ik = tile (i, k) for the upper solve; (R_ki)^T for R^T.
+    if (TRANS && Rt) {
+      tile_gemv<NB, false>(ys, xs, Rt + (static_cast<size_t>(k) * q + i) * NB * NB, nc, ps);
+    } else {
+      const double* R = TRANS ? tiles + (static_cast<size_t>(i) * p + k) * NB * NB
+                              : tiles + (static_cast<size_t>(k) * p + i) * NB * NB;
+      tile_gemv<NB, TRANS>(ys, xs, R, nc, ps);
+    }
+  }
+  double sign = 1.0;
+  if (Rinv) {
+    // xs = Y_i, ys = -op(inv(R_ii)) Y_i.
+    for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
+      xs[e] = ys[e];
+      ys[e] = 0.0;
+    }
+    __syncthreads();
+    if (TRANS && Rt)
+      tile_gemv<NB, false>(ys, xs, Rinv + static_cast<size_t>(i) * NB * NB, nc, ps);
+    else
+      tile_gemv<NB, TRANS>(ys, xs, Rinv + static_cast<size_t>(i) * NB * NB, nc, ps);
+    sign = -1.0;
+  } else {
+    diag_solve<NB, TRANS>(ys, Rd, xinv, ps, nc, wave, rr, half);
+  }
+  for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
+    const int c = e / NB, r = e % NB;
+    if (c < nc) st_coh(Y + c * ldy + r0 + r, sign * ys[e]);
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (tid == 0) __hip_atomic_store(flags + i, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Aty[c * n + j] = sign * sum_r A[j * lda + r] Y[c * ldy + r] for j < n,
-// c < nrhs: one wave per (column j, right-hand side c), lanes over rows.
+// Tile transposes for the R^T solve: block (a, b), a >= b, writes
+// dst tile (a, b) of a q x q grid = (src tile (b, a) of a p-row grid)^T;
+// with diag, block (i, 0) writes dst tile i = (src tile i)^T (single tiles
+// laid out one after the other).  64 x 64 sub-blocks through LDS.
+template <int NB>
+__global__ __launch_bounds__(256) void transpose_tiles_kernel(const double* src, int p, int q, double* dst, int diag) {
+  __shared__ double buf[64][65];
+  const int a = blockIdx.x, b = blockIdx.y;
+  const double* S;
+  double* D;
+  if (diag) {
+    if (b != 0) return;
+    S = src + static_cast<size_t>(a) * NB * NB;
+    D = dst + static_cast<size_t>(a) * NB * NB;
+  } else {
+    if (a < b) return;
+    S = src + (static_cast<size_t>(a) * p + b) * NB * NB;
+    D = dst + (static_cast<size_t>(b) * q + a) * NB * NB;
+  }
+  constexpr int SB = NB < 64 ? NB : 64;
+  const int tx = threadIdx.x % SB, ty = threadIdx.x / SB;
+  constexpr int RY = 256 / SB;
+  for (int r0 = 0; r0 < NB; r0 += SB)
+    for (int c0 = 0; c0 < NB; c0 += SB) {
+      // buf[c][r] = S[r0 + r][c0 + c] (column-major S: (r, c) at c * NB + r).
+      for (int c = ty; c < SB; c += RY) buf[c][tx] = S[static_cast<size_t>(c0 + c) * NB + r0 + tx];
+      __syncthreads();
+      // D[c0 + c][r0 + r] = S[r0 + r][c0 + c]: D column r0 + r, row c0 + c.
+      for (int r = ty; r < SB; r += RY) D[static_cast<size_t>(r0 + r) * NB + c0 + tx] = buf[tx][r];
+      __syncthreads();
+    }
+}
+
+// out[c * ldo + j] = sign * sum_r A[j * lda + r] Y[c * ldy + r] for j < n,
+// c < nrhs: one wave per column j (read once per 4 right-hand sides), lanes
+// over rows.
 __global__ __launch_bounds__(256) void gemv_t_kernel(const double* A, int64_t lda, int64_t m, int64_t n,
                                                      const double* Y, int64_t ldy, int64_t nrhs, double* out,
                                                      int64_t ldo, double sign) {
-  const int64_t w = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t j = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const int lane = threadIdx.x & 63;
-  if (w >= n * nrhs) return;
-  const int64_t j = w % n, c = w / n;
+  if (j >= n) return;
   const double* a = A + j * lda;
-  const double* y = Y + c * ldy;
-  double s = 0.0;
-  for (int64_t r = lane; r < m; r += 64) s += a[r] * y[r];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  if (lane == 0) out[c * ldo + j] = sign * s;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += 4) {
+    double s[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t r = lane; r < m; r += 64) {
+      const double v = a[r];
+#pragma unroll
+      for (int h = 0; h < 4; ++h)
+        if (c0 + h < nrhs) s[h] += v * Y[(c0 + h) * ldy + r];
+    }
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      double t = s[h];
+      for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+      if (lane == 0 && c0 + h < nrhs) out[(c0 + h) * ldo + j] = sign * t;
+    }
+  }
 }
 
 // Rv = B - A X for m x n A; grid (row blocks, column chunks), partial sums
@@ -311,37 +507,71 @@ int grid_of(int64_t total) {
 }  // namespace
 
 template <bool TRANS>
-static hipError_t trsm_launch(const double* tiles, int p, int q, int nb, double* Y, int64_t ldy, int64_t nrhs,
-                              int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks, hipStream_t s) {
+static hipError_t trsm_launch(const double* tiles, const double* Rt, const double* Rinv, int p, int q, int nb,
+                              double* Y, int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch, int32_t* err,
+                              int64_t spin_ticks, hipStream_t s) {
   for (int64_t c0 = 0; c0 < nrhs; c0 += TR_COLS) {
     const int nc = static_cast<int>(nrhs - c0 < TR_COLS ? nrhs - c0 : TR_COLS);
     const int32_t ep = ++*epoch;
     double* Yc = Y + c0 * ldy;
     switch (nb) {
-      case 32: hipLaunchKernelGGL((trsm_wave_kernel<32, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
-      case 64: hipLaunchKernelGGL((trsm_wave_kernel<64, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
-      case 128: hipLaunchKernelGGL((trsm_wave_kernel<128, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
-      case 256: hipLaunchKernelGGL((trsm_wave_kernel<256, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
+      case 32: hipLaunchKernelGGL((trsm_wave_kernel<32, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, Rt, Rinv, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
+      case 64: hipLaunchKernelGGL((trsm_wave_kernel<64, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, Rt, Rinv, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
+      case 128: hipLaunchKernelGGL((trsm_wave_kernel<128, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, Rt, Rinv, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
+      case 256: hipLaunchKernelGGL((trsm_wave_kernel<256, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, Rt, Rinv, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
       default: return hipErrorInvalidValue;
     }
   }
   return hipGetLastError();
 }
 
-hipError_t launch_trsm_upper(const double* tiles, int p, int q, int nb, double* Y, int64_t ldy, int64_t nrhs,
-                             int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks, hipStream_t s) {
-  return trsm_launch<false>(tiles, p, q, nb, Y, ldy, nrhs, flags, epoch, err, spin_ticks, s);
+hipError_t launch_trsm_upper(const double* tiles, const double* Rinv, int p, int q, int nb, double* Y, int64_t ldy,
+                             int64_t nrhs, int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks,
+                             hipStream_t s) {
+  return trsm_launch<false>(tiles, nullptr, Rinv, p, q, nb, Y, ldy, nrhs, flags, epoch, err, spin_ticks, s);
 }
 
-hipError_t launch_trsm_upper_t(const double* tiles, int p, int q, int nb, double* Y, int64_t ldy, int64_t nrhs,
-                               int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks, hipStream_t s) {
-  return trsm_launch<true>(tiles, p, q, nb, Y, ldy, nrhs, flags, epoch, err, spin_ticks, s);
+hipError_t launch_trsm_upper_t(const double* tiles, const double* Rt, const double* Rinv, int p, int q, int nb,
+                               double* Y, int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch, int32_t* err,
+                               int64_t spin_ticks, hipStream_t s) {
+  return trsm_launch<true>(tiles, Rt, Rinv, p, q, nb, Y, ldy, nrhs, flags, epoch, err, spin_ticks, s);
+}
+
+hipError_t launch_transpose_r(const double* tiles, const double* Rinv, int p, int q, int nb, double* Rt,
+                              double* RinvT, hipStream_t s) {
+  switch (nb) {
+#define TQR_TR(NBV)                                                                                          \
+  case NBV:                                                                                                  \
+    hipLaunchKernelGGL(transpose_tiles_kernel<NBV>, dim3(q, q), dim3(256), 0, s, tiles, p, q, Rt, 0);         \
+    hipLaunchKernelGGL(transpose_tiles_kernel<NBV>, dim3(q, 1), dim3(256), 0, s, Rinv, p, q, RinvT, 1);       \
+    break;
+    TQR_TR(32)
+    TQR_TR(64)
+    TQR_TR(128)
+    TQR_TR(256)
+#undef TQR_TR
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_trinv(const double* tiles, int p, int q, int nb, double* Rinv, hipStream_t s) {
+  if (nb % TR_COLS != 0) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(q), static_cast<unsigned>(nb / TR_COLS));
+  switch (nb) {
+    case 32: hipLaunchKernelGGL(trinv_kernel<32>, grid, dim3(TR_THREADS), 0, s, tiles, p, Rinv); break;
+    case 64: hipLaunchKernelGGL(trinv_kernel<64>, grid, dim3(TR_THREADS), 0, s, tiles, p, Rinv); break;
+    case 128: hipLaunchKernelGGL(trinv_kernel<128>, grid, dim3(TR_THREADS), 0, s, tiles, p, Rinv); break;
+    case 256: hipLaunchKernelGGL(trinv_kernel<256>, grid, dim3(TR_THREADS), 0, s, tiles, p, Rinv); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* Y, int64_t ldy,
                          int64_t nrhs, double* out, int64_t ldo, double sign, hipStream_t s) {
-  const int64_t threads = n * nrhs * 64;
-  if (threads == 0) return hipSuccess;
+  const int64_t threads = n * 64;
+  if (threads == 0 || nrhs == 0) return hipSuccess;
   hipLaunchKernelGGL(gemv_t_kernel, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256), 0, s, A, lda, m,
                      n, Y, ldy, nrhs, out, ldo, sign);
   return hipGetLastError();

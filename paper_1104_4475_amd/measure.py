@@ -1,10 +1,12 @@
 """Measurement sweeps on the current GPU, printed as Markdown tables.
 
-  python -m paper_1104_4475_amd.measure trees    [--m 16384 --n 2048 --nb 256]
+  python -m paper_1104_4475_amd.measure trees    [--m 16384 --n 2048 --nb 256 --upd 0 --ts]
       every reduction tree (PlasmaTree with BS 1..64) on an N(0,1) matrix:
       executor time against the critical path of the task graph (Sec. 2.3)
       in Table 1 units and in measured time (each kind weighted by its
-      mean measured duration from the executor trace)
+      mean measured duration from the executor trace); --upd selects the
+      update precision (0 FP64, 1 FP32, 2 BF16), --ts adds every tree with
+      TS kernels at its leaves
   python -m paper_1104_4475_amd.measure batched  [--count 512]
       the batched launch of tall-skinny problems, FP64 and FP32 updates
 """
@@ -30,7 +32,7 @@ def _cp(tasks, ptr, idx, w):
     return fin.max() if len(fin) else 0.0
 
 
-def trees(m, n, nb, reps=3):
+def trees(m, n, nb, reps=3, upd=0, ts=False):
     import torch
     p, q = m // nb, n // nb
     g = torch.Generator(device="cuda")
@@ -42,13 +44,16 @@ def trees(m, n, nb, reps=3):
              ("Greedy", _lib.TREE_GREEDY, 1, _lib.KERN_TT)]
     cases += [("PlasmaTree BS=%d" % bs, _lib.TREE_PLASMA, bs, _lib.KERN_TT) for bs in (1, 2, 4, 8, 16, 32, 64)
               if bs <= p]
+    if ts:
+        cases += [(name.replace(" (TT flat)", "") + " + TS", tree, bs, _lib.KERN_TS) for name, tree, bs, kern in cases
+                  if kern == _lib.KERN_TT and tree not in (_lib.TREE_FLAT, _lib.TREE_SAMEH_KUCK)]
     flops = 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
     print("| tree | tasks | CP (units) | makespan (ms) | GFLOP/s | CP with measured task times (ms) | makespan / CP |")
     print("|---|---|---|---|---|---|---|")
     for name, tree, bs, kern in cases:
         tasks, cp_units = _lib.schedule(p, q, tree, bs, kern)
         ptr, idx = _lib.task_preds(p, q, tree, bs, kern)
-        F = factor(A, nb, tree, bs, kern, 0)
+        F = factor(A, nb, tree, bs, kern, upd)
         F.sync()
         best = np.inf
         for _ in range(reps):
@@ -111,9 +116,11 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--nb", type=int, default=256)
     ap.add_argument("--count", type=int, default=512)
+    ap.add_argument("--upd", type=int, default=0)
+    ap.add_argument("--ts", action="store_true")
     a = ap.parse_args(argv)
     if a.what == "trees":
-        trees(a.m, a.n, a.nb)
+        trees(a.m, a.n, a.nb, upd=a.upd, ts=a.ts)
     else:
         batched(a.count)
     return 0

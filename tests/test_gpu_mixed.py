@@ -91,17 +91,20 @@ def test_mixed_factor_bounds(torch_cuda, case, upd):
     assert dR <= 10 * kappa * bound, dR
 
 
-@pytest.mark.parametrize("upd,kappa", [(1, 1e2), (1, 1e6), (2, 1e2)])
-def test_mixed_refined_lstsq_matches_oracle(torch_cuda, upd, kappa):
+# method: 0 auto (semi-normal corrections while they contract fast, then
+# classical), 1 classical, 3 semi-normal only.
+@pytest.mark.parametrize("upd,kappa,method", [(1, 1e2, 0), (1, 1e6, 0), (2, 1e2, 0), (1, 1e2, 1), (1, 1e6, 1),
+                                              (1, 1e2, 3), (2, 1e2, 3)])
+def test_mixed_refined_lstsq_matches_oracle(torch_cuda, upd, kappa, method):
     import paper_1104_4475_amd as tqr
     torch = torch_cuda
     n, nb, nrhs = 512, 64, 4
-    _say("mixed refined lstsq %s n %d kappa %g" % (NAME[upd], n, kappa))
+    _say("mixed refined lstsq %s n %d kappa %g method %d" % (NAME[upd], n, kappa, method))
     A = tqr_inputs.conditioned(n, kappa, 51, 52)
     rng = np.random.default_rng(53)
     B = A @ rng.standard_normal((n, nrhs))
     F = tqr.factor(_gpu(torch, A), nb, trees.GREEDY, 1, dag.KERN_DEFAULT, upd)
-    X, info = F.lstsq(_gpu(torch, B), A0=_gpu(torch, A), tol=1e-12, raise_on_noconv=True)
+    X, info = F.lstsq(_gpu(torch, B), A0=_gpu(torch, A), tol=1e-12, method=method, raise_on_noconv=True)
     X = X.cpu().numpy()
     eta = tiled.backward_error(A, X, B)
     O = tiled.tiled_qr(A, nb, trees.GREEDY, 1)
