@@ -88,14 +88,15 @@ def cpu_baseline(nb, tree, bs, kern, kappa):
     import tqr_inputs
     from oracle import tiled
     n = 7 * nb
+    bs = min(bs, 7)  # PlasmaTree's domain size is at most p = 7 in the sample
     A = tqr_inputs.conditioned(n, kappa, 102, 103)
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         tiled.tiled_qr(A, nb, tree, bs, kern)
         dt = time.perf_counter() - t0
     return {"value": flops(n, n) / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle tiled QR of a %dx%d conditioned matrix (kappa %g), nb=%d, same tree and kernels, "
-                      "1 BLAS thread, %.1f s" % (n, n, kappa, nb, dt),
+            "sample": "oracle tiled QR of a %dx%d conditioned matrix (kappa %g), nb=%d, same tree (BS %d) and "
+                      "kernels, 1 BLAS thread, %.1f s" % (n, n, kappa, nb, bs, dt),
             "seconds": dt, "host_cpus": len(os.sched_getaffinity(0))}
 
 

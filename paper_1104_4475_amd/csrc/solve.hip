@@ -294,9 +294,11 @@ __global__ __launch_bounds__(TR_THREADS) void trinv_kernel(const double* tiles, 
 // else by diag_solve.  With TRANS and Rt (the tiles of R^T, from
 // launch_transpose_r: tile (i, k), k <= i, of a q x q tile grid) the
 // products read Rt and Rinv = the transposed inverses without transposition,
-// so every load is coalesced.  Up to TR_COLS right-hand sides per launch.  A
-// wait longer than spin_ticks sets *err and the workgroup leaves.
-template <int NB, bool TRANS>
+// so every load is coalesced.  INV: Rinv is given (a compile-time variant,
+// so that the substitution's block inverses hold no registers in the
+// product path).  Up to TR_COLS right-hand sides per launch.  A wait longer
+// than spin_ticks sets *err and the workgroup leaves.
+template <int NB, bool TRANS, bool INV>
 __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* tiles, const double* Rt,
                                                                const double* Rinv, int p, int q, double* Y,
                                                                int64_t ldy, int nc, int32_t* flags, int32_t epoch,
@@ -317,7 +319,7 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
   const int lane = tid & 63, rr = lane & 31, half = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   double xinv[32];
-  if (!Rinv) block_inverse<NB, TRANS>(Rd, wave, rr, half, xinv, ps + wave * 32 * 32);
+  if (!INV) block_inverse<NB, TRANS>(Rd, wave, rr, half, xinv, ps + wave * 32 * 32);
   __syncthreads();
   const int k_first = TRANS ? 0 : q - 1;
   const int k_end = TRANS ? i : i;
@@ -352,7 +354,7 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
     }
   }
   double sign = 1.0;
-  if (Rinv) {
+  if (INV) {
     // xs = Y_i, ys = -op(inv(R_ii)) Y_i.
     for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
       xs[e] = ys[e];
@@ -421,7 +423,21 @@ __global__ __launch_bounds__(256) void gemv_t_kernel(const double* A, int64_t ld
   const double* a = A + j * lda;
   for (int64_t c0 = 0; c0 < nrhs; c0 += 4) {
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t r = lane; r < m; r += 64) {
+    int64_t r = lane;
+    // Eight rows per lane per pass, loads issued before the products.
+    for (; r + 7 * 64 < m; r += 8 * 64) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = a[r + 64 * u];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        if (c0 + h >= nrhs) continue;
+        const double* y = Y + (c0 + h) * ldy + r;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[h] += v[u] * y[64 * u];
+      }
+    }
+    for (; r < m; r += 64) {
       const double v = a[r];
 #pragma unroll
       for (int h = 0; h < 4; ++h)
@@ -448,7 +464,20 @@ __global__ __launch_bounds__(256) void residual_kernel(const double* A, int64_t 
   if (row >= m) return;
   for (int64_t h0 = 0; h0 < nrhs; h0 += 4) {
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t c = c0; c < c1; ++c) {
+    int64_t c = c0;
+    // Eight columns per pass, loads issued before the products.
+    for (; c + 8 <= c1; c += 8) {
+      double a[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) a[u] = A[(c + u) * lda + row];
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        if (h0 + h >= nrhs) continue;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s[h] += a[u] * X[(h0 + h) * ldx + c + u];
+      }
+    }
+    for (; c < c1; ++c) {
       const double a = A[c * lda + row];
 #pragma unroll
       for (int h = 0; h < 4; ++h)
@@ -514,11 +543,21 @@ static hipError_t trsm_launch(const double* tiles, const double* Rt, const doubl
     const int nc = static_cast<int>(nrhs - c0 < TR_COLS ? nrhs - c0 : TR_COLS);
     const int32_t ep = ++*epoch;
     double* Yc = Y + c0 * ldy;
-    switch (nb) {
-      case 32: hipLaunchKernelGGL((trsm_wave_kernel<32, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, Rt, Rinv, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
-      case 64: hipLaunchKernelGGL((trsm_wave_kernel<64, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, Rt, Rinv, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
-      case 128: hipLaunchKernelGGL((trsm_wave_kernel<128, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, Rt, Rinv, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
-      case 256: hipLaunchKernelGGL((trsm_wave_kernel<256, TRANS>), dim3(q), dim3(TR_THREADS), 0, s, tiles, Rt, Rinv, p, q, Yc, ldy, nc, flags, ep, spin_ticks, err); break;
+    switch (nb * 2 + (Rinv ? 1 : 0)) {
+#define TQR_TRSM(NBV, INVV)                                                                                      \
+  case NBV * 2 + INVV:                                                                                           \
+    hipLaunchKernelGGL((trsm_wave_kernel<NBV, TRANS, INVV>), dim3(q), dim3(TR_THREADS), 0, s, tiles, Rt, Rinv, p, q, \
+                       Yc, ldy, nc, flags, ep, spin_ticks, err);                                                 \
+    break;
+      TQR_TRSM(32, 0)
+      TQR_TRSM(32, 1)
+      TQR_TRSM(64, 0)
+      TQR_TRSM(64, 1)
+      TQR_TRSM(128, 0)
+      TQR_TRSM(128, 1)
+      TQR_TRSM(256, 0)
+      TQR_TRSM(256, 1)
+#undef TQR_TRSM
       default: return hipErrorInvalidValue;
     }
   }
