@@ -40,6 +40,22 @@ TUNE_CANDIDATES = [("flat", 1, "ts"), ("plasma", 8, "ts"), ("plasma", 16, "ts"),
                    ("greedy", 1, "tt"), ("greedy", 1, "ts"), ("fibonacci", 1, "ts")]
 # Table 1 weights by task kind (GEQRT, UNMQR, TSQRT, TSMQR, TTQRT, TTMQR).
 UNITS = (4, 6, 6, 12, 2, 6)
+# HBM bytes per launch of the executor from rocprofv3 FETCH_SIZE + WRITE_SIZE
+# (calibrated by a plain copy; profiles/hbm_traffic_square10240_nb256.md),
+# keyed by (workload, update precision, tree, BS, kernels, nb) and valid for
+# the executor sources with the given SHA-256 prefix only.
+TRAFFIC = {("square", "f32", "plasma", 16, "ts", 256): (88.877e9, "fe7a26be67365878"),
+           ("square", "f64", "plasma", 16, "ts", 256): (90.171e9, "fe7a26be67365878")}
+
+
+def executor_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    here = os.path.dirname(os.path.abspath(__file__))
+    for f in ("kernels.hip", "device.hpp"):
+        with open(os.path.join(here, "paper_1104_4475_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
@@ -211,6 +227,10 @@ def main():
         fu = update_flop_fraction(p, q, TREES[tname], bs, KERNS[kname])
         peak = 1.0 / (fu / PEAK_TFLOPS[args.upd] + (1.0 - fu) / PEAK_TFLOPS["f64"])
     achieved = F / exec_s / 1e12
+    traffic = None
+    key = (args.workload, args.upd, tname, bs, kname, nb)
+    if key in TRAFFIC and TRAFFIC[key][1] == executor_source_hash():
+        traffic = TRAFFIC[key][0]
     line = {
         "metric": METRIC,
         "value": round(main_res["gflops"], 2),
@@ -228,7 +248,7 @@ def main():
                    "upd": args.upd, "refine_tol": args.tol if args.upd != "f64" else None,
                    "tuned": args.tree == "auto"},
         "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": None,
+                     "frac": round(achieved / peak, 4), "traffic": traffic,
                      "kernel": "exec_persistent<%d>" % nb, "kernel_ms": round(main_res["exec_ms"], 3)},
         "fp64": {"gflops": round(fp64["gflops"], 2), "ms_per_step": round(fp64["ms_per_step"], 3),
                  "exec_ms": round(fp64["exec_ms"], 3), "backward_err": fp64["backward_err"],
