@@ -380,7 +380,11 @@ int create(const tqr_opts* o, tqr_factors** out, ExecPlan* keep = nullptr) {
   exec_weights(o->nb, o->upd, w);
   ExecPlan ex;
   const int nslab = std::max(1, F->nb / tqr::SLAB);
-  tqr::make_exec_plan(F->plan, nslab, exec_order(), w, ex);
+  // Panel tasks as one subtask per inner block (nb >= 128; TQR_PANEL_SPLIT=0
+  // keeps whole panel tasks).
+  const char* ps = std::getenv("TQR_PANEL_SPLIT");
+  const int pblk = (F->nb >= 128 && !(ps && ps[0] == '0')) ? F->nb / tqr::IB : 1;
+  tqr::make_exec_plan(F->plan, nslab, exec_order(), w, ex, pblk);
   int st = upload(ex, F->exec);
   if (st != TQR_OK) return st;
   if (keep) *keep = ex;

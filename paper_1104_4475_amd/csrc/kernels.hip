@@ -901,8 +901,10 @@ __device__ __forceinline__ void panel_to_lp(double* Ps, int ldp, int K, double* 
 // ---- GEQRT ---------------------------------------------------------------
 // P: precision of the block update of the rest of the tile (the reflector
 // generation, norms, scaling and T, is FP64 in every mode).
+// The inner blocks c0 = cb, cb + ib, ... < ce are factored (all of them, or
+// one when the planner splits the task into block subtasks).
 template <int NB, int P>
-__device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm) {
+__device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm, int cb, int ce) {
   constexpr int ldp = Smem<NB>::LDP;
   double* Ps = sm + Smem<NB>::PS;
   double* Ts = sm + Smem<NB>::TS;
@@ -912,7 +914,7 @@ __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm) {
   const int tid = threadIdx.x, lane = lane_id(), gw = wave_id() & 3;
   double* wx = sm + Smem<NB>::WX + gw * 16 * 64;
 #pragma unroll 1
-  for (int c0 = 0; c0 < NB; c0 += IB) {
+  for (int c0 = cb; c0 < ce; c0 += IB) {
     const int K = NB - c0;
     stage_block<NB, ST_FULL>(Ps, ldp, A + c0 * NB + c0, K, c0);
     __syncthreads();
@@ -958,8 +960,9 @@ __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm) {
 // ---- TSQRT / TTQRT ----------------------------------------------------------
 // R1: the pivot tile (upper triangle holds R), A2: the tile to zero.
 // TT: 1 for TTQRT (A2 upper triangular), 0 for TSQRT.
+// Inner blocks cb <= c0 < ce as for geqrt_task.
 template <int NB, int P, int TT>
-__device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T, double* sm) {
+__device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T, double* sm, int cb, int ce) {
   constexpr int tt = TT;
   constexpr int ldp = Smem<NB>::LDP;
   double* Ps = sm + Smem<NB>::PS;
@@ -971,7 +974,7 @@ __device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T,
   const int tid = threadIdx.x, lane = lane_id(), gw = wave_id() & 3;
   double* wx = sm + Smem<NB>::WX + gw * 16 * 64;
 #pragma unroll 1
-  for (int c0 = 0; c0 < NB; c0 += IB) {
+  for (int c0 = cb; c0 < ce; c0 += IB) {
     const int K = tt ? c0 + IB : NB;
     for (int e = tid; e < IB * IB; e += NTHREADS) {
       const int a = e % IB, c = e / IB;
@@ -1330,9 +1333,11 @@ __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T,
 // subtasks and the application of Q to right-hand sides are FP64.
 template <int NB, int P>
 __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, double* sm) {
+  // Panel subtasks: slab = the inner block to factor, or -1 for all.
+  const int cb = s.slab < 0 ? 0 : s.slab * IB, ce = s.slab < 0 ? NB : cb + IB;
   switch (s.kind) {
     case D_GEQRT:
-      geqrt_task<NB, P>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), sm);
+      geqrt_task<NB, P>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), sm, cb, ce);
       break;
     case D_UNMQR:
       unmqr_task<NB, P>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), tile_ptr(a, s.i, s.j), s.slab * SLAB, NB, sm, 1);
@@ -1340,9 +1345,9 @@ __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, doub
     case D_TSQRT:
     case D_TTQRT:
       if (s.kind == D_TTQRT)
-        pair_qrt_task<NB, P, 1>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm);
+        pair_qrt_task<NB, P, 1>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm, cb, ce);
       else
-        pair_qrt_task<NB, P, 0>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm);
+        pair_qrt_task<NB, P, 0>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm, cb, ce);
       break;
     case D_TSMQR:
     case D_TTMQR:

@@ -245,10 +245,22 @@ bool make_plan(int p, int q, int tree, int bs, int family, Plan& plan) {
 // slab s, so dependencies are tracked per (tile, slab); the panel tasks touch
 // every slab of their tiles.  The two parts of a tile (upper / lower) are
 // tracked separately as in the task expansion.
-void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex) {
+//
+// With pblk > 1 a panel task becomes pblk subtasks, one per inner block b of
+// ib columns (c0 = b ib), in order.  Block b of a panel task reads and writes
+// only rows c0 .. c0 + ib - 1 of its pivot triangle R1 (TSQRT, TTQRT), rows
+// 0 .. c0 + ib - 1 of a killed triangle (TTQRT), and rows c0 .. nb - 1 of a
+// tile it triangularizes (GEQRT), each in columns >= c0.  So on a tile that
+// an earlier panel task of the same column wrote, block b only has to wait
+// for block b of that task (which follows its blocks 0 .. b - 1), not for
+// the whole task: consecutive panel tasks on a pivot pipeline block by
+// block.  Block 0 waits for the task's other (update) predecessors, block b
+// for block b - 1, and later tasks depend on the last block.
+void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex, int pblk) {
   const int p = plan.p, q = plan.q, S = nslab;
   ex = ExecPlan();
   ex.nslab = S;
+  ex.pblk = pblk;
   const size_t ntile = static_cast<size_t>(p) * q;
   std::vector<int32_t> up(ntile * S, -1), lo(ntile * S, -1);
   auto slot = [&](int r, int c, int s) { return (static_cast<size_t>(r - 1) * q + (c - 1)) * S + s; };
@@ -258,6 +270,7 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
   std::vector<int32_t> task_of;
   sub.reserve(plan.tasks.size() * 2);
 
+  std::vector<int32_t> first_blk;  // panel subtasks: id of block 0 of the task; -1 otherwise
   auto add = [&](const Task& t, int32_t tidx, int slab, std::vector<int32_t>&& d) {
     std::sort(d.begin(), d.end());
     d.erase(std::unique(d.begin(), d.end()), d.end());
@@ -265,7 +278,42 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
     sub.push_back({t.kind, t.i - 1, t.piv > 0 ? t.piv - 1 : 0, t.k - 1, t.j > 0 ? t.j - 1 : 0, slab, 0, 0});
     pre.push_back(std::move(d));
     task_of.push_back(tidx);
+    first_blk.push_back(-1);
     return static_cast<int32_t>(sub.size()) - 1;
+  };
+  // A panel task: one subtask, or pblk block subtasks; returns the id of the
+  // last.  d_full: writers the task waits for as a whole (from block 0);
+  // d_blk: writers of the triangles of its pivot (and, for TTQRT, of its
+  // killed tile), which block b waits for block by block when they are
+  // block subtasks of an earlier panel task.
+  auto add_panel = [&](const Task& t, int32_t tidx, std::vector<int32_t>&& d_full, std::vector<int32_t>&& d_blk) {
+    if (pblk <= 1) {
+      d_full.insert(d_full.end(), d_blk.begin(), d_blk.end());
+      return add(t, tidx, -1, std::move(d_full));
+    }
+    std::vector<int32_t> other, panel_first;
+    for (int32_t x : d_full)
+      if (x >= 0) other.push_back(x);
+    for (int32_t x : d_blk) {
+      if (x < 0) continue;
+      if (first_blk[x] >= 0)
+        panel_first.push_back(first_blk[x]);
+      else
+        other.push_back(x);
+    }
+    std::sort(panel_first.begin(), panel_first.end());
+    panel_first.erase(std::unique(panel_first.begin(), panel_first.end()), panel_first.end());
+    int32_t first = -1, prev = -1;
+    for (int b = 0; b < pblk; ++b) {
+      std::vector<int32_t> db;
+      if (b == 0) db = other;
+      if (prev >= 0) db.push_back(prev);
+      for (int32_t f : panel_first) db.push_back(f + b);
+      prev = add(t, tidx, b, std::move(db));
+      if (b == 0) first = prev;
+      first_blk[prev] = first;
+    }
+    return prev;
   };
 
   for (size_t ti = 0; ti < plan.tasks.size(); ++ti) {
@@ -278,19 +326,23 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
           d.push_back(up[slot(t.i, t.k, s)]);
           d.push_back(lo[slot(t.i, t.k, s)]);
         }
-        const int32_t id = add(t, tid, 0, std::move(d));
+        const int32_t id = add_panel(t, tid, std::move(d), {});
         for (int s = 0; s < S; ++s) up[slot(t.i, t.k, s)] = lo[slot(t.i, t.k, s)] = id;
         break;
       }
       case K_TTQRT:
       case K_TSQRT: {
-        std::vector<int32_t> d;
+        std::vector<int32_t> d_full, d_blk;
         for (int s = 0; s < S; ++s) {
-          d.push_back(up[slot(t.piv, t.k, s)]);
-          d.push_back(up[slot(t.i, t.k, s)]);
-          if (t.kind == K_TSQRT) d.push_back(lo[slot(t.i, t.k, s)]);
+          d_blk.push_back(up[slot(t.piv, t.k, s)]);
+          if (t.kind == K_TTQRT) {
+            d_blk.push_back(up[slot(t.i, t.k, s)]);
+          } else {
+            d_full.push_back(up[slot(t.i, t.k, s)]);
+            d_full.push_back(lo[slot(t.i, t.k, s)]);
+          }
         }
-        const int32_t id = add(t, tid, 0, std::move(d));
+        const int32_t id = add_panel(t, tid, std::move(d_full), std::move(d_blk));
         for (int s = 0; s < S; ++s) {
           up[slot(t.piv, t.k, s)] = id;
           up[slot(t.i, t.k, s)] = id;
@@ -331,13 +383,13 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
 
   // Priorities: ASAP start (order 0), ALAP start (order 1) or largest bottom
   // level first (order 2) of each subtask, with per-kind weights (updates
-  // divided among their slabs).
+  // divided among their slabs, panel tasks among their blocks).
   const size_t n = sub.size();
   std::vector<double> wt(n), est(n, 0.0), lst(n, 0.0);
   for (size_t s = 0; s < n; ++s) {
     const int kd = sub[s].kind;
     const bool is_upd = (kd == K_UNMQR || kd == K_TSMQR || kd == K_TTMQR);
-    wt[s] = is_upd ? w[kd] / S : w[kd];
+    wt[s] = is_upd ? w[kd] / S : w[kd] / (sub[s].slab >= 0 ? pblk : 1);
   }
   double span = 0.0;
   for (size_t s = 0; s < n; ++s) {
@@ -460,7 +512,9 @@ void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, co
   std::map<std::tuple<int, int, int>, int32_t> panel;
   for (size_t t = 0; t < nf; ++t) {
     const SubTask& s = fac.sub[t];
-    if (s.kind == K_GEQRT || s.kind == K_TSQRT || s.kind == K_TTQRT) panel[{s.kind, s.i, s.k}] = static_cast<int32_t>(t);
+    // the subtask that completes the panel task (the whole task, or its last block)
+    if ((s.kind == K_GEQRT || s.kind == K_TSQRT || s.kind == K_TTQRT) && (s.slab < 0 || s.slab == fac.pblk - 1))
+      panel[{s.kind, s.i, s.k}] = static_cast<int32_t>(t);
   }
   std::vector<std::vector<int32_t>> pre(n);
   for (size_t t = 0; t < nf; ++t)
@@ -477,7 +531,7 @@ void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, co
   for (size_t t = 0; t < nf; ++t) {
     const int kd = fac.sub[t].kind;
     const bool is_upd = (kd == K_UNMQR || kd == K_TSMQR || kd == K_TTMQR);
-    wt[t] = is_upd ? w[kd] / S : w[kd];
+    wt[t] = is_upd ? w[kd] / S : w[kd] / (fac.sub[t].slab >= 0 ? fac.pblk : 1);
   }
   for (size_t a = 0; a < na; ++a) wt[nf + a] = w_apply;
   // Bottom levels: successors have larger indices in this numbering
@@ -511,6 +565,7 @@ void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, co
   for (size_t r = 0; r < n; ++r) pos[perm[r]] = static_cast<int32_t>(r);
   out = ExecPlan();
   out.nslab = nslab;
+  out.pblk = fac.pblk;
   out.sub.resize(n);
   out.key.resize(n);
   for (size_t r = 0; r < n; ++r) {

@@ -38,7 +38,8 @@ bool make_plan(int p, int q, int tree, int bs, int family, Plan& plan);
 // (a topological order), dependencies index earlier subtasks.
 struct SubTask {
   int32_t kind, i, piv, k, j;   // 0-based tile indices (i, piv, k, j)
-  int32_t slab;                 // column slab of the C tiles (updates)
+  int32_t slab;                 // column slab of the C tiles (updates); for panel
+                                // tasks the inner block it factors, -1 = all
   int32_t dep_begin, dep_end;   // range in deps[]
 };
 
@@ -49,12 +50,15 @@ struct ExecPlan {
   std::vector<int32_t> level_order;  // indices into sub, level by level
   std::vector<double> key;           // priority key of each subtask (ascending = earlier)
   int32_t nslab = 1;
+  int32_t pblk = 1;                  // subtasks per panel task (inner blocks)
 };
 
 // order: 0 = ascending ASAP start time, 1 = ascending ALAP start time,
 // 2 = descending bottom level (longest remaining path).
 // w: per-kind weights used for the priority (any positive values).
-void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex);
+// pblk > 1 splits every panel task (GEQRT, TSQRT, TTQRT) into its pblk inner
+// blocks of columns, one subtask each (see plan.cpp).
+void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex, int pblk = 1);
 
 // One executor plan for the factorization and Q^T B together: the
 // subtasks of fac (built by make_exec_plan with the same nslab and weights

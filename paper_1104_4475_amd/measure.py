@@ -70,8 +70,12 @@ def trees(m, n, nb, reps=3, upd=0, ts=False):
         for k in range(6):
             sel = tr[:, 0] == k
             if sel.any():
-                # a task's column slabs run side by side: its time is one slab's
+                # a task's column slabs run side by side: its time is one
+                # slab's; a panel task split into inner-block subtasks (slab =
+                # block index) takes the sum of its blocks
                 w[k] = dur[sel].mean()
+                if k in (0, 2, 4) and tr[sel, 5].min() >= 0:
+                    w[k] *= tr[sel, 5].max() + 1
         cpt = _cp(tasks, ptr, idx, w)
         print("| %s | %d | %d | %.2f | %.0f | %.2f | %.2f |" % (name, len(tasks), cp_units, best, flops / best / 1e6,
                                                                 cpt, best / cpt if cpt > 0 else float("nan")))

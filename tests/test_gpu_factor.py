@@ -75,6 +75,10 @@ SMALL = [
     (512, 256, 256, trees.GREEDY, 1, dag.KERN_TT),
     (512, 256, 256, trees.FLAT, 1, dag.KERN_TS),
     (768, 512, 256, trees.PLASMA, 2, dag.KERN_TT),
+    # TS-hybrid trees at nb >= 128 (panel tasks run as inner-block subtasks
+    # that pipeline along a pivot: TS leaves, TT merges)
+    (1024, 512, 256, trees.PLASMA, 2, dag.KERN_TS),
+    (768, 768, 128, trees.GREEDY, 1, dag.KERN_TS),
 ]
 
 
