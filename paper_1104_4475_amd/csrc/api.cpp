@@ -169,6 +169,8 @@ struct tqr_factors {
   mutable int32_t solve_epoch = 0;  // advanced by every triangular solve launch
   mutable double* rinv = nullptr;   // inverses of the q diagonal tiles of R
   mutable bool rinv_ok = false;     // rinv matches the current factors
+  mutable double* wn = nullptr;     // coupling tiles of the R solve
+  mutable double* wnt = nullptr;    // coupling tiles of the R^T solve
   mutable double* rt = nullptr;     // tiles of R^T (q x q grid, lower part)
   mutable double* rinvt = nullptr;  // transposes of the diagonal-tile inverses
   mutable bool rt_ok = false;       // rt, rinvt match the current factors
@@ -187,6 +189,8 @@ struct tqr_factors {
     if (Bt16) (void)hipFree(Bt16);
     if (rinv) (void)hipFree(rinv);
     if (rt) (void)hipFree(rt);
+    if (wn) (void)hipFree(wn);
+    if (wnt) (void)hipFree(wnt);
     if (rinvt) (void)hipFree(rinvt);
     for (auto& kv : apply) kv.second.release();
     if (tiles) (void)hipFree(tiles);
@@ -277,14 +281,23 @@ const double* diag_inverses(const tqr_factors* F, hipStream_t s, hipError_t* e) 
   const char* sub = std::getenv("TQR_TRSM_SUBST");
   if (sub && sub[0] == '1') return nullptr;
   if (F->rinv_ok) return F->rinv;
+  const size_t bytes = static_cast<size_t>(F->q) * F->nb * F->nb * sizeof(double);
   if (!F->rinv) {
-    *e = hipMalloc(&F->rinv, static_cast<size_t>(F->q) * F->nb * F->nb * sizeof(double));
+    *e = hipMalloc(&F->rinv, bytes);
     if (*e != hipSuccess) {
       F->rinv = nullptr;
       return nullptr;
     }
   }
+  if (!F->wn) {
+    *e = hipMalloc(&F->wn, bytes);
+    if (*e != hipSuccess) {
+      F->wn = nullptr;
+      return nullptr;
+    }
+  }
   *e = tqr::launch_trinv(F->tiles, F->p, F->q, F->nb, F->rinv, s);
+  if (*e == hipSuccess) *e = tqr::launch_coupling(F->tiles, nullptr, F->p, F->q, F->nb, 0, F->wn, s);
   F->rinv_ok = *e == hipSuccess;
   return F->rinv;
 }
@@ -294,8 +307,8 @@ hipError_t solve_r(const tqr_factors* F, double* X, int64_t ldx, int64_t nrhs, h
   hipError_t e;
   const double* ri = diag_inverses(F, s, &e);
   if (e != hipSuccess) return e;
-  return tqr::launch_trsm_upper(F->tiles, ri, F->p, F->q, F->nb, X, ldx, nrhs, F->ctl + 3, &F->solve_epoch,
-                                F->ctl + 2, 4 * wall_ticks_per_second(), s);
+  return tqr::launch_trsm_upper(F->tiles, ri, ri ? F->wn : nullptr, F->p, F->q, F->nb, X, ldx, nrhs, F->ctl + 3,
+                                &F->solve_epoch, F->ctl + 2, 4 * wall_ticks_per_second(), s);
 }
 
 // X <- R^{-T} X (n x nrhs, in place), from the transposed tiles of R and
@@ -321,12 +334,21 @@ hipError_t solve_rt(const tqr_factors* F, double* X, int64_t ldx, int64_t nrhs, 
         return e;
       }
     }
+    if (!F->wnt) {
+      e = hipMalloc(&F->wnt, static_cast<size_t>(F->q) * tile * sizeof(double));
+      if (e != hipSuccess) {
+        F->wnt = nullptr;
+        return e;
+      }
+    }
     e = tqr::launch_transpose_r(F->tiles, ri, F->p, F->q, F->nb, F->rt, F->rinvt, s);
+    if (e == hipSuccess) e = tqr::launch_coupling(F->tiles, F->rt, F->p, F->q, F->nb, 1, F->wnt, s);
     if (e != hipSuccess) return e;
     F->rt_ok = true;
   }
-  return tqr::launch_trsm_upper_t(F->tiles, ri ? F->rt : nullptr, ri ? F->rinvt : nullptr, F->p, F->q, F->nb, X, ldx,
-                                  nrhs, F->ctl + 3, &F->solve_epoch, F->ctl + 2, 4 * wall_ticks_per_second(), s);
+  return tqr::launch_trsm_upper_t(F->tiles, ri ? F->rt : nullptr, ri ? F->rinvt : nullptr, ri ? F->wnt : nullptr, F->p,
+                                  F->q, F->nb, X, ldx, nrhs, F->ctl + 3, &F->solve_epoch, F->ctl + 2,
+                                  4 * wall_ticks_per_second(), s);
 }
 
 int run_plan(tqr_factors* F, DevPlan& d, ExecArgs a, hipStream_t s) {

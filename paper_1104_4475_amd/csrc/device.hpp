@@ -83,18 +83,23 @@ hipError_t launch_unpack_b(const double* Bt, double* B, int64_t ldb, int64_t nrh
                            hipStream_t s);
 // X = R^{-1} Y in place (Y: n x nrhs, column-major).  Rinv: inverses of
 // the q diagonal tiles from launch_trinv, or null (substitution inside the
-// diagonal tiles).  flags: q int32 owned by the caller, compared with the
-// per-launch epoch (*epoch is advanced); err: set when a wait exceeds
-// spin_ticks.
-hipError_t launch_trsm_upper(const double* tiles, const double* Rinv, int p, int q, int nb, double* Y, int64_t ldy,
-                             int64_t nrhs, int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks,
-                             hipStream_t s);
+// diagonal tiles).  Wn: coupling tiles from launch_coupling (trans 0), or
+// null; used with Rinv only.  flags: q int32 owned by the caller, compared
+// with the per-launch epoch (*epoch is advanced); err: set when a wait
+// exceeds spin_ticks.
+hipError_t launch_trsm_upper(const double* tiles, const double* Rinv, const double* Wn, int p, int q, int nb, double* Y,
+                             int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch, int32_t* err,
+                             int64_t spin_ticks, hipStream_t s);
 // X = R^{-T} Y in place (same conventions).  Rt: the tiles of R^T from
 // launch_transpose_r with Rinv then the transposed inverses, or null
 // (transposed reads of R and Rinv).
-hipError_t launch_trsm_upper_t(const double* tiles, const double* Rt, const double* Rinv, int p, int q, int nb,
-                               double* Y, int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch, int32_t* err,
-                               int64_t spin_ticks, hipStream_t s);
+hipError_t launch_trsm_upper_t(const double* tiles, const double* Rt, const double* Rinv, const double* Wn, int p,
+                               int q, int nb, double* Y, int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch,
+                               int32_t* err, int64_t spin_ticks, hipStream_t s);
+// Wn (q tiles) = coupling tiles -op(R_ii)^{-1} N_i of the solve with R
+// (trans 0: N_i = R_{i,i+1}) or R^T (trans 1: N_i = tile (i, i-1) of Rt).
+hipError_t launch_coupling(const double* tiles, const double* Rt, int p, int q, int nb, int trans, double* Wn,
+                           hipStream_t s);
 // Rt (q x q tile grid, tiles (i, k) with k <= i) = tiles of R^T, and RinvT
 // (q tiles) = transposes of the diagonal-tile inverses Rinv.
 hipError_t launch_transpose_r(const double* tiles, const double* Rinv, int p, int q, int nb, double* Rt,

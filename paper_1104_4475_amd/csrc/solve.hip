@@ -282,6 +282,33 @@ __global__ __launch_bounds__(TR_THREADS) void trinv_kernel(const double* tiles, 
   for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) out[e] = ys[e];
 }
 
+// Coupling tiles of the triangular solves: block (i, c) writes columns
+// 16 c .. 16 c + 15 of Wn_i = -op(R_ii)^{-1} N_i into tile i of Wn, where
+// N_i is the tile coupling row i to the row solved just before it: for R
+// (back substitution) N_i = R_{i,i+1}, i < q - 1; for R^T (forward) N_i =
+// (R^T)_{i,i-1}, tile (i, i - 1) of Rt, i >= 1.  By diag_solve on the
+// columns of N_i.
+template <int NB, bool TRANS>
+__global__ __launch_bounds__(TR_THREADS) void coupling_kernel(const double* tiles, const double* Rt, int p, int q,
+                                                              double* Wn) {
+  __shared__ double ys[NB * TR_COLS];
+  __shared__ double ps[TR_THREADS * TR_COLS];
+  const int i = TRANS ? static_cast<int>(blockIdx.x) + 1 : static_cast<int>(blockIdx.x);
+  const int c0 = blockIdx.y * TR_COLS;
+  const int tid = threadIdx.x, lane = tid & 63, rr = lane & 31, half = lane >> 5;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const double* N = TRANS ? Rt + (static_cast<size_t>(i - 1) * q + i) * NB * NB
+                          : tiles + (static_cast<size_t>(i + 1) * p + i) * NB * NB;
+  for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) ys[e] = N[static_cast<size_t>(c0) * NB + e];
+  const double* Rd = tiles + (static_cast<size_t>(i) * p + i) * NB * NB;
+  double xinv[32];
+  block_inverse<NB, TRANS>(Rd, wave, rr, half, xinv, ps + wave * 32 * 32);
+  __syncthreads();
+  diag_solve<NB, TRANS>(ys, Rd, xinv, ps, TR_COLS, wave, rr, half);
+  double* out = Wn + static_cast<size_t>(i) * NB * NB + static_cast<size_t>(c0) * NB;
+  for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) out[e] = -ys[e];
+}
+
 // X = R^{-1} Y (TRANS = false) or X = R^{-T} Y (TRANS = true) in place in Y
 // (rows i nb .. i nb + nb - 1 of tile row i), with the tiled upper
 // triangular R (tiles (i, k), i <= k < q).  One workgroup per tile row,
@@ -296,13 +323,17 @@ __global__ __launch_bounds__(TR_THREADS) void trinv_kernel(const double* tiles, 
 // products read Rt and Rinv = the transposed inverses without transposition,
 // so every load is coalesced.  INV: Rinv is given (a compile-time variant,
 // so that the substitution's block inverses hold no registers in the
-// product path).  Up to TR_COLS right-hand sides per launch.  A wait longer
-// than spin_ticks sets *err and the workgroup leaves.
+// product path).  With Wn (coupling tiles from coupling_kernel) as well,
+// row i forms z_i = op(inv(R_ii)) (Y_i - sum over the rows solved before
+// the last one) before it waits for that last row, then X_i = z_i + Wn_i
+// X_last: one tile product per step on the solve's critical chain instead
+// of two.  Up to TR_COLS right-hand sides per launch.  A wait longer than
+// spin_ticks sets *err and the workgroup leaves.
 template <int NB, bool TRANS, bool INV>
 __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* tiles, const double* Rt,
-                                                               const double* Rinv, int p, int q, double* Y,
-                                                               int64_t ldy, int nc, int32_t* flags, int32_t epoch,
-                                                               int64_t spin_ticks, int32_t* err) {
+                                                               const double* Rinv, const double* Wn, int p, int q,
+                                                               double* Y, int64_t ldy, int nc, int32_t* flags,
+                                                               int32_t epoch, int64_t spin_ticks, int32_t* err) {
   __shared__ double ys[NB * TR_COLS];
   __shared__ double xs[NB * TR_COLS];
   __shared__ double ps[TR_THREADS * TR_COLS];  // partial sums of tr_update; block inverses for TRANS
@@ -321,9 +352,8 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
   double xinv[32];
   if (!INV) block_inverse<NB, TRANS>(Rd, wave, rr, half, xinv, ps + wave * 32 * 32);
   __syncthreads();
-  const int k_first = TRANS ? 0 : q - 1;
-  const int k_end = TRANS ? i : i;
-  for (int k = k_first; TRANS ? (k < k_end) : (k > k_end); k += TRANS ? 1 : -1) {
+  // Wait for row k's flag, then xs = X_k; false when the wait failed.
+  auto fetch = [&](int k) {
     if (tid == 0) {
       const uint64_t t0 = wall_clock64();
       while (__hip_atomic_load(flags + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
@@ -337,13 +367,21 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
       }
     }
     __syncthreads();
-    if (__builtin_amdgcn_readfirstlane(s_abort)) return;
+    if (__builtin_amdgcn_readfirstlane(s_abort)) return false;
     const int64_t k0 = static_cast<int64_t>(k) * NB;
     for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
       const int c = e / NB, r = e % NB;
       xs[e] = c < nc ? ld_coh(Y + c * ldy + k0 + r) : 0.0;
     }
     __syncthreads();
+    return true;
+  };
+  // The row solved just before this one (coupled through Wn), if any.
+  const bool coupled = INV && Wn && (TRANS ? i > 0 : i < q - 1);
+  const int k_first = TRANS ? 0 : q - 1;
+  const int k_end = coupled ? (TRANS ? i - 1 : i + 1) : i;
+  for (int k = k_first; TRANS ? (k < k_end) : (k > k_end); k += TRANS ? 1 : -1) {
+    if (!fetch(k)) return;
     // op(R)_ik: R_ik = tile (i, k) for the upper solve; (R_ki)^T for R^T.
     if (TRANS && Rt) {
       tile_gemv<NB, false>(ys, xs, Rt + (static_cast<size_t>(k) * q + i) * NB * NB, nc, ps);
@@ -366,6 +404,11 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
     else
       tile_gemv<NB, TRANS>(ys, xs, Rinv + static_cast<size_t>(i) * NB * NB, nc, ps);
     sign = -1.0;
+    if (coupled) {
+      // ys = -z_i - Wn_i X_last = -X_i.
+      if (!fetch(k_end)) return;
+      tile_gemv<NB, false>(ys, xs, Wn + static_cast<size_t>(i) * NB * NB, nc, ps);
+    }
   } else {
     diag_solve<NB, TRANS>(ys, Rd, xinv, ps, nc, wave, rr, half);
   }
@@ -536,9 +579,9 @@ int grid_of(int64_t total) {
 }  // namespace
 
 template <bool TRANS>
-static hipError_t trsm_launch(const double* tiles, const double* Rt, const double* Rinv, int p, int q, int nb,
-                              double* Y, int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch, int32_t* err,
-                              int64_t spin_ticks, hipStream_t s) {
+static hipError_t trsm_launch(const double* tiles, const double* Rt, const double* Rinv, const double* Wn, int p, int q,
+                              int nb, double* Y, int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch,
+                              int32_t* err, int64_t spin_ticks, hipStream_t s) {
   for (int64_t c0 = 0; c0 < nrhs; c0 += TR_COLS) {
     const int nc = static_cast<int>(nrhs - c0 < TR_COLS ? nrhs - c0 : TR_COLS);
     const int32_t ep = ++*epoch;
@@ -546,7 +589,7 @@ static hipError_t trsm_launch(const double* tiles, const double* Rt, const doubl
     switch (nb * 2 + (Rinv ? 1 : 0)) {
 #define TQR_TRSM(NBV, INVV)                                                                                      \
   case NBV * 2 + INVV:                                                                                           \
-    hipLaunchKernelGGL((trsm_wave_kernel<NBV, TRANS, INVV>), dim3(q), dim3(TR_THREADS), 0, s, tiles, Rt, Rinv, p, q, \
+    hipLaunchKernelGGL((trsm_wave_kernel<NBV, TRANS, INVV>), dim3(q), dim3(TR_THREADS), 0, s, tiles, Rt, Rinv, Wn, p, q, \
                        Yc, ldy, nc, flags, ep, spin_ticks, err);                                                 \
     break;
       TQR_TRSM(32, 0)
@@ -564,16 +607,40 @@ static hipError_t trsm_launch(const double* tiles, const double* Rt, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_trsm_upper(const double* tiles, const double* Rinv, int p, int q, int nb, double* Y, int64_t ldy,
-                             int64_t nrhs, int32_t* flags, int32_t* epoch, int32_t* err, int64_t spin_ticks,
-                             hipStream_t s) {
-  return trsm_launch<false>(tiles, nullptr, Rinv, p, q, nb, Y, ldy, nrhs, flags, epoch, err, spin_ticks, s);
+hipError_t launch_trsm_upper(const double* tiles, const double* Rinv, const double* Wn, int p, int q, int nb, double* Y,
+                             int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch, int32_t* err,
+                             int64_t spin_ticks, hipStream_t s) {
+  return trsm_launch<false>(tiles, nullptr, Rinv, Wn, p, q, nb, Y, ldy, nrhs, flags, epoch, err, spin_ticks, s);
 }
 
-hipError_t launch_trsm_upper_t(const double* tiles, const double* Rt, const double* Rinv, int p, int q, int nb,
-                               double* Y, int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch, int32_t* err,
-                               int64_t spin_ticks, hipStream_t s) {
-  return trsm_launch<true>(tiles, Rt, Rinv, p, q, nb, Y, ldy, nrhs, flags, epoch, err, spin_ticks, s);
+hipError_t launch_trsm_upper_t(const double* tiles, const double* Rt, const double* Rinv, const double* Wn, int p,
+                               int q, int nb, double* Y, int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch,
+                               int32_t* err, int64_t spin_ticks, hipStream_t s) {
+  return trsm_launch<true>(tiles, Rt, Rinv, Wn, p, q, nb, Y, ldy, nrhs, flags, epoch, err, spin_ticks, s);
+}
+
+hipError_t launch_coupling(const double* tiles, const double* Rt, int p, int q, int nb, int trans, double* Wn,
+                           hipStream_t s) {
+  if (q < 2) return hipSuccess;
+  if (nb % TR_COLS != 0) return hipErrorInvalidValue;
+  const dim3 grid(static_cast<unsigned>(q - 1), static_cast<unsigned>(nb / TR_COLS));
+  switch (nb * 2 + (trans ? 1 : 0)) {
+#define TQR_CPL(NBV, TV)                                                                              \
+  case NBV * 2 + TV:                                                                                  \
+    hipLaunchKernelGGL((coupling_kernel<NBV, TV != 0>), grid, dim3(TR_THREADS), 0, s, tiles, Rt, p, q, Wn); \
+    break;
+    TQR_CPL(32, 0)
+    TQR_CPL(32, 1)
+    TQR_CPL(64, 0)
+    TQR_CPL(64, 1)
+    TQR_CPL(128, 0)
+    TQR_CPL(128, 1)
+    TQR_CPL(256, 0)
+    TQR_CPL(256, 1)
+#undef TQR_CPL
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_transpose_r(const double* tiles, const double* Rinv, int p, int q, int nb, double* Rt,
