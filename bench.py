@@ -44,8 +44,8 @@ UNITS = (4, 6, 6, 12, 2, 6)
 # (calibrated by a plain copy; profiles/hbm_traffic_square10240_nb256.md),
 # keyed by (workload, update precision, tree, BS, kernels, nb) and valid for
 # the executor sources with the given SHA-256 prefix only.
-TRAFFIC = {("square", "f32", "plasma", 16, "ts", 256): (88.877e9, "fe7a26be67365878"),
-           ("square", "f64", "plasma", 16, "ts", 256): (90.171e9, "fe7a26be67365878")}
+TRAFFIC = {("square", "f32", "plasma", 16, "ts", 256): (88.603e9, "2b12d75b7a27b848"),
+           ("square", "f64", "plasma", 16, "ts", 256): (90.277e9, "2b12d75b7a27b848")}
 
 
 def executor_source_hash():
