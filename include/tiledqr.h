@@ -93,7 +93,11 @@ int tiledqr_last_hip_error(void);
  * A is only read; the handle owns a tile-layout copy holding R, the
  * reflectors V and the compact-WY T factors.  On success *F must later be
  * released with tiledqr_destroy.  The factorization is enqueued on stream;
- * errors of the device executor are reported by tiledqr_sync.
+ * errors of the device executor are reported by tiledqr_sync.  The
+ * executor runs the tasks of the DAG as subtasks: update tasks per 64-column
+ * slab and, for nb >= 128, panel tasks per inner block of ib columns, block b
+ * waiting only for block b of the previous panel task on the same triangle
+ * (environment TQR_PANEL_SPLIT=0 keeps whole panel tasks).
  * Errors: TQR_EINVAL (null pointer, m % nb, n % nb, m < n, nb or ib not
  * supported, bs outside [1, p] for PlasmaTree, lda < m), TQR_ENOMEM,
  * TQR_EHIP. */
@@ -141,7 +145,8 @@ int tiledqr_exec_time(tqr_factors* F, float* ms);
  * wall-clock tick when its workgroup took the ticket, when its predecessors
  * were complete, when it finished, and the workgroup index.
  * tiledqr_get_trace writes 10 int64 per subtask to out (host): kind, i, piv,
- * k, j (0-based tiles), column slab, ticket, ready, end, workgroup; out may
+ * k, j (0-based tiles), column slab (update kinds) or inner block (panel
+ * kinds; -1 for a whole panel task), ticket, ready, end, workgroup; out may
  * be NULL to query *n; *ticks_per_second (may be NULL) gets the clock rate.
  * Synchronizes the handle's stream.  Errors: TQR_EINVAL, TQR_ENOMEM, TQR_EHIP. */
 int tiledqr_set_trace(tqr_factors* F, int enable);
@@ -186,7 +191,13 @@ typedef struct {      /* host memory, filled by tiledqr_lstsq */
  * Synchronizes the stream once per refinement iteration.  Returns
  * TQR_ENOTCONV (info filled, X holding the last iterate) if the tolerance is
  * not reached within max_iter or the error stops halving over three
- * iterations.  Errors: TQR_EINVAL, TQR_ENOMEM, TQR_EHIP, TQR_EEXEC. */
+ * iterations.  The triangular solves use the inverses of the q diagonal
+ * tiles of R and the coupling tiles -inv(R_ii) R_{i,i+1}, formed on the
+ * first solve after a factorization (2 q nb^2 doubles of device memory
+ * owned by the handle); an R^{-T} solve also keeps the tiles of R^T and
+ * the transposed counterparts (q^2 + 2 q tiles of nb^2 doubles).
+ * Environment TQR_TRSM_SUBST=1 solves by substitution inside the diagonal
+ * tiles instead.  Errors: TQR_EINVAL, TQR_ENOMEM, TQR_EHIP, TQR_EEXEC. */
 int tiledqr_lstsq(const tqr_factors* F, const double* A0, int64_t lda,
                   const double* B, int64_t ldb, int64_t nrhs,
                   double* X, int64_t ldx, const tqr_refine* r,
