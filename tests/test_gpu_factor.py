@@ -168,6 +168,55 @@ def test_lstsq_matches_oracle(torch_cuda):
     assert np.max(np.abs(X.cpu().numpy() - want)) <= 1e-10
 
 
+@pytest.mark.parametrize("upd", [0, 1])
+def test_panel_block_subtasks_bit_identical(torch_cuda, upd):
+    """Panel tasks run as inner-block subtasks (the default at nb >= 128) or
+    whole (TQR_PANEL_SPLIT=0): every tile sees the same operations in the
+    same order, so the factors are bit-identical."""
+    import os
+    import paper_1104_4475_amd as tqr
+    torch = torch_cuda
+    _say("panel block subtasks vs whole panel tasks, upd %d" % upd)
+    A = _gpu(torch, tqr_inputs.gaussian(1024, 768, seed=41))
+    out = []
+    for split in ("1", "0"):
+        os.environ["TQR_PANEL_SPLIT"] = split
+        try:
+            F = tqr.factor(A, 256, trees.PLASMA, 2, dag.KERN_TS, upd)
+            F.sync()
+            out.append(F.packed().cpu().numpy())
+        finally:
+            del os.environ["TQR_PANEL_SPLIT"]
+    assert np.array_equal(out[0], out[1])
+
+
+def test_trsm_inverse_and_substitution_agree(torch_cuda):
+    """Triangular solves with the diagonal-tile inverses and coupling tiles
+    (default) against substitution inside the diagonal tiles
+    (TQR_TRSM_SUBST=1), through lstsq and the R^-T solve of the augmented
+    refinement; both against the oracle."""
+    import os
+    torch = torch_cuda
+    _say("trsm inverse vs substitution")
+    A = tqr_inputs.gaussian(1024, 512, seed=43)
+    B = tqr_inputs.gaussian(1024, 5, seed=44)
+    F, O = _factor_both(torch, A, 128, trees.GREEDY, 1, dag.KERN_TT)
+    want = tiled.lstsq(O, B)
+    sols = []
+    for sub in ("0", "1"):
+        os.environ["TQR_TRSM_SUBST"] = sub
+        try:
+            X, info = F.lstsq(_gpu(torch, B), A0=_gpu(torch, A), tol=1e-13)
+            sols.append(X.cpu().numpy())
+        finally:
+            del os.environ["TQR_TRSM_SUBST"]
+        assert info["converged"]
+    scale = np.max(np.abs(want))
+    for X in sols:
+        assert np.max(np.abs(X - want)) <= 1e-10 * scale
+    assert np.max(np.abs(sols[0] - sols[1])) <= 1e-10 * scale
+
+
 def test_square_refinement_fp64(torch_cuda):
     _say("square refinement fp64")
     torch = torch_cuda
