@@ -162,7 +162,7 @@ struct tqr_factors {
   double* tiles = nullptr;
   double* Tg = nullptr;
   double* Tp = nullptr;
-  int32_t* ctl = nullptr;  // [0] ticket, [1] executor err, [2] solve err, [3..3+q) solve flags
+  int32_t* ctl = nullptr;  // [0] ticket, [1] executor err, [2] solve err, [3..3+4q) solve flags
   ExecPlan exec_host;      // host copy of the factorization plan (joint plans are built from it)
   DevPlan fused;           // factorization + Q^T B (16 columns) in one executor plan
   double* Bt16 = nullptr;  // packed right-hand sides of the joint plan (p row tiles of nb x 16)
@@ -416,11 +416,11 @@ int create(const tqr_opts* o, tqr_factors** out, ExecPlan* keep = nullptr) {
   if (!hip_ok(hipMalloc(&F->tiles, ntile * nbb * nbb * sizeof(double))) ||
       !hip_ok(hipMalloc(&F->Tg, ntile * tqr::IB * nbb * sizeof(double))) ||
       !hip_ok(hipMalloc(&F->Tp, ntile * tqr::IB * nbb * sizeof(double))) ||
-      !hip_ok(hipMalloc(&F->ctl, (3 + F->q) * sizeof(int32_t))))
+      !hip_ok(hipMalloc(&F->ctl, (3 + 4 * F->q) * sizeof(int32_t))))
     return TQR_ENOMEM;
   HIP_TRY(hipMemset(F->Tg, 0, ntile * tqr::IB * nbb * sizeof(double)));
   HIP_TRY(hipMemset(F->Tp, 0, ntile * tqr::IB * nbb * sizeof(double)));
-  HIP_TRY(hipMemset(F->ctl, 0, (3 + F->q) * sizeof(int32_t)));
+  HIP_TRY(hipMemset(F->ctl, 0, (3 + 4 * F->q) * sizeof(int32_t)));
   F->grid = device_cus() * tqr::persistent_occupancy(F->nb, F->o.upd);
   *out = F.release();
   return TQR_OK;

@@ -84,7 +84,8 @@ hipError_t launch_unpack_b(const double* Bt, double* B, int64_t ldb, int64_t nrh
 // X = R^{-1} Y in place (Y: n x nrhs, column-major).  Rinv: inverses of
 // the q diagonal tiles from launch_trinv, or null (substitution inside the
 // diagonal tiles).  Wn: coupling tiles from launch_coupling (trans 0), or
-// null; used with Rinv only.  flags: q int32 owned by the caller, compared
+// null; used with Rinv only.  flags: 4 q int32 owned by the caller (one per
+// tile row and part of a row), compared
 // with the per-launch epoch (*epoch is advanced); err: set when a wait
 // exceeds spin_ticks.
 hipError_t launch_trsm_upper(const double* tiles, const double* Rinv, const double* Wn, int p, int q, int nb, double* Y,

@@ -184,6 +184,47 @@ __device__ __forceinline__ void tile_gemv(double* ys, const double* xs, const do
   }
 }
 
+// ys[c * NB + r] -= sum_l M[r][l] xs[c * NB + l] for the ROWS rows r =
+// rlo .. rlo + ROWS - 1 only (ROWS = 64: one row per lane), columns split
+// over the waves as in tile_gemv.  Contains barriers.
+template <int NB, int ROWS>
+__device__ __forceinline__ void rows_gemv(double* ys, const double* xs, const double* M, int rlo, int nc, double* ps) {
+  static_assert(ROWS == 64, "one row per lane");
+  constexpr int NW = TR_THREADS / 64;
+  constexpr int PER = NB / NW;
+  constexpr int TB = PER < 8 ? PER : 8;
+  const int lane = threadIdx.x & 63, w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int r = rlo + lane;
+  for (int c0 = 0; c0 < nc; c0 += 4) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int t0 = 0; t0 < PER; t0 += TB) {
+      double m[TB];
+#pragma unroll
+      for (int b = 0; b < TB; ++b) m[b] = M[static_cast<size_t>(w + NW * (t0 + b)) * NB + r];
+#pragma unroll
+      for (int b = 0; b < TB; ++b) {
+        const int l = w + NW * (t0 + b);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[c] += m[b] * ((c0 + c < nc) ? xs[(c0 + c) * NB + l] : 0.0);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) ps[(w * 4 + c) * ROWS + lane] = acc[c];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 4 * ROWS; e += TR_THREADS) {
+      const int c = e / ROWS, rr = e % ROWS;
+      if (c0 + c < nc) {
+        double t = 0.0;
+#pragma unroll
+        for (int v = 0; v < NW; ++v) t += ps[(v * 4 + c) * ROWS + rr];
+        ys[(c0 + c) * NB + rlo + rr] -= t;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Inverse of diagonal block w (32 x 32, upper triangular) of the tile Rd
 // on wave w < NB / 32: lane (rr, half) ends with row rr of the inverse
 // (both halves alike); with TRANS, with row rr of the inverse's transpose
@@ -327,23 +368,32 @@ __global__ __launch_bounds__(TR_THREADS) void coupling_kernel(const double* tile
 // row i forms z_i = op(inv(R_ii)) (Y_i - sum over the rows solved before
 // the last one) before it waits for that last row, then X_i = z_i + Wn_i
 // X_last: one tile product per step on the solve's critical chain instead
-// of two.  Up to TR_COLS right-hand sides per launch.  A wait longer than
-// spin_ticks sets *err and the workgroup leaves.
-template <int NB, bool TRANS, bool INV>
+// of two.  GP > 1 (with Wn): GP workgroups per tile row, each computing
+// the whole of z_i (off the chain) but only its NB / GP = 64 rows of X_i
+// from the coupling product, so that product on the chain reads 1/GP of
+// Wn_i; flags are per (row, part).  The right-hand sides are read from Yin
+// (ld ldin): with GP > 1 a copy of Y, since a part of a row is written
+// while other parts of the row may still read it.  Up to TR_COLS
+// right-hand sides per launch.  A wait longer than spin_ticks sets *err and
+// the workgroup leaves.
+template <int NB, bool TRANS, bool INV, int GP>
 __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* tiles, const double* Rt,
                                                                const double* Rinv, const double* Wn, int p, int q,
-                                                               double* Y, int64_t ldy, int nc, int32_t* flags,
-                                                               int32_t epoch, int64_t spin_ticks, int32_t* err) {
+                                                               const double* Yin, int64_t ldin, double* Y,
+                                                               int64_t ldy, int nc, int32_t* flags, int32_t epoch,
+                                                               int64_t spin_ticks, int32_t* err) {
+  static_assert(GP == 1 || NB / GP == 64, "parts of 64 rows");
   __shared__ double ys[NB * TR_COLS];
   __shared__ double xs[NB * TR_COLS];
   __shared__ double ps[TR_THREADS * TR_COLS];  // partial sums of tr_update; block inverses for TRANS
   __shared__ int s_abort;
-  const int i = TRANS ? static_cast<int>(blockIdx.x) : q - 1 - static_cast<int>(blockIdx.x);
+  const int blk = static_cast<int>(blockIdx.x) / GP, part = static_cast<int>(blockIdx.x) % GP;
+  const int i = TRANS ? blk : q - 1 - blk;
   const int tid = threadIdx.x;
   const int64_t r0 = static_cast<int64_t>(i) * NB;
   for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
     const int c = e / NB, r = e % NB;
-    ys[e] = c < nc ? Y[c * ldy + r0 + r] : 0.0;
+    ys[e] = c < nc ? Yin[c * ldin + r0 + r] : 0.0;
   }
   if (tid == 0) s_abort = 0;
   const double* Rd = tiles + (static_cast<size_t>(i) * p + i) * NB * NB;
@@ -352,18 +402,21 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
   double xinv[32];
   if (!INV) block_inverse<NB, TRANS>(Rd, wave, rr, half, xinv, ps + wave * 32 * 32);
   __syncthreads();
-  // Wait for row k's flag, then xs = X_k; false when the wait failed.
+  // Wait for the flags of row k (all its parts), then xs = X_k; false when
+  // the wait failed.
   auto fetch = [&](int k) {
     if (tid == 0) {
       const uint64_t t0 = wall_clock64();
-      while (__hip_atomic_load(flags + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-        if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-            static_cast<int64_t>(wall_clock64() - t0) > spin_ticks) {
-          __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          s_abort = 1;
-          break;
+      for (int g = 0; g < GP && !s_abort; ++g) {
+        while (__hip_atomic_load(flags + k * GP + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+          if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+              static_cast<int64_t>(wall_clock64() - t0) > spin_ticks) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_abort = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
         }
-        __builtin_amdgcn_s_sleep(1);
       }
     }
     __syncthreads();
@@ -405,20 +458,24 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
       tile_gemv<NB, TRANS>(ys, xs, Rinv + static_cast<size_t>(i) * NB * NB, nc, ps);
     sign = -1.0;
     if (coupled) {
-      // ys = -z_i - Wn_i X_last = -X_i.
+      // ys = -z_i - Wn_i X_last = -X_i (this part's rows with GP > 1).
       if (!fetch(k_end)) return;
-      tile_gemv<NB, false>(ys, xs, Wn + static_cast<size_t>(i) * NB * NB, nc, ps);
+      if (GP > 1)
+        rows_gemv<NB, 64>(ys, xs, Wn + static_cast<size_t>(i) * NB * NB, part * 64, nc, ps);
+      else
+        tile_gemv<NB, false>(ys, xs, Wn + static_cast<size_t>(i) * NB * NB, nc, ps);
     }
   } else {
     diag_solve<NB, TRANS>(ys, Rd, xinv, ps, nc, wave, rr, half);
   }
-  for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
-    const int c = e / NB, r = e % NB;
-    if (c < nc) st_coh(Y + c * ldy + r0 + r, sign * ys[e]);
+  constexpr int PR = NB / GP;  // rows stored by this workgroup
+  for (int e = tid; e < PR * TR_COLS; e += TR_THREADS) {
+    const int c = e / PR, r = part * PR + e % PR;
+    if (c < nc) st_coh(Y + c * ldy + r0 + r, sign * ys[c * NB + r]);
   }
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
-  if (tid == 0) __hip_atomic_store(flags + i, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (tid == 0) __hip_atomic_store(flags + i * GP + part, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Tile transposes for the R^T solve: block (a, b), a >= b, writes
@@ -582,28 +639,50 @@ template <bool TRANS>
 static hipError_t trsm_launch(const double* tiles, const double* Rt, const double* Rinv, const double* Wn, int p, int q,
                               int nb, double* Y, int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch,
                               int32_t* err, int64_t spin_ticks, hipStream_t s) {
+  // Parts per tile row: NB / 64 workgroups with the coupling tiles at
+  // NB >= 128, else one; then the right-hand sides are read from a copy.
+  const int gp = (Rinv && Wn && nb >= 128) ? nb / 64 : 1;
+  const int64_t n = static_cast<int64_t>(q) * nb;
+  double* Ycopy = nullptr;
+  if (gp > 1) {
+    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&Ycopy), static_cast<size_t>(n) * nrhs * sizeof(double), s);
+    if (e == hipSuccess)
+      e = hipMemcpy2DAsync(Ycopy, n * sizeof(double), Y, ldy * sizeof(double), n * sizeof(double), nrhs,
+                           hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) {
+      if (Ycopy) (void)hipFreeAsync(Ycopy, s);
+      return e;
+    }
+  }
   for (int64_t c0 = 0; c0 < nrhs; c0 += TR_COLS) {
     const int nc = static_cast<int>(nrhs - c0 < TR_COLS ? nrhs - c0 : TR_COLS);
     const int32_t ep = ++*epoch;
     double* Yc = Y + c0 * ldy;
-    switch (nb * 2 + (Rinv ? 1 : 0)) {
-#define TQR_TRSM(NBV, INVV)                                                                                      \
-  case NBV * 2 + INVV:                                                                                           \
-    hipLaunchKernelGGL((trsm_wave_kernel<NBV, TRANS, INVV>), dim3(q), dim3(TR_THREADS), 0, s, tiles, Rt, Rinv, Wn, p, q, \
-                       Yc, ldy, nc, flags, ep, spin_ticks, err);                                                 \
+    const double* Yi = gp > 1 ? Ycopy + c0 * n : Yc;
+    const int64_t ldi = gp > 1 ? n : ldy;
+    switch (nb * 4 + (Rinv ? 2 : 0) + (gp > 1 ? 1 : 0)) {
+#define TQR_TRSM(NBV, INVV, GPV)                                                                                  \
+  case NBV * 4 + INVV * 2 + (GPV > 1 ? 1 : 0):                                                                   \
+    hipLaunchKernelGGL((trsm_wave_kernel<NBV, TRANS, INVV, GPV>), dim3(q * GPV), dim3(TR_THREADS), 0, s, tiles, Rt, \
+                       Rinv, Wn, p, q, Yi, ldi, Yc, ldy, nc, flags, ep, spin_ticks, err);                        \
     break;
-      TQR_TRSM(32, 0)
-      TQR_TRSM(32, 1)
-      TQR_TRSM(64, 0)
-      TQR_TRSM(64, 1)
-      TQR_TRSM(128, 0)
-      TQR_TRSM(128, 1)
-      TQR_TRSM(256, 0)
-      TQR_TRSM(256, 1)
+      TQR_TRSM(32, 0, 1)
+      TQR_TRSM(32, 1, 1)
+      TQR_TRSM(64, 0, 1)
+      TQR_TRSM(64, 1, 1)
+      TQR_TRSM(128, 0, 1)
+      TQR_TRSM(128, 1, 1)
+      TQR_TRSM(128, 1, 2)
+      TQR_TRSM(256, 0, 1)
+      TQR_TRSM(256, 1, 1)
+      TQR_TRSM(256, 1, 4)
 #undef TQR_TRSM
-      default: return hipErrorInvalidValue;
+      default:
+        if (Ycopy) (void)hipFreeAsync(Ycopy, s);
+        return hipErrorInvalidValue;
     }
   }
+  if (Ycopy) (void)hipFreeAsync(Ycopy, s);
   return hipGetLastError();
 }
 
