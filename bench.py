@@ -48,8 +48,8 @@ UNITS = (4, 6, 6, 12, 2, 6)
 # (calibrated by a plain copy; profiles/hbm_traffic_square10240_nb256.md),
 # keyed by (workload, update precision, tree, BS, kernels, nb) and valid for
 # the executor sources with the given SHA-256 prefix only.
-TRAFFIC = {("square", "f32", "plasma", 16, "ts", 256): (88.603e9, "2b12d75b7a27b848"),
-           ("square", "f64", "plasma", 16, "ts", 256): (90.277e9, "2b12d75b7a27b848")}
+TRAFFIC = {("square", "f32", "plasma", 16, "ts", 256): (88.920e9, "c568be352b4b9688"),
+           ("square", "f64", "plasma", 16, "ts", 256): (90.097e9, "c568be352b4b9688")}
 
 
 def executor_source_hash():
