@@ -51,7 +51,9 @@ class Factors:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h and getattr(self, "owner", None) is None:
-            _lib.tiledqr_destroy(h)
+            destroy = getattr(_lib, "tiledqr_destroy", None)
+            if destroy is not None:  # None once the interpreter tears modules down
+                destroy(h)
         self.handle = None
 
     def sync(self):
@@ -193,7 +195,9 @@ class Batch:
     def __del__(self):
         h = getattr(self, "handle", None)
         if h:
-            _lib.tiledqr_batch_destroy(h)
+            destroy = getattr(_lib, "tiledqr_batch_destroy", None)
+            if destroy is not None:  # None once the interpreter tears modules down
+                destroy(h)
             self.handle = None
 
     def run(self, mats):
