@@ -180,14 +180,16 @@ typedef struct {      /* host memory, filled by tiledqr_lstsq */
  * for A0 = QR and costs two products with A0 and one more triangular solve
  * instead of an application of Q^T); method 0 takes semi-normal steps
  * while each one cuts the backward error at least fourfold, then (after
- * undoing a step that raised it) classical ones.  Tall systems refine the
- * augmented system [I A0; A0^T 0][r; x] = [b; 0] (Bjorck 1967) with the same
- * factors: residuals f = b - r - A0 x and g = -A0^T r in FP64, corrections
- * h = R^{-T} g, d = Q^T f, dx = R^{-1}(d(1:n) - h), dr = Q [h; d(n+1:m)].
- * method 2 selects the augmented system for square systems too.  The
+ * undoing a step that raised it) classical ones.  Tall systems take the
+ * same semi-normal steps (method 0 or 3), and with method 0 (or methods 1
+ * and 2) then refine the augmented system [I A0; A0^T 0][r; x] = [b; 0]
+ * (Bjorck 1967) with the same factors: residuals f = b - r - A0 x and
+ * g = -A0^T r in FP64, corrections h = R^{-T} g, d = Q^T f,
+ * dx = R^{-1}(d(1:n) - h), dr = Q [h; d(n+1:m)].  method 2 selects the
+ * augmented system for square systems too.  The
  * backward error of x (r = b - A0 x, norms 2-norms per column, ||A0||_F) is
- * ||r|| / (||A0|| ||x|| + ||b||) for classical refinement; the augmented
- * refinement takes the smaller of that and ||A0^T r|| / (||A0|| ||r||).
+ * ||r|| / (||A0|| ||x|| + ||b||) for square systems; for tall systems the
+ * smaller of that and ||A0^T r|| / (||A0|| ||r||).
  * Synchronizes the stream once per refinement iteration.  Returns
  * TQR_ENOTCONV (info filled, X holding the last iterate) if the tolerance is
  * not reached within max_iter or the error stops halving over three

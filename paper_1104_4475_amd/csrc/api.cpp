@@ -865,7 +865,11 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
     return fail(TQR_OK);
   }
   const int max_iter = r->max_iter > 0 ? r->max_iter : 30;
-  if (m != n || r->method == 2) {
+  const bool tall = m != n;
+  // Tall systems: semi-normal corrections (methods 0 and 3), with the
+  // augmented system taking over for method 0; methods 1 and 2: the
+  // augmented system.
+  if (r->method == 2 || (tall && r->method != 0 && r->method != 3)) {
     st = refine_augmented(F, A0, lda, B, ldb, nrhs, X, ldx, r->tol, max_iter, Bt, ncolB, info, s);
     return fail(st);
   }
@@ -873,15 +877,14 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
   if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Rv), rv_elems * sizeof(double), s)) ||
       !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&D), static_cast<size_t>(n) * nrhs * sizeof(double), s)) ||
       !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Xp), static_cast<size_t>(n) * nrhs * sizeof(double), s)) ||
-      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&nrm), (3 * nrhs + 1) * sizeof(double), s)))
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&nrm), 4 * nrhs * sizeof(double), s)))
     return fail(TQR_ENOMEM);
   // Corrections: semi-normal (method 3, and method 0 while each one cuts
-  // the backward error at least fourfold) or classical with Q (method 1,
-  // and method 0 from then on).
+  // the backward error at least fourfold) or, after that, classical with Q
+  // (square) or the augmented system (tall).
   bool semi = r->method == 0 || r->method == 3;
-  // ||A||_F^2 and ||b||^2 once.
-  double* nA = nrm + 3 * nrhs;
-  if (!hip_ok(hipMemsetAsync(nrm, 0, (3 * nrhs + 1) * sizeof(double), s))) return fail(TQR_EHIP);
+  // nrm: ||r||^2, ||x||^2, ||b||^2 (once), ||A^T r||^2 (tall) per column.
+  if (!hip_ok(hipMemsetAsync(nrm, 0, 4 * nrhs * sizeof(double), s))) return fail(TQR_EHIP);
   std::vector<double> colA(static_cast<size_t>(n));
   {
     double* ca = nullptr;
@@ -893,21 +896,24 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
     (void)hipFreeAsync(ca, s);
     if (!ok) return fail(TQR_EHIP);
   }
-  (void)nA;
-  std::vector<double> h(3 * nrhs);
+  std::vector<double> h(4 * nrhs);
   double best = INFINITY, eta = INFINITY;
   std::vector<double> hist;
   int it = 0;
   bool conv = false;
   for (;; ++it) {
-    // residual and norms
+    // residual and norms (tall: also A^T r into D, used by the correction)
     if (!hip_ok(tqr::launch_residual(A0, lda, m, n, X, ldx, B, ldb, nrhs, Rv, m, s))) return fail(TQR_EHIP);
     if (!hip_ok(hipMemsetAsync(nrm, 0, 2 * nrhs * sizeof(double), s))) return fail(TQR_EHIP);
     if (!hip_ok(tqr::launch_colnorms2(Rv, m, m, nrhs, nrm, s)) ||
         !hip_ok(tqr::launch_colnorms2(X, ldx, n, nrhs, nrm + nrhs, s)))
       return fail(TQR_EHIP);
+    if (tall && (!hip_ok(tqr::launch_gemv_t(A0, lda, m, n, Rv, m, nrhs, D, n, 1.0, s)) ||
+                 !hip_ok(hipMemsetAsync(nrm + 3 * nrhs, 0, nrhs * sizeof(double), s)) ||
+                 !hip_ok(tqr::launch_colnorms2(D, n, n, nrhs, nrm + 3 * nrhs, s))))
+      return fail(TQR_EHIP);
     int32_t serr = 0;
-    if (!hip_ok(hipMemcpyAsync(h.data(), nrm, 3 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s)) ||
+    if (!hip_ok(hipMemcpyAsync(h.data(), nrm, 4 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s)) ||
         !hip_ok(hipMemcpyAsync(&serr, F->ctl + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s)) ||
         !hip_ok(hipStreamSynchronize(s)))
       return fail(TQR_EHIP);
@@ -917,8 +923,13 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
     fa = std::sqrt(fa);
     eta = 0.0;
     for (int64_t c = 0; c < nrhs; ++c) {
+      const double nr = std::sqrt(h[c]);
       const double den = fa * std::sqrt(h[nrhs + c]) + std::sqrt(h[2 * nrhs + c]);
-      eta = std::max(eta, den > 0 ? std::sqrt(h[c]) / den : 0.0);
+      double e = den > 0 ? nr / den : 0.0;
+      // tall: the smaller of that and ||A^T r|| / (||A|| ||r||), as in the
+      // augmented refinement
+      if (tall && nr > 0 && fa > 0) e = std::min(e, std::sqrt(h[3 * nrhs + c]) / (fa * nr));
+      eta = std::max(eta, e);
     }
     best = std::min(best, eta);
     hist.push_back(eta);
@@ -928,14 +939,22 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
     }
     if (semi && r->method == 0 && hist.size() >= 2 && eta > 0.25 * hist[hist.size() - 2]) {
       semi = false;
-      if (eta > hist[hist.size() - 2]) {
+      const bool undo = eta > hist[hist.size() - 2];
+      if (undo) {
         // The last semi-normal step did not help: back to its starting
         // point, then classical corrections.
         hist.pop_back();
         eta = hist.back();
         if (!hip_ok(tqr::launch_copy_cols(Xp, n, X, ldx, n, nrhs, s))) return fail(TQR_EHIP);
-        continue;
       }
+      if (tall) {
+        // The augmented system from here, with the iterations left.
+        st = refine_augmented(F, A0, lda, B, ldb, nrhs, X, ldx, r->tol, std::max(1, max_iter - it), Bt, ncolB,
+                              info, s);
+        if (info) info->iters += it;
+        return fail(st);
+      }
+      if (undo) continue;
     }
     if (it >= max_iter) break;
     if (hist.size() > 3 && hist.back() > 0.5 * hist[hist.size() - 4]) break;
@@ -943,12 +962,13 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
       // Semi-normal correction D = R^{-1} R^{-T} A^T Rv (A = QR gives
       // R^{-T} A^T = Q^T); X += D.
       if (r->method == 0 && !hip_ok(tqr::launch_copy_cols(X, ldx, Xp, n, n, nrhs, s))) return fail(TQR_EHIP);
-      if (!hip_ok(tqr::launch_gemv_t(A0, lda, m, n, Rv, m, nrhs, D, n, 1.0, s)) ||
+      if ((!tall && !hip_ok(tqr::launch_gemv_t(A0, lda, m, n, Rv, m, nrhs, D, n, 1.0, s))) ||
           !hip_ok(solve_rt(F, D, n, nrhs, s)) || !hip_ok(solve_r(F, D, n, nrhs, s)) ||
           !hip_ok(tqr::launch_axpy_cols(X, ldx, D, n, n, nrhs, s)))
         return fail(TQR_EHIP);
       continue;
     }
+    if (tall) break;  // method 3 only: no classical step for tall systems
     // correction D = R^{-1} (Q^T Rv)(1:n); X += D
     if (!hip_ok(tqr::launch_pack_b(Rv, m, nrhs, Bt, F->p, F->nb, ncolB, s))) return fail(TQR_EHIP);
     st = apply_tiles(F, 1, Bt, ncolB, s);
