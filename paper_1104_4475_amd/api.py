@@ -131,8 +131,11 @@ class Factors:
 
     def lstsq(self, B, A0=None, tol=0.0, max_iter=30, method=0, raise_on_noconv=False, QtB=None):
         """Solve min ||B - A X||.  With tol > 0 the solution is refined
-        against A0 (the original matrix).  QtB: Q^T B already computed (from
-        refactor_qtb).  Returns (X, info dict)."""
+        against A0 (the original matrix); method: 0 auto (semi-normal
+        corrections, then classical for square or the augmented system for
+        tall matrices), 1 classical, 2 augmented system, 3 semi-normal only
+        (tiledqr_lstsq).  QtB: Q^T B already computed (from refactor_qtb).
+        Returns (X, info dict)."""
         torch = _torch()
         B = colmajor(B)
         nrhs = B.shape[1]
