@@ -70,7 +70,7 @@ typedef enum { TQR_UPD_F64 = 0, TQR_UPD_F32 = 1, TQR_UPD_BF16 = 2 } tqr_update_p
 
 typedef struct {
   int64_t m, n;     /* matrix size; m % nb == 0, n % nb == 0, m >= n >= nb */
-  int32_t nb;       /* tile size: 32, 64, 128 or 256                       */
+  int32_t nb;       /* tile size: 32, 64, 128 or 256 (512: TQR_EUNSUPPORTED) */
   int32_t ib;       /* inner block size: 0 = default (32); must be 32      */
   int32_t tree;     /* tqr_tree                                            */
   int32_t bs;       /* PlasmaTree domain size, ignored for other trees     */
@@ -99,7 +99,8 @@ int tiledqr_last_hip_error(void);
  * waiting only for block b of the previous panel task on the same triangle
  * (environment TQR_PANEL_SPLIT=0 keeps whole panel tasks).
  * Errors: TQR_EINVAL (null pointer, m % nb, n % nb, m < n, nb or ib not
- * supported, bs outside [1, p] for PlasmaTree, lda < m), TQR_ENOMEM,
+ * valid, bs outside [1, p] for PlasmaTree, lda < m), TQR_EUNSUPPORTED
+ * (nb = 512: a valid tile size without kernels here), TQR_ENOMEM,
  * TQR_EHIP. */
 int tiledqr_factor(const tqr_opts* opts, const double* A, int64_t lda,
                    tqr_factors** F, void* stream);
@@ -152,6 +153,24 @@ int tiledqr_exec_time(tqr_factors* F, float* ms);
 int tiledqr_set_trace(tqr_factors* F, int enable);
 int tiledqr_get_trace(tqr_factors* F, int64_t* out, int64_t* n, double* ticks_per_second);
 
+/* The executor's subtask table of the factorization (host copy, dispatch
+ * order): sub (host, 8 int32 per subtask, may be NULL) = kind, i, piv, k, j
+ * (0-based tiles), slab (column slab of an update, inner block of a panel
+ * subtask or -1 for a whole panel task), dep_begin, dep_end; deps (host,
+ * may be NULL) = the predecessor indices of subtask t in
+ * deps[dep_begin .. dep_end - 1], all smaller than t.  These are the edges of
+ * the DAG of Sec. 2.3 refined to subtasks.  Errors: TQR_EINVAL. */
+int tiledqr_exec_plan(const tqr_factors* F, int32_t* sub, int64_t* nsub, int32_t* deps, int64_t* ndeps);
+
+/* X (device, n x nrhs, ldx >= n) <- R^{-1} X (trans 'N') or R^{-T} X (trans
+ * 'T') in place, with the upper triangular factor R held in the handle
+ * (Sec. 1: the back substitution of least squares).  Uses and, on the first
+ * call after a factorization, forms the same diagonal-tile inverses and
+ * coupling tiles as tiledqr_lstsq.  Errors: TQR_EINVAL (null, ldx < n,
+ * nrhs < 0, trans), TQR_ENOMEM, TQR_EHIP; a device wait time limit is
+ * reported by tiledqr_sync. */
+int tiledqr_solve_r(const tqr_factors* F, char trans, double* X, int64_t ldx, int64_t nrhs, void* stream);
+
 /* Release a handle (synchronizes its stream first).  NULL is accepted. */
 int tiledqr_destroy(tqr_factors* F);
 
@@ -160,14 +179,16 @@ int tiledqr_destroy(tqr_factors* F);
 typedef struct {
   double tol;        /* target backward error (e.g. 1e-12); <= 0: no refinement */
   int32_t max_iter;  /* refinement iterations (default 30 if <= 0)          */
-  int32_t method;    /* 0 auto, 1 classical (square), 2 augmented system,
-                        3 semi-normal corrections (square)                  */
+  int32_t method;    /* 0 auto, 1 classical (square) / augmented (tall),
+                        2 augmented system, 3 semi-normal corrections only  */
 } tqr_refine;
 
 typedef struct {      /* host memory, filled by tiledqr_lstsq */
-  int32_t iters;
+  int32_t iters;        /* corrections computed (an undone one included)    */
   int32_t converged;
-  double backward_err;  /* max over right-hand sides                        */
+  double backward_err;  /* of the returned X, max over right-hand sides     */
+  int32_t semi_normal;  /* semi-normal corrections kept                     */
+  int32_t augmented;    /* augmented-system iterations                      */
 } tqr_refine_info;
 
 /* X (device, n x nrhs, ldx >= n) <- argmin ||B - A X|| using the factors F
@@ -191,8 +212,9 @@ typedef struct {      /* host memory, filled by tiledqr_lstsq */
  * ||r|| / (||A0|| ||x|| + ||b||) for square systems; for tall systems the
  * smaller of that and ||A0^T r|| / (||A0|| ||r||).
  * Synchronizes the stream once per refinement iteration.  Returns
- * TQR_ENOTCONV (info filled, X holding the last iterate) if the tolerance is
- * not reached within max_iter or the error stops halving over three
+ * TQR_ENOTCONV (info filled, X holding the iterate with the smallest
+ * backward error seen, info->backward_err its error) if the tolerance is not
+ * reached within max_iter or the error stops halving over three
  * iterations.  The triangular solves use the inverses of the q diagonal
  * tiles of R and the coupling tiles -inv(R_ii) R_{i,i+1}, formed on the
  * first solve after a factorization (2 q nb^2 doubles of device memory

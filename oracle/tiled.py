@@ -19,7 +19,11 @@ row signs), by numpy.linalg.qr / numpy.linalg.lstsq, and by the residual and
 orthogonality bounds ||A - QR||_F / ||A||_F <= 50 n eps and
 ||Q^T Q - I||_F <= 50 n eps (tests/test_oracle_tiled.py).  The refinement
 loop is pinned on the CPU by planting a perturbed factorization and checking
-that it converges to the FP64 solution.
+that it converges to the FP64 solution.  backward_error is pinned by hand
+values (square and tall, with ||A||_F != ||A||_2), by the perturbations of
+the Rigal-Gaches theorem that attain it, by its zeros (exact and
+least-squares solutions, b orthogonal to range(A)) and by its invariance
+under A, b -> cA, cb.
 """
 
 import numpy as np

@@ -15,7 +15,7 @@ from ._lib import (  # noqa: F401
     TiledQRError, lib, lib_path, Opts, RefineOpts, RefineInfo,
     tiledqr_factor, tiledqr_refactor, tiledqr_sync, tiledqr_apply_q, tiledqr_get_r,
     tiledqr_get_packed, tiledqr_get_tau, tiledqr_destroy, tiledqr_lstsq, tiledqr_exec_time,
-    tiledqr_set_trace, tiledqr_get_trace,
+    tiledqr_set_trace, tiledqr_get_trace, tiledqr_exec_plan, tiledqr_solve_r,
     tiledqr_factor_batched, tiledqr_refactor_qtb, tiledqr_lstsq_qtb, tiledqr_batch_create, tiledqr_batch_run, tiledqr_batch_sync, tiledqr_batch_time,
     tiledqr_batch_get, tiledqr_batch_destroy, tiledqr_elim_list, tiledqr_schedule, tiledqr_task_preds,
     tiledqr_strerror, elim_list, schedule, task_preds,

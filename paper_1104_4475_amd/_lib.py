@@ -38,7 +38,8 @@ class RefineOpts(ctypes.Structure):
 
 
 class RefineInfo(ctypes.Structure):
-    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("backward_err", ctypes.c_double)]
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32), ("backward_err", ctypes.c_double),
+                ("semi_normal", ctypes.c_int32), ("augmented", ctypes.c_int32)]
 
 
 class TiledQRError(RuntimeError):
@@ -64,6 +65,8 @@ _sigs = {
     "tiledqr_get_packed": (ctypes.c_int, [_vp, _dp, _i64, _vp]),
     "tiledqr_get_tau": (ctypes.c_int, [_vp, _dp, _vp]),
     "tiledqr_destroy": (ctypes.c_int, [_vp]),
+    "tiledqr_exec_plan": (ctypes.c_int, [_vp, _P(_i32), _P(_i64), _P(_i32), _P(_i64)]),
+    "tiledqr_solve_r": (ctypes.c_int, [_vp, ctypes.c_char, _dp, _i64, _i64, _vp]),
     "tiledqr_exec_time": (ctypes.c_int, [_vp, _P(ctypes.c_float)]),
     "tiledqr_set_trace": (ctypes.c_int, [_vp, ctypes.c_int]),
     "tiledqr_get_trace": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(ctypes.c_double)]),

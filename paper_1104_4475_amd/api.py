@@ -81,6 +81,28 @@ class Factors:
                                      ctypes.byref(n), ctypes.byref(rate)), "tiledqr_get_trace")
         return out[:n.value], rate.value
 
+    def exec_plan(self):
+        """Executor subtasks of the factorization in dispatch order: int32
+        array (n, 8) = kind, i, piv, k, j, slab, dep_begin, dep_end, and the
+        int32 predecessor array (tiledqr_exec_plan)."""
+        import numpy as np
+        n, nd = ctypes.c_int64(), ctypes.c_int64()
+        check(_lib.tiledqr_exec_plan(self.handle, None, ctypes.byref(n), None, ctypes.byref(nd)), "tiledqr_exec_plan")
+        sub = np.zeros((max(1, n.value), 8), dtype=np.int32)
+        deps = np.zeros(max(1, nd.value), dtype=np.int32)
+        P = ctypes.POINTER(ctypes.c_int32)
+        check(_lib.tiledqr_exec_plan(self.handle, sub.ctypes.data_as(P), ctypes.byref(n), deps.ctypes.data_as(P),
+                                     ctypes.byref(nd)), "tiledqr_exec_plan")
+        return sub[:n.value], deps[:nd.value]
+
+    def solve_r(self, X, trans="N"):
+        """Return R^{-1} X (trans 'N') or R^{-T} X (trans 'T') for X with n
+        rows (tiledqr_solve_r); X is not modified."""
+        X = colmajor(X).clone()
+        check(_lib.tiledqr_solve_r(self.handle, trans.encode(), X.data_ptr(), _ld(X), X.shape[1], _stream()),
+              "tiledqr_solve_r")
+        return X
+
     def refactor(self, A):
         A = colmajor(A)
         check(_lib.tiledqr_refactor(self.handle, A.data_ptr(), _ld(A), _stream()), "tiledqr_refactor")
@@ -156,7 +178,8 @@ class Factors:
         if st != _lib.TQR_OK and not (st == _lib.TQR_ENOTCONV and not raise_on_noconv):
             raise _lib.TiledQRError(st, "tiledqr_lstsq")
         return X, {"iters": info.iters, "converged": bool(info.converged),
-                   "backward_err": info.backward_err, "status": st}
+                   "backward_err": info.backward_err, "semi_normal": info.semi_normal,
+                   "augmented": info.augmented, "status": st}
 
 
 def factor(A, nb, tree=_lib.TREE_GREEDY, bs=1, kernels=_lib.KERN_DEFAULT, upd=_lib.UPD_F64):

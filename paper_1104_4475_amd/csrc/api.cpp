@@ -39,6 +39,10 @@ bool hip_ok(hipError_t e) {
   } while (0)
 
 bool nb_supported(int nb) { return nb == 32 || nb == 64 || nb == 128 || nb == 256; }
+// Tile sizes that are valid for the method but have no kernels here: an
+// FP64 tile of 512 is 2 MB, and the update kernels keep a column slab of a
+// whole tile in registers (half the register file of a workgroup at 256).
+bool nb_unsupported(int nb) { return nb == 512; }
 
 // Device copy of an executor plan with its flags.
 struct DevPlan {
@@ -377,6 +381,7 @@ int run_plan(tqr_factors* F, DevPlan& d, ExecArgs a, hipStream_t s) {
 int check_opts(const tqr_opts* o, int64_t lda) {
   if (!o) return TQR_EINVAL;
   if (o->nb <= 0 || o->m <= 0 || o->n <= 0) return TQR_EINVAL;
+  if (nb_unsupported(o->nb)) return TQR_EUNSUPPORTED;
   if (!nb_supported(o->nb)) return TQR_EINVAL;
   if (o->ib != 0 && o->ib != tqr::IB) return TQR_EINVAL;
   if (o->m % o->nb || o->n % o->nb || o->m < o->n) return TQR_EINVAL;
@@ -480,9 +485,10 @@ int refine_augmented(const tqr_factors* F, const double* A0, int64_t lda, const 
                      int64_t nrhs, double* X, int64_t ldx, double tol, int max_iter, double* Bt, int ncolB,
                      tqr_refine_info* info, hipStream_t s) {
   const int64_t m = F->o.m, n = F->o.n;
-  double *Rv = nullptr, *Rr = nullptr, *Z = nullptr, *H = nullptr, *D = nullptr, *nrm = nullptr, *ca = nullptr;
+  double *Rv = nullptr, *Rr = nullptr, *Z = nullptr, *H = nullptr, *D = nullptr, *nrm = nullptr, *ca = nullptr,
+         *Xb = nullptr;
   auto done = [&](int code) {
-    for (double* ptr : {Rv, Rr, Z, H, D, nrm, ca})
+    for (double* ptr : {Rv, Rr, Z, H, D, nrm, ca, Xb})
       if (ptr) (void)hipFreeAsync(ptr, s);
     return code;
   };
@@ -492,6 +498,7 @@ int refine_augmented(const tqr_factors* F, const double* A0, int64_t lda, const 
       !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Z), mb, s)) ||
       !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&H), nbytes, s)) ||
       !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&D), nbytes, s)) ||
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Xb), nbytes, s)) ||
       !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&nrm), 4 * nrhs * sizeof(double), s)) ||
       !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&ca), n * sizeof(double), s)))
     return done(TQR_ENOMEM);
@@ -512,7 +519,7 @@ int refine_augmented(const tqr_factors* F, const double* A0, int64_t lda, const 
   if (!hip_ok(tqr::launch_residual(A0, lda, m, n, X, ldx, B, ldb, nrhs, Rr, m, s))) return done(TQR_EHIP);
   std::vector<double> h(3 * nrhs);
   std::vector<double> hist;
-  double eta = INFINITY;
+  double eta = INFINITY, best = INFINITY;
   int it = 0;
   bool conv = false;
   for (;; ++it) {
@@ -543,6 +550,10 @@ int refine_augmented(const tqr_factors* F, const double* A0, int64_t lda, const 
       conv = true;
       break;
     }
+    if (eta < best) {  // keep the best iterate for a non-converged return
+      best = eta;
+      if (!hip_ok(tqr::launch_copy_cols(X, ldx, Xb, n, n, nrhs, s))) return done(TQR_EHIP);
+    }
     if (it >= max_iter) break;
     if (hist.size() > 3 && hist.back() > 0.5 * hist[hist.size() - 4]) break;
     // f = b - A x - r (in Rv), h = R^{-T} (-A^T r)
@@ -570,10 +581,16 @@ int refine_augmented(const tqr_factors* F, const double* A0, int64_t lda, const 
         !hip_ok(tqr::launch_axpy_cols(Rr, m, Z, m, m, nrhs, s)))
       return done(TQR_EHIP);
   }
+  if (!conv && eta > best) {  // return the best iterate seen
+    if (!hip_ok(tqr::launch_copy_cols(Xb, n, X, ldx, n, nrhs, s))) return done(TQR_EHIP);
+    eta = best;
+  }
   if (info) {
     info->iters = it;
     info->converged = conv ? 1 : 0;
     info->backward_err = eta;
+    info->semi_normal = 0;
+    info->augmented = it;
   }
   return done(conv ? TQR_OK : TQR_ENOTCONV);
 }
@@ -676,6 +693,38 @@ int tiledqr_get_trace(tqr_factors* F, int64_t* out, int64_t* n, double* ticks_pe
     o[8] = t[4 * s + 2];
     o[9] = t[4 * s + 3];
   }
+  return TQR_OK;
+}
+
+int tiledqr_exec_plan(const tqr_factors* F, int32_t* sub, int64_t* nsub, int32_t* deps, int64_t* ndeps) {
+  if (!F || !nsub || !ndeps) return TQR_EINVAL;
+  const tqr::ExecPlan& ex = F->exec_host;
+  *nsub = static_cast<int64_t>(ex.sub.size());
+  *ndeps = static_cast<int64_t>(ex.deps.size());
+  if (sub)
+    for (size_t t = 0; t < ex.sub.size(); ++t) {
+      const tqr::SubTask& st = ex.sub[t];
+      int32_t* o = sub + 8 * t;
+      o[0] = st.kind;
+      o[1] = st.i;
+      o[2] = st.piv;
+      o[3] = st.k;
+      o[4] = st.j;
+      o[5] = st.slab;
+      o[6] = st.dep_begin;
+      o[7] = st.dep_end;
+    }
+  if (deps) std::copy(ex.deps.begin(), ex.deps.end(), deps);
+  return TQR_OK;
+}
+
+int tiledqr_solve_r(const tqr_factors* F, char trans, double* X, int64_t ldx, int64_t nrhs, void* stream) {
+  if (!F || (!X && nrhs > 0) || ldx < F->o.n || nrhs < 0 || nrhs > (1 << 20)) return TQR_EINVAL;
+  const bool t = trans == 'T' || trans == 't';
+  if (!t && trans != 'N' && trans != 'n') return TQR_EINVAL;
+  if (nrhs == 0) return TQR_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(t ? solve_rt(F, X, ldx, nrhs, s) : solve_r(F, X, ldx, nrhs, s));
   return TQR_OK;
 }
 
@@ -835,14 +884,11 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
   const int64_t m = F->o.m, n = F->o.n;
   const int ncolB = static_cast<int>((nrhs + 15) / 16 * 16);
   const size_t bt_elems = static_cast<size_t>(F->p) * F->nb * ncolB;
-  double *Bt = nullptr, *Rv = nullptr, *D = nullptr, *nrm = nullptr, *Xp = nullptr;
+  double *Bt = nullptr, *Rv = nullptr, *D = nullptr, *nrm = nullptr, *Xp = nullptr, *Xb = nullptr;
   int st = TQR_OK;
   auto fail = [&](int code) {
-    if (Bt) (void)hipFreeAsync(Bt, s);
-    if (Rv) (void)hipFreeAsync(Rv, s);
-    if (D) (void)hipFreeAsync(D, s);
-    if (nrm) (void)hipFreeAsync(nrm, s);
-    if (Xp) (void)hipFreeAsync(Xp, s);
+    for (double* ptr : {Bt, Rv, D, nrm, Xp, Xb})
+      if (ptr) (void)hipFreeAsync(ptr, s);
     return code;
   };
   if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Bt), bt_elems * sizeof(double), s))) return fail(TQR_ENOMEM);
@@ -861,6 +907,8 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
       info->iters = 0;
       info->converged = 1;
       info->backward_err = -1.0;
+      info->semi_normal = 0;
+      info->augmented = 0;
     }
     return fail(TQR_OK);
   }
@@ -874,9 +922,11 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
     return fail(st);
   }
   const size_t rv_elems = static_cast<size_t>(m) * nrhs;
+  const size_t nx_bytes = static_cast<size_t>(n) * nrhs * sizeof(double);
   if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Rv), rv_elems * sizeof(double), s)) ||
-      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&D), static_cast<size_t>(n) * nrhs * sizeof(double), s)) ||
-      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Xp), static_cast<size_t>(n) * nrhs * sizeof(double), s)) ||
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&D), nx_bytes, s)) ||
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Xp), nx_bytes, s)) ||
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Xb), nx_bytes, s)) ||
       !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&nrm), 4 * nrhs * sizeof(double), s)))
     return fail(TQR_ENOMEM);
   // Corrections: semi-normal (method 3, and method 0 while each one cuts
@@ -899,7 +949,7 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
   std::vector<double> h(4 * nrhs);
   double best = INFINITY, eta = INFINITY;
   std::vector<double> hist;
-  int it = 0;
+  int it = 0, nsemi = 0;
   bool conv = false;
   for (;; ++it) {
     // residual and norms (tall: also A^T r into D, used by the correction)
@@ -931,7 +981,6 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
       if (tall && nr > 0 && fa > 0) e = std::min(e, std::sqrt(h[3 * nrhs + c]) / (fa * nr));
       eta = std::max(eta, e);
     }
-    best = std::min(best, eta);
     hist.push_back(eta);
     if (eta <= r->tol) {
       conv = true;
@@ -945,16 +994,26 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
         // point, then classical corrections.
         hist.pop_back();
         eta = hist.back();
+        --nsemi;
         if (!hip_ok(tqr::launch_copy_cols(Xp, n, X, ldx, n, nrhs, s))) return fail(TQR_EHIP);
       }
       if (tall) {
-        // The augmented system from here, with the iterations left.
+        // The augmented system from here, with the iterations left (it
+        // keeps the best of its own iterates, the first of which is this
+        // one, the best so far).
         st = refine_augmented(F, A0, lda, B, ldb, nrhs, X, ldx, r->tol, std::max(1, max_iter - it), Bt, ncolB,
                               info, s);
-        if (info) info->iters += it;
+        if (info) {
+          info->iters += it;
+          info->semi_normal = nsemi;
+        }
         return fail(st);
       }
       if (undo) continue;
+    }
+    if (eta < best) {  // keep the best iterate for a non-converged return
+      best = eta;
+      if (!hip_ok(tqr::launch_copy_cols(X, ldx, Xb, n, n, nrhs, s))) return fail(TQR_EHIP);
     }
     if (it >= max_iter) break;
     if (hist.size() > 3 && hist.back() > 0.5 * hist[hist.size() - 4]) break;
@@ -966,6 +1025,7 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
           !hip_ok(solve_rt(F, D, n, nrhs, s)) || !hip_ok(solve_r(F, D, n, nrhs, s)) ||
           !hip_ok(tqr::launch_axpy_cols(X, ldx, D, n, n, nrhs, s)))
         return fail(TQR_EHIP);
+      ++nsemi;
       continue;
     }
     if (tall) break;  // method 3 only: no classical step for tall systems
@@ -978,10 +1038,16 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
         !hip_ok(tqr::launch_axpy_cols(X, ldx, D, n, n, nrhs, s)))
       return fail(TQR_EHIP);
   }
+  if (!conv && eta > best) {  // return the best iterate seen
+    if (!hip_ok(tqr::launch_copy_cols(Xb, n, X, ldx, n, nrhs, s))) return fail(TQR_EHIP);
+    eta = best;
+  }
   if (info) {
     info->iters = it;
     info->converged = conv ? 1 : 0;
     info->backward_err = eta;
+    info->semi_normal = nsemi;
+    info->augmented = 0;
   }
   return fail(conv ? TQR_OK : TQR_ENOTCONV);
 }
@@ -1114,8 +1180,10 @@ int tiledqr_batch_run(tqr_batch* b, const double* const* A, void* stream) {
   HIP_TRY(hipGraphLaunch(b->gexec, s));
   HIP_TRY(hipEventRecord(b->ev1, s));
   for (tqr_factors* F : b->F) {
+    if (!F) continue;
     F->stream = s;
     F->timed = false;
+    F->rinv_ok = F->rt_ok = false;  // the factors change
   }
   b->stream = s;
   b->ran = true;

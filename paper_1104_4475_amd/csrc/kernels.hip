@@ -1430,15 +1430,18 @@ __device__ __forceinline__ int wait_deps(const LoopCtl& c, int t, int lane) {
 
 // After run(t): every data store of the task is device-coherent, so once
 // each wave has seen its stores complete the flag can be published.
+// The end tick is read before the flag is published, so a successor's ready
+// tick (read after it has seen the flag) is never earlier than it.
 __device__ __forceinline__ void finish_task(const LoopCtl& c, int t, int wave, int lane) {
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (wave == 0 && lane == 0) {
-    __hip_atomic_store(c.flags + t, c.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (c.trace) {
       c.trace[4 * static_cast<int64_t>(t) + 2] = static_cast<int64_t>(wall_clock64());
       c.trace[4 * static_cast<int64_t>(t) + 3] = blockIdx.x;
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);  // keep the clock read before the flag store
     }
+    __hip_atomic_store(c.flags + t, c.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 

@@ -53,6 +53,9 @@ def test_factor_rejects_bad_options_before_any_launch():
     assert _lib.tiledqr_factor(ctypes.byref(o), fake, 100, ctypes.byref(h), None) == tqr.TQR_EINVAL  # lda
     assert _lib.tiledqr_factor(ctypes.byref(o), None, 256, ctypes.byref(h), None) == tqr.TQR_EINVAL
     assert _lib.tiledqr_factor(None, fake, 256, ctypes.byref(h), None) == tqr.TQR_EINVAL
+    # nb = 512 is a valid tile size without kernels here
+    o = _lib.Opts(1024, 512, 512, 0, 4, 1, 0, 0)
+    assert _lib.tiledqr_factor(ctypes.byref(o), fake, 1024, ctypes.byref(h), None) == tqr.TQR_EUNSUPPORTED
 
 
 def test_other_entry_points_reject_null_handles():
@@ -60,6 +63,9 @@ def test_other_entry_points_reject_null_handles():
     assert _lib.tiledqr_lstsq(None, None, 1, None, 1, 1, None, 1, None, None, None) == tqr.TQR_EINVAL
     assert _lib.tiledqr_get_r(None, None, 1, None) == tqr.TQR_EINVAL
     assert _lib.tiledqr_destroy(None) == tqr.TQR_OK
+    n = ctypes.c_int64()
+    assert _lib.tiledqr_exec_plan(None, None, ctypes.byref(n), None, ctypes.byref(n)) == tqr.TQR_EINVAL
+    assert _lib.tiledqr_solve_r(None, b"N", None, 1, 1, None) == tqr.TQR_EINVAL
 
 
 def test_batch_create_rejects_bad_options_before_allocating():

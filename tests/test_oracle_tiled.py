@@ -107,3 +107,72 @@ def test_refinement_reports_stagnation():
     F = tiled.tiled_qr(A + E, 8, trees.GREEDY)
     X, iters, ok, eta = tiled.refine(A, B, lambda rhs: tiled.lstsq(F, rhs), max_iter=30)
     assert not ok and iters < 30
+
+
+# ---- pins of the backward error -----------------------------------------
+# Square systems: eta(x) = ||b - A x|| / (||A||_F ||x|| + ||b||) is the
+# normwise backward error of Rigal and Gaches (Higham, Accuracy and Stability
+# of Numerical Algorithms, Thm. 7.1): the smallest eps with (A + dA) x = b +
+# db, ||dA||_F <= eps ||A||_F, ||db|| <= eps ||b||.  Tall systems: eta(x) =
+# ||A^T r|| / (||A||_F ||r||), zero exactly at the least-squares solution.
+
+def test_backward_error_square_hand_values():
+    # A = diag(3, 4): ||A||_F = 5 while ||A||_2 = 4, so a 2-norm in place of
+    # the Frobenius norm, or a dropped ||b|| term, changes the value.
+    A = np.diag([3.0, 4.0])
+    b = np.array([[3.0], [4.0]])
+    x = np.array([[1.0], [0.0]])       # r = (0, 4)
+    assert tiled.backward_error(A, x, b)[0] == pytest.approx(4.0 / (5.0 * 1.0 + 5.0), rel=1e-15)
+    x = np.array([[1.0], [1.0]])       # exact solution
+    assert tiled.backward_error(A, x, b)[0] == 0.0
+    x = np.zeros((2, 1))               # r = b: eta = ||b|| / ||b|| = 1
+    assert tiled.backward_error(A, x, b)[0] == pytest.approx(1.0, rel=1e-15)
+
+
+def test_backward_error_square_is_attained():
+    """The perturbations dA = a r x^T / ||x||^2 and db = -c r with
+    relative sizes exactly eta (a ||r|| / ||x|| = eta ||A||_F, c ||r|| = eta
+    ||b||) make x exact: (A + dA) x = b + db holds iff a + c = 1, i.e. iff
+    eta is the value of the theorem."""
+    rng = np.random.default_rng(71)
+    for n in (1, 5, 17):
+        A = rng.standard_normal((n, n))
+        b = rng.standard_normal((n, 1))
+        x = np.linalg.solve(A, b) + 1e-3 * rng.standard_normal((n, 1))
+        eta = tiled.backward_error(A, x, b)[0]
+        r = b - A @ x
+        nr, nx = np.linalg.norm(r), np.linalg.norm(x)
+        a = eta * np.linalg.norm(A, "fro") * nx / nr
+        c = eta * np.linalg.norm(b) / nr
+        dA = a * (r @ x.T) / nx ** 2
+        db = -c * r
+        assert np.linalg.norm(dA, "fro") == pytest.approx(eta * np.linalg.norm(A, "fro"), rel=1e-12)
+        assert np.allclose((A + dA) @ x, b + db, rtol=0, atol=1e-12 * np.linalg.norm(b))
+
+
+def test_backward_error_tall_hand_values():
+    A = np.array([[3.0, 0.0], [0.0, 4.0], [0.0, 0.0]])   # ||A||_F = 5, ||A||_2 = 4
+    b = np.array([[1.0], [1.0], [1.0]])
+    x = np.zeros((2, 1))   # r = b, A^T r = (3, 4): eta = 5 / (5 sqrt 3)
+    assert tiled.backward_error(A, x, b)[0] == pytest.approx(1.0 / np.sqrt(3.0), rel=1e-15)
+    x = np.array([[1.0 / 3.0], [0.25]])  # least-squares solution: A^T r = 0
+    assert tiled.backward_error(A, x, b)[0] == pytest.approx(0.0, abs=1e-16)
+    # b orthogonal to range(A) and x = 0: r = b != 0 and A^T r = 0
+    b = np.array([[0.0], [0.0], [2.0]])
+    assert tiled.backward_error(A, np.zeros((2, 1)), b)[0] == 0.0
+    # consistent system solved exactly: r = 0
+    b = A @ np.array([[1.0], [-2.0]])
+    assert tiled.backward_error(A, np.array([[1.0], [-2.0]]), b)[0] == 0.0
+
+
+def test_backward_error_scale_invariant_and_per_column():
+    rng = np.random.default_rng(72)
+    for (m, n) in ((9, 9), (12, 5)):
+        A = rng.standard_normal((m, n))
+        X = rng.standard_normal((n, 3))
+        B = rng.standard_normal((m, 3))
+        e = tiled.backward_error(A, X, B)
+        assert e.shape == (3,)
+        assert np.allclose(tiled.backward_error(1e5 * A, X, 1e5 * B), e, rtol=1e-12)
+        for c in range(3):
+            assert tiled.backward_error(A, X[:, c:c + 1], B[:, c:c + 1])[0] == pytest.approx(e[c], rel=1e-15)
