@@ -325,6 +325,25 @@ int tiledqr_mlp_loss_grad(const float* params, const float* X, const float* t, i
 int tiledqr_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t nparam,
                      float lr, float beta1, float beta2, float eps, int32_t step, void* stream);
 
+/* tiledqr_mlp_loss_grad without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight training
+ * loops, harnesses that forbid hipMalloc).  Same arguments, kernels and
+ * results as tiledqr_mlp_loss_grad (bit-identical), but the per-chunk partial
+ * gradients live in a fixed array of the library's device memory instead of
+ * a stream-ordered workspace: one array per GPU (5.2 MB, held until the
+ * process ends), located on the first call on each device (make that first
+ * call before any graph capture).  n is limited to
+ * tiledqr_mlp_noalloc_max_samples() = 16384 samples.  Every call on one GPU
+ * uses that GPU's single array, so calls that overlap on one GPU (on
+ * different streams or threads without ordering) race and give wrong
+ * gradients; calls ordered on one stream are safe.  No part of the array
+ * needs clearing: each call writes every entry it reads.
+ * Errors: TQR_EINVAL (as tiledqr_mlp_loss_grad, and n above the limit),
+ * TQR_EHIP. */
+int tiledqr_mlp_loss_grad_noalloc(const float* params, const float* X, const float* t, int64_t n,
+                                  float* grad, float* loss, void* stream);
+int tiledqr_mlp_noalloc_max_samples(void);
+
 /* ---- host-only planning (no GPU needed) -------------------------------- */
 
 /* Elimination list of a tree (Sec. 3): triples (i, piv, k), 1-based, in the

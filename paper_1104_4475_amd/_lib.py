@@ -85,6 +85,8 @@ _sigs = {
     "tiledqr_mlp_nparam": (ctypes.c_int, []),
     "tiledqr_mlp_forward": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp]),
     "tiledqr_mlp_loss_grad": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "tiledqr_mlp_loss_grad_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _vp, _vp]),
+    "tiledqr_mlp_noalloc_max_samples": (ctypes.c_int, []),
     "tiledqr_mlp_adam": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                         ctypes.c_float, _i32, _vp]),
     "tiledqr_elim_list": (ctypes.c_int, [_i32, _i32, _i32, _i32, _P(_i32), _P(_i64)]),

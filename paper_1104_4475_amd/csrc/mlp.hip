@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
 #include "tiledqr.h"
 
@@ -175,7 +176,33 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float* __restrict__ P, co
   P[e] -= lr * mh / (sqrtf(vh) + eps);
 }
 
+// Partial gradients of tiledqr_mlp_loss_grad_noalloc: a fixed array in the
+// library's device memory (one copy per GPU, held until the process ends),
+// NOALLOC_MAX_CHUNKS chunks of MLP_CHUNK samples, 5.2 MB.
+constexpr int NOALLOC_MAX_CHUNKS = 256;
+__device__ __align__(256) float scratch[NOALLOC_MAX_CHUNKS * (NPARAM + 1)];
+
 }  // namespace
+
+// Device address of scratch on the current device, looked up once per device
+// (host code must not pass the array's name to a kernel: on the host it is a
+// stand-in, not a device address).  Null if the lookup failed.
+float* noalloc_scratch() {
+  constexpr int MAXDEV = 64;
+  static std::mutex mu;
+  static float* ptr[MAXDEV] = {};
+  static bool done[MAXDEV] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAXDEV) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!done[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    ptr[dev] = static_cast<float*>(p);
+    done[dev] = true;
+  }
+  return ptr[dev];
+}
 
 }  // namespace tqr
 
@@ -210,6 +237,24 @@ int tiledqr_mlp_loss_grad(const float* params, const float* X, const float* t, i
   (void)hipFreeAsync(part, s);
   return e == hipSuccess ? TQR_OK : TQR_EHIP;
 }
+
+int tiledqr_mlp_loss_grad_noalloc(const float* params, const float* X, const float* t, int64_t n, float* grad,
+                                  float* loss, void* stream) {
+  if (!params || !X || !t || !grad || n < 1 || n > tiledqr_mlp_noalloc_max_samples()) return TQR_EINVAL;
+  float* part = tqr::noalloc_scratch();
+  if (!part) return TQR_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t nchunk = (n + tqr::MLP_CHUNK - 1) / tqr::MLP_CHUNK;
+  // Every chunk's kernel writes all NPARAM + 1 entries of its part, so the
+  // array needs no clearing between calls.
+  hipLaunchKernelGGL(tqr::mlp_grad_kernel, dim3(static_cast<unsigned>(nchunk)), dim3(64 * tqr::MLP_WAVES), 0, s,
+                     params, X, t, n, part);
+  hipLaunchKernelGGL(tqr::mlp_sum_kernel, dim3((tqr::NPARAM + 1 + 255) / 256), dim3(256), 0, s, part,
+                     static_cast<int>(nchunk), grad, loss);
+  return hipGetLastError() == hipSuccess ? TQR_OK : TQR_EHIP;
+}
+
+int tiledqr_mlp_noalloc_max_samples(void) { return tqr::NOALLOC_MAX_CHUNKS * tqr::MLP_CHUNK; }
 
 int tiledqr_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t nparam, float lr, float beta1,
                      float beta2, float eps, int32_t step, void* stream) {
