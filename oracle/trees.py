@@ -12,6 +12,8 @@ Trees (Sec. 3.1 and Sec. 3.2):
   Greedy                   Algorithm 4 (rounds of nT/nZ counters).
   PlasmaTree(BS)           flat trees inside domains of BS rows anchored at
                            row k, then a binary merge of the domain heads.
+  ASAP, GRASAP(k)          run-time pairings of the tiled model
+                           (oracle/dynamic.py).
 
 Readings where the text leaves room (each pinned by Table 3 of the paper):
   * BinaryTree is re-rooted at row k in every column (offsets from k).
@@ -26,9 +28,10 @@ tests/golden/), by the list identities PT(1) == BinaryTree, PT(p) == FlatTree,
 and by the validity conditions of Sec. 2.2 and Lemma 1.
 """
 
-FLAT, SAMEH_KUCK, BINARY, FIBONACCI, GREEDY, PLASMA = 0, 1, 2, 3, 4, 5
+FLAT, SAMEH_KUCK, BINARY, FIBONACCI, GREEDY, PLASMA, ASAP, GRASAP = 0, 1, 2, 3, 4, 5, 6, 7
 TREE_NAMES = {FLAT: "FlatTree", SAMEH_KUCK: "Sameh-Kuck", BINARY: "BinaryTree",
-              FIBONACCI: "Fibonacci", GREEDY: "Greedy", PLASMA: "PlasmaTree"}
+              FIBONACCI: "Fibonacci", GREEDY: "Greedy", PLASMA: "PlasmaTree",
+              ASAP: "ASAP", GRASAP: "GRASAP"}
 
 
 def _check(p, q):
@@ -185,6 +188,9 @@ def elim_list(p, q, tree, bs=1):
         return greedy_tree(p, q)
     if tree == PLASMA:
         return plasma_tree(p, q, bs)
+    if tree in (ASAP, GRASAP):
+        from . import dynamic  # the run-time pairings (their own module)
+        return dynamic.asap(p, q) if tree == ASAP else dynamic.grasap(p, q, bs)
     raise ValueError("unknown tree %r" % (tree,))
 
 
