@@ -43,14 +43,23 @@ typedef enum {
 
 /* Reduction trees (Sec. 3.1 and Sec. 3.2).  FLAT and SAMEH_KUCK produce the
  * same elimination list (the tiled Sameh-Kuck algorithm is PLASMA's
- * FlatTree); they differ only in their default kernel family. */
+ * FlatTree); they differ only in their default kernel family.  ASAP and
+ * GRASAP choose their pairs as a unit-weight execution with TT kernels and
+ * the Table 1 weights runs: whenever r >= 2 rows of a column are
+ * triangularized and not in a running TTQRT, the bottom r / 2 of them are
+ * killed by the r / 2 rows right above them.  The pairs are computed on the
+ * host before the factorization and form an ordinary elimination list, so
+ * the GPU runs them like any other tree. */
 typedef enum {
   TQR_TREE_FLAT = 0,
   TQR_TREE_SAMEH_KUCK = 1,
   TQR_TREE_BINARY = 2,
   TQR_TREE_FIBONACCI = 3,
   TQR_TREE_GREEDY = 4,
-  TQR_TREE_PLASMA = 5      /* needs bs in [1, p] (domain size)             */
+  TQR_TREE_PLASMA = 5,     /* needs bs in [1, p] (domain size)             */
+  TQR_TREE_ASAP = 6,       /* run-time pairing of the tiled model (Sec. 3.2) */
+  TQR_TREE_GRASAP = 7      /* Greedy for the first q - bs columns, ASAP for
+                              the last bs (bs in [0, q]; Sec. 3.2)         */
 } tqr_tree;
 
 /* Kernel family (Sec. 2.1): TT = triangle on top of triangle (Algorithm 3),
@@ -73,7 +82,8 @@ typedef struct {
   int32_t nb;       /* tile size: 32, 64, 128 or 256 (512: TQR_EUNSUPPORTED) */
   int32_t ib;       /* inner block size: 0 = default (32); must be 32      */
   int32_t tree;     /* tqr_tree                                            */
-  int32_t bs;       /* PlasmaTree domain size, ignored for other trees     */
+  int32_t bs;       /* PlasmaTree domain size; GRASAP: ASAP columns k;
+                       ignored for other trees                             */
   int32_t kernels;  /* tqr_kernels                                         */
   int32_t upd;      /* tqr_update_prec                                     */
 } tqr_opts;

@@ -1,7 +1,8 @@
 // Host planner (see plan.hpp).
 //
 // Elimination lists follow Sec. 3.1 / Sec. 3.2 of the paper (FlatTree ==
-// Sameh-Kuck, BinaryTree, Fibonacci, PlasmaTree) and Algorithm 4 (Greedy).
+// Sameh-Kuck, BinaryTree, Fibonacci, PlasmaTree, and the run-time pairings
+// ASAP and GRASAP(k) of the tiled model) and Algorithm 4 (Greedy).
 // The expansion into kernels follows Algorithms 2 (TS) and 3 (TT), skipping
 // GEQRT on tiles that are already triangles (Sec. 2.1).  The schedule is the
 // unbounded-processor as-soon-as-possible execution of Sec. 2.3 with the
@@ -12,14 +13,17 @@
 #include <cmath>
 #include <map>
 #include <numeric>
+#include <queue>
+#include <set>
 #include <tuple>
 
 namespace tqr {
 
 bool valid_shape(int p, int q, int tree, int bs) {
   if (q < 1 || p < q) return false;
-  if (tree < T_FLAT || tree > T_PLASMA) return false;
+  if (tree < T_FLAT || tree > T_GRASAP) return false;
   if (tree == T_PLASMA && (bs < 1 || bs > p)) return false;
+  if (tree == T_GRASAP && (bs < 0 || bs > q)) return false;
   return true;
 }
 
@@ -115,6 +119,108 @@ void plasma(int p, int q, int bs, std::vector<Elim>& out) {
   }
 }
 
+// ASAP and GRASAP(kdyn), Sec. 3.2 (Table 4): the pairs of the last kdyn
+// columns (all of them for ASAP) are chosen while a unit-weight execution
+// with TT kernels and the Table 1 weights runs; the columns before them take
+// the Greedy pairs in Greedy's order.  A row is ready in column k once
+// GEQRT(i, k) has finished (after every update of tile (i, k) from column
+// k - 1) and idle when no TTQRT that uses it is running.  At each time at
+// which a row of a run-time column becomes ready or idle, the r ready idle
+// rows of that column (top to bottom) are paired: the bottom s = r / 2 are
+// killed by the s rows right above them.  Every other task starts when its
+// inputs are ready (Algorithm 3's data flow: GEQRT and UNMQR after the last
+// update of their tiles, TTMQR after its TTQRT and both tiles' last
+// updates; a TTQRT needs only the two triangles).  The list is the static
+// part in order, then the run-time eliminations by start time, column and
+// killed row, so the ordinary task expansion schedules it as it ran.
+void dynamic_pairs(int p, int q, int kdyn, std::vector<Elim>& out) {
+  const int kmax = std::min(p, q);
+  const int cut = (kdyn <= 0) ? kmax + 1 : std::max(1, kmax - kdyn + 1);  // first run-time column
+  const int64_t WG = kWeight[K_GEQRT], WU = kWeight[K_UNMQR], WQ = kWeight[K_TTQRT], WM = kWeight[K_TTMQR];
+  std::vector<int64_t> avail(static_cast<size_t>(p + 1) * (q + 1), 0);  // last update of tile (r, j)
+  std::vector<int64_t> ready(static_cast<size_t>(p + 1) * (kmax + 2), -1);  // GEQRT(r, k) finish
+  std::vector<int64_t> busy(p + 1, 0);                                       // running TTQRT finish
+  auto A = [&](int r, int j) -> int64_t& { return avail[static_cast<size_t>(r) * (q + 1) + j]; };
+  auto R = [&](int r, int k) -> int64_t& { return ready[static_cast<size_t>(r) * (kmax + 2) + k]; };
+  auto enter = [&](int r, int k) {
+    const int64_t f = A(r, k) + WG;
+    R(r, k) = f;
+    A(r, k) = f;
+    for (int j = k + 1; j <= q; ++j) A(r, j) = std::max(f, A(r, j)) + WU;
+    return f;
+  };
+  // TTQRT(i, piv, k) at t with its updates; returns row i's GEQRT finish in
+  // column k + 1, or -1.
+  auto eliminate = [&](int i, int piv, int k, int64_t t) -> int64_t {
+    const int64_t f = t + WQ;
+    busy[i] = busy[piv] = f;
+    for (int j = k + 1; j <= q; ++j) {
+      const int64_t u = std::max(f, std::max(A(piv, j), A(i, j))) + WM;
+      A(piv, j) = A(i, j) = u;
+    }
+    return (k + 1 <= kmax) ? enter(i, k + 1) : -1;
+  };
+  for (int r = 1; r <= p; ++r) enter(r, 1);
+  if (cut > 1) {
+    std::vector<Elim> g;
+    greedy(p, q, g);
+    std::vector<int64_t> tri(static_cast<size_t>(p + 1) * (kmax + 2), 0);  // triangle free
+    auto T = [&](int r, int k) -> int64_t& { return tri[static_cast<size_t>(r) * (kmax + 2) + k]; };
+    for (int r = 1; r <= p; ++r) T(r, 1) = R(r, 1);
+    for (const Elim& e : g) {
+      if (e.k >= cut) continue;
+      const int64_t t = std::max(T(e.piv, e.k), T(e.i, e.k));
+      const int64_t f = eliminate(e.i, e.piv, e.k, t);
+      T(e.piv, e.k) = t + WQ;
+      if (f >= 0) T(e.i, e.k + 1) = f;
+      out.push_back(e);
+    }
+  }
+  // Run-time columns, event by event (time, column).
+  std::vector<std::set<int>> alive(kmax + 2);
+  std::priority_queue<std::pair<int64_t, int>, std::vector<std::pair<int64_t, int>>, std::greater<>> ev;
+  for (int k = cut; k <= kmax; ++k)
+    for (int r = k; r <= p; ++r)
+      if (R(r, k) >= 0) {
+        alive[k].insert(r);
+        ev.push({R(r, k), k});
+      }
+  struct Dyn { int64_t t; int k, i, piv; };
+  std::vector<Dyn> dyn;
+  std::vector<int> rows;
+  while (!ev.empty()) {
+    const int64_t t = ev.top().first;
+    std::set<int> cols;
+    while (!ev.empty() && ev.top().first == t) {
+      cols.insert(ev.top().second);
+      ev.pop();
+    }
+    for (int k : cols) {
+      rows.clear();
+      for (int r : alive[k])
+        if (R(r, k) <= t && busy[r] <= t) rows.push_back(r);
+      const int s = static_cast<int>(rows.size()) / 2;
+      if (s == 0) continue;
+      const int n = static_cast<int>(rows.size());
+      for (int a = 0; a < s; ++a) {
+        const int piv = rows[n - 2 * s + a], i = rows[n - s + a];
+        const int64_t f = eliminate(i, piv, k, t);
+        alive[k].erase(i);
+        dyn.push_back({t, k, i, piv});
+        if (f >= 0) {
+          alive[k + 1].insert(i);
+          ev.push({f, k + 1});
+        }
+      }
+      ev.push({t + WQ, k});
+    }
+  }
+  std::sort(dyn.begin(), dyn.end(), [](const Dyn& a, const Dyn& b) {
+    return std::tie(a.t, a.k, a.i, a.piv) < std::tie(b.t, b.k, b.i, b.piv);
+  });
+  for (const Dyn& d : dyn) out.push_back({d.i, d.piv, d.k});
+}
+
 }  // namespace
 
 bool make_elims(int p, int q, int tree, int bs, std::vector<Elim>& out) {
@@ -127,6 +233,8 @@ bool make_elims(int p, int q, int tree, int bs, std::vector<Elim>& out) {
     case T_FIBONACCI: fibonacci(p, q, out); break;
     case T_GREEDY: greedy(p, q, out); break;
     case T_PLASMA: plasma(p, q, bs, out); break;
+    case T_ASAP: dynamic_pairs(p, q, std::min(p, q), out); break;
+    case T_GRASAP: dynamic_pairs(p, q, bs, out); break;
     default: return false;
   }
   return true;

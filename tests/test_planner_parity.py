@@ -8,7 +8,7 @@ import pytest
 
 import paper_1104_4475_amd as tqr
 from conftest import load_rows
-from oracle import dag, trees
+from oracle import dag, dynamic, trees
 
 TREES = [trees.FLAT, trees.SAMEH_KUCK, trees.BINARY, trees.FIBONACCI, trees.GREEDY]
 
@@ -79,3 +79,25 @@ def test_invalid_arguments_rejected():
                  (5, 2, tqr.TREE_PLASMA, 6)):
         with pytest.raises(tqr.TiledQRError):
             tqr.elim_list(*args)
+
+
+@pytest.mark.parametrize("p,q", [(1, 1), (2, 2), (8, 4), (15, 3), (15, 6), (16, 16), (23, 7), (40, 8), (64, 8)])
+def test_asap_grasap_lists_identical(p, q):
+    assert [tuple(r) for r in tqr.elim_list(p, q, tqr.TREE_ASAP).tolist()] == dynamic.asap(p, q)
+    for k in sorted({0, 1, 2, q // 2, q}):
+        if k <= q:
+            got = [tuple(r) for r in tqr.elim_list(p, q, tqr.TREE_GRASAP, k).tolist()]
+            assert got == dynamic.grasap(p, q, k), k
+
+
+def test_table4b_asap_through_planner():
+    # 128 x 64: the reading of the pairing rule gives 1734 (Table 4(b): 1748).
+    for p, q, _greedy, asap in load_rows("table4b_greedy_asap.txt"):
+        cp = tqr.schedule(p, q, tqr.TREE_ASAP, 1, tqr.KERN_TT)[1]
+        assert cp == {(128, 64): 1734}.get((p, q), asap), (p, q)
+
+
+def test_grasap_k_out_of_range_rejected():
+    for k in (-1, 4):
+        with pytest.raises(tqr.TiledQRError):
+            tqr.elim_list(8, 3, tqr.TREE_GRASAP, k)
