@@ -166,6 +166,8 @@ struct tqr_factors {
   double* tiles = nullptr;
   double* Tg = nullptr;
   double* Tp = nullptr;
+  unsigned char* imgg = nullptr;  // low-precision reflector images (nb >= 128, upd != FP64)
+  unsigned char* imgp = nullptr;
   int32_t* ctl = nullptr;  // [0] ticket, [1] executor err, [2] solve err, [3..3+4q) solve flags
   ExecPlan exec_host;      // host copy of the factorization plan (joint plans are built from it)
   DevPlan fused;           // factorization + Q^T B (16 columns) in one executor plan
@@ -200,6 +202,8 @@ struct tqr_factors {
     if (tiles) (void)hipFree(tiles);
     if (Tg) (void)hipFree(Tg);
     if (Tp) (void)hipFree(Tp);
+    if (imgg) (void)hipFree(imgg);
+    if (imgp) (void)hipFree(imgp);
     if (ctl) (void)hipFree(ctl);
   }
 };
@@ -251,6 +255,8 @@ ExecArgs base_args(const tqr_factors* F, const DevPlan& d) {
   a.tiles = F->tiles;
   a.Tg = F->Tg;
   a.Tp = F->Tp;
+  a.imgg = F->imgg;
+  a.imgp = F->imgp;
   a.B = nullptr;
   a.sub = d.sub;
   a.deps = d.deps;
@@ -406,7 +412,7 @@ int create(const tqr_opts* o, tqr_factors** out, ExecPlan* keep = nullptr) {
   double w[6];
   exec_weights(o->nb, o->upd, w);
   ExecPlan ex;
-  const int nslab = std::max(1, F->nb / tqr::SLAB);
+  const int nslab = std::max(1, F->nb / tqr::update_slab(F->nb, o->upd));
   // Panel tasks as one subtask per inner block (nb >= 128; TQR_PANEL_SPLIT=0
   // keeps whole panel tasks).
   const char* ps = std::getenv("TQR_PANEL_SPLIT");
@@ -425,6 +431,10 @@ int create(const tqr_opts* o, tqr_factors** out, ExecPlan* keep = nullptr) {
     return TQR_ENOMEM;
   HIP_TRY(hipMemset(F->Tg, 0, ntile * tqr::IB * nbb * sizeof(double)));
   HIP_TRY(hipMemset(F->Tp, 0, ntile * tqr::IB * nbb * sizeof(double)));
+  if (tqr::update_slab(F->nb, o->upd) == tqr::WIDE_SLAB) {
+    const size_t ib = ntile * static_cast<size_t>(F->nb / tqr::IB) * tqr::image_bytes(F->nb, o->upd);
+    if (!hip_ok(hipMalloc(&F->imgg, ib)) || !hip_ok(hipMalloc(&F->imgp, ib))) return TQR_ENOMEM;
+  }
   HIP_TRY(hipMemset(F->ctl, 0, (3 + 4 * F->q) * sizeof(int32_t)));
   F->grid = device_cus() * tqr::persistent_occupancy(F->nb, F->o.upd);
   *out = F.release();
@@ -841,7 +851,7 @@ int tiledqr_refactor_qtb(tqr_factors* F, const double* A, int64_t lda, double* B
   if (!F->fused.sub) {
     double w[6];
     exec_weights(F->nb, F->o.upd, w);
-    const int nslab = std::max(1, F->nb / tqr::SLAB);
+    const int nslab = std::max(1, F->nb / tqr::update_slab(F->nb, F->o.upd));
     ExecPlan ex;
     tqr::make_factor_apply_plan(F->plan, F->exec_host, nslab, w, 1, 0.1 * w[1], ex);
     const int st = upload(ex, F->fused);

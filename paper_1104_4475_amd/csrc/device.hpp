@@ -9,6 +9,17 @@ namespace tqr {
 constexpr int IB = 32;        // inner block size of every kernel (Sec. 4: ib = 32)
 constexpr int NTHREADS = 512; // 8 waves of 64 lanes (two per SIMD)
 constexpr int SLAB = 64;      // columns of C per update subtask (16 per wave)
+constexpr int WIDE_SLAB = 128; // columns of a low-precision update subtask at nb >= 128
+
+// Low-precision update subtasks at nb >= 128 read each block of reflectors
+// from an image written by the panel subtask that computed it (FP32 or BF16
+// reflectors and an FP32 T block, laid out as its padded LDS copy): bytes
+// per ib-block for update precision upd (1 FP32, 2 BF16).
+constexpr int image_bytes(int nb, int upd) {
+  return upd == 1 ? IB * (nb + 4) * 4 + IB * 36 * 4 : IB * (nb + 8) * 2 + nb * 40 * 2 + IB * 36 * 4;
+}
+// Column slab of update subtasks for a tile size and update precision.
+constexpr int update_slab(int nb, int upd) { return (upd != 0 && nb >= 128) ? WIDE_SLAB : SLAB; }
 
 // Executor task kinds: the six tile kernels (Table 1) and the application of
 // a panel task's reflectors to right-hand-side row tiles (apply_q).
@@ -43,6 +54,8 @@ struct ExecArgs {
   int64_t* trace;       // optional: per subtask (ticket, ready, end, workgroup)
   int32_t debug;        // diagnostics: bit 0 = clear the workgroup's LDS before each task
   int32_t fused;        // B set and the plan mixes factorization and Q^T B subtasks
+  unsigned char* imgg;  // low-precision images of the GEQRT sets (nb >= 128, upd != FP64), nb/ib per tile
+  unsigned char* imgp;  // the same for the TS/TT sets, indexed by the zeroed tile
 };
 
 // One problem of a batched launch: its tile storage and shape.

@@ -128,6 +128,16 @@ __device__ __forceinline__ double* tg_ptr(const ExecArgs& a, int r, int c) {
 __device__ __forceinline__ double* tp_ptr(const ExecArgs& a, int r, int c) {
   return a.Tp + (static_cast<size_t>(c) * a.p + r) * static_cast<size_t>(IB) * a.nb;
 }
+// Image of block 0 of the GEQRT set of tile (r, c), or of the TS/TT set that
+// zeroed it (blocks follow one another).
+template <int NB, int P>
+__device__ __forceinline__ unsigned char* imgg_ptr(const ExecArgs& a, int r, int c) {
+  return a.imgg + (static_cast<size_t>(c) * a.p + r) * (NB / IB) * static_cast<size_t>(image_bytes(NB, P));
+}
+template <int NB, int P>
+__device__ __forceinline__ unsigned char* imgp_ptr(const ExecArgs& a, int r, int c) {
+  return a.imgp + (static_cast<size_t>(c) * a.p + r) * (NB / IB) * static_cast<size_t>(image_bytes(NB, P));
+}
 
 // LDS of one workgroup, in doubles.
 // Precision of the update kernels' two large contractions (the panel
@@ -686,6 +696,332 @@ __device__ __forceinline__ void apply_block_lp(const unsigned char* vl, const do
 }
 
 // ---------------------------------------------------------------------------
+// Wide low-precision update subtasks (nb >= 128, FP32 or BF16 updates).
+//
+// The panel subtask that computes an ib-block of reflectors rounds it once
+// into an image in device memory; every update subtask that applies the
+// block copies the image to LDS as it is (no conversion, and half the bytes
+// of the FP64 reflectors).  An update subtask covers a slab of WSLAB = 128
+// columns: wave w owns columns 16 w .. 16 w + 15 of the slab over all nb
+// rows, so it forms W = V^T C for its columns alone (no exchange between
+// waves), and a single barrier per block hands over the three LDS slots
+// that hold consecutive images.
+//
+// Image of one block.  Rows and reflectors are kept in lp_row order within
+// each 16 (position x of a group holds natural row, or reflector,
+// lp_row(x)); V rows are the tile rows 0..nb-1, zero outside the block's
+// support.  The image is laid out exactly as its LDS copy, padding
+// included, so the copy is a plain transfer; the padded strides put the 64
+// lanes of every operand read below on distinct banks.
+//   FP32: cm[m'][k'] = V[k][m] as float, rows of LCM = nb + 4 floats;
+//   BF16: cm as bf16, rows of LCM = nb + 8; then from RM, rm[k'][m'] =
+//         V[k][m] as bf16, rows of SRM = 40;
+//   both: from TO, Tq[kk'][aa'] = T[kk][aa] as float, rows of TLD = 36.
+// BYTES is a whole number of KB (37 KB FP32, 41 KB BF16 at nb = 256).
+constexpr int WSLAB = 128;
+
+__device__ __forceinline__ int nat16(int x) { return (x & ~15) | lp_row(x & 15); }
+
+template <int NB, int P>
+struct Img {
+  static constexpr int ESZ = (P == P_F32) ? 4 : 2;
+  static constexpr int LCM = (P == P_F32) ? NB + 4 : NB + 8;
+  static constexpr int RM = IB * LCM * ESZ;
+  static constexpr int SRM = 40;
+  static constexpr int TO = RM + ((P == P_F32) ? 0 : NB * SRM * 2);
+  static constexpr int TLD = 36;
+  static constexpr int BYTES = TO + IB * TLD * 4;
+  static constexpr int NKB = BYTES / 1024;
+};
+static_assert(Img<256, P_F32>::BYTES == image_bytes(256, P_F32) && Img<128, P_F32>::BYTES == image_bytes(128, P_F32) &&
+                  Img<256, P_BF16>::BYTES == image_bytes(256, P_BF16) &&
+                  Img<128, P_BF16>::BYTES == image_bytes(128, P_BF16),
+              "image size");
+static_assert(Img<256, P_F32>::BYTES % 1024 == 0 && Img<128, P_F32>::BYTES % 1024 == 0 &&
+                  Img<256, P_BF16>::BYTES % 1024 == 0 && Img<128, P_BF16>::BYTES % 1024 == 0,
+              "image in whole KB");
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_b(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, bytes, 0x00020000);
+}
+
+// Image of the block whose explicit reflectors are in the FP64 LDS panel Ps
+// (ld ldp, K rows, Ps row 0 = tile row vrow0) and whose T factor is in Ts
+// (natural order, column-major), written with device-coherent stores (one
+// thread per 16-byte piece; padding written as zeros).  Only reads LDS.
+template <int NB, int P>
+__device__ __forceinline__ void write_image(unsigned char* img, const double* Ps, int ldp, int vrow0, int K,
+                                            const double* Ts) {
+  using I = Img<NB, P>;
+  const auto r = rsrc_b(img, I::BYTES);
+  auto V = [&](int k, int m) -> double {
+    const int kk = k - vrow0;
+    return (kk >= 0 && kk < K) ? Ps[kk + m * ldp] : 0.0;
+  };
+  for (int c = threadIdx.x; c < I::BYTES / 16; c += NTHREADS) {
+    const int o = 16 * c;
+    u4 out = {0u, 0u, 0u, 0u};
+    if (o < I::RM) {
+      const int mp = o / (I::LCM * I::ESZ), kp = (o % (I::LCM * I::ESZ)) / I::ESZ;
+      const int m = nat16(mp);
+      if constexpr (P == P_F32) {
+        if (kp < NB) {
+          f4 f;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) f[e] = static_cast<float>(V(nat16(kp + e), m));
+          out = __builtin_bit_cast(u4, f);
+        }
+      } else {
+        if (kp < NB) {
+          bf8 h;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) h[e] = to_lp<P_BF16>(V(nat16(kp + e), m));
+          out = __builtin_bit_cast(u4, h);
+        }
+      }
+    } else if (o < I::TO) {  // BF16 rm
+      const int kp = (o - I::RM) / (I::SRM * 2), mp = ((o - I::RM) % (I::SRM * 2)) / 2;
+      if (mp < IB) {
+        const int k = nat16(kp);
+        bf8 h;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) h[e] = to_lp<P_BF16>(V(k, nat16(mp + e)));
+        out = __builtin_bit_cast(u4, h);
+      }
+    } else {
+      const int t = (o - I::TO) / 4, kp = t / I::TLD, ap = t % I::TLD;
+      if (ap < IB) {
+        const int kk = nat16(kp);
+        f4 f;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) f[e] = static_cast<float>(Ts[kk + nat16(ap + e) * IB]);
+        out = __builtin_bit_cast(u4, f);
+      }
+    }
+    __builtin_amdgcn_raw_buffer_store_b128(out, r, o, 0, CPOL_SC1);
+  }
+}
+
+// Copy of one image into an LDS slot by direct loads into LDS (device-
+// coherent): each wave instruction moves 1 KB (lane l: bytes 16 l ..
+// 16 l + 15 of it); wave w moves KB w, w + 8, ...  The data is in LDS once
+// the wave's vector memory counter has drained.
+// One direct load of 16 bytes per lane into LDS (lane l to lds + 16 l).  The
+// builtin exists for the device target only; the host pass of this file
+// needs no body.
+__device__ __forceinline__ void lds_load16(__amdgpu_buffer_rsrc_t r, unsigned char* lds, int voff) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (__attribute__((address_space(3))) void*)lds, 16, voff, 0, 0, CPOL_SC1);
+#endif
+}
+
+template <int NB, int P>
+__device__ __forceinline__ void img_dma(const unsigned char* img, unsigned char* slot) {
+  using I = Img<NB, P>;
+  const auto r = rsrc_b(img, I::BYTES);
+  const int lane = lane_id(), w = wave_id();
+#pragma unroll
+  for (int j0 = 0; j0 < I::NKB; j0 += NWAVES) {
+    const int j = j0 + w;
+    if (j < I::NKB) lds_load16(r, slot + 1024 * j, 1024 * j + 16 * lane);
+  }
+}
+
+// Rows 16 rb + lp_row(4 g + r) of the lane's column (first column Cg of the
+// wave's 16, lane (g, n) -> column n), all nb rows.
+template <int NB>
+__device__ __forceinline__ void load_strip_lp(d4 (&acc)[NB / 16], const double* Cg) {
+  const int lane = lane_id(), g = lane >> 4, n = lane & 15;
+  const auto r = rsrc(Cg, 16 * NB * 8);
+#pragma unroll
+  for (int rb = 0; rb < NB / 16; ++rb) {
+    const int off = (n * NB + rb * 16 + 2 * g) * 8;
+    const d2 a = gld2(r, off), b = gld2(r, off + 64);
+    acc[rb] = d4{a[0], a[1], b[0], b[1]};
+  }
+}
+template <int NB>
+__device__ __forceinline__ void store_strip_lp(const d4 (&acc)[NB / 16], double* Cg) {
+  const int lane = lane_id(), g = lane >> 4, n = lane & 15;
+  const auto r = rsrc(Cg, 16 * NB * 8);
+#pragma unroll
+  for (int rb = 0; rb < NB / 16; ++rb) {
+    const int off = (n * NB + rb * 16 + 2 * g) * 8;
+    gst2(r, off, d2{acc[rb][0], acc[rb][1]});
+    gst2(r, off + 64, d2{acc[rb][2], acc[rb][3]});
+  }
+}
+
+// Update subtask on columns col0 .. col0 + 127 of the target tile(s):
+//   V_UNM  C2 <- Q^T C2 with the GEQRT set of a factored tile (C1 unused);
+//   V_TS / V_TT  [C1; C2] <- Q^T [C1; C2] with a TS / TT set.
+// img: image of block 0 of the set (blocks follow at Img<NB, P>::BYTES);
+// lds: three slots of that size.  Only Q^T (the factorization).
+template <int NB, int P, int VAR>
+__device__ __forceinline__ void wide_update_task(const unsigned char* img, double* C1, double* C2, int col0,
+                                                 unsigned char* lds) {
+  using I = Img<NB, P>;
+  using T = typename LpV<32, P>::T;
+  constexpr int NBLK = NB / IB, NJ = NB / 16, SLOT = I::BYTES;
+  constexpr bool PAIR = VAR != V_UNM;
+  const int lane = lane_id(), g = lane >> 4, n = lane & 15;
+  const size_t colo = static_cast<size_t>(col0 + 16 * wave_id()) * NB;
+  double* C2g = C2 + colo;
+  double* C1g = PAIR ? C1 + colo : nullptr;
+  // Three LDS slots: block b is read from slot b % 3 while the image of
+  // block b + 2 lands in slot (b + 2) % 3, which block b - 1 read before the
+  // barrier that ended it.
+  img_dma<NB, P>(img, lds);
+  if (NBLK > 1) img_dma<NB, P>(img + I::BYTES, lds + SLOT);
+  d4 acc[NJ];
+  load_strip_lp<NB>(acc, C2g);
+  d4 c1v[2] = {zero4(), zero4()};
+  if constexpr (PAIR) load_c1_lp<NB>(c1v, C1g, 0, true);
+  wait_vm();
+  __syncthreads();
+  int scur = 0;
+#pragma unroll 1
+  for (int b = 0; b < NBLK; ++b) {
+    const int c0 = b * IB;
+    const unsigned char* cur = lds + scur * SLOT;
+    if (b + 2 < NBLK) img_dma<NB, P>(img + static_cast<size_t>(b + 2) * I::BYTES, lds + ((scur == 0) ? 2 : scur - 1) * SLOT);
+    scur = (scur == 2) ? 0 : scur + 1;
+    const int rb_lo = (VAR == V_UNM) ? (c0 >> 4) : 0;
+    const int rb_hi = (VAR == V_TT) ? ((c0 + IB) >> 4) : NJ;
+    // W = V^T C2 (+ C1 rows c0 .. c0 + 31): w[mb] holds positions
+    // 16 mb + 4 g + r of W for column n.
+    f4 w[2] = {zero4f(), zero4f()};
+    if constexpr (P == P_F32) {
+      // Lane (g, n) supplies V at reflector position 16 mb + n and row
+      // positions 16 rb + 4 g + r (one 16-byte piece per mb).
+      const float* cm = reinterpret_cast<const float*>(cur);
+      f4 w1[2] = {zero4f(), zero4f()};
+#pragma unroll
+      for (int rb = 0; rb < NJ; ++rb) {
+        if (rb < rb_lo || rb >= rb_hi) continue;
+        const float* va = cm + n * I::LCM + rb * 16 + 4 * g;
+        const f4 a0 = *reinterpret_cast<const f4*>(va);
+        const f4 a1 = *reinterpret_cast<const f4*>(va + 16 * I::LCM);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float bb = static_cast<float>(acc[rb][r]);
+          if (r & 1) {
+            w1[0] = mfma32(a0[r], bb, w1[0]);
+            w1[1] = mfma32(a1[r], bb, w1[1]);
+          } else {
+            w[0] = mfma32(a0[r], bb, w[0]);
+            w[1] = mfma32(a1[r], bb, w[1]);
+          }
+        }
+      }
+      w[0] += w1[0];
+      w[1] += w1[1];
+    } else {
+      // k-slice of 32 rows: element e of lane (g, n) is row position
+      // 16 (rb + e / 4) + 4 g + e % 4.
+      const bf4 zb = {static_cast<__bf16>(0.0f), static_cast<__bf16>(0.0f), static_cast<__bf16>(0.0f),
+                      static_cast<__bf16>(0.0f)};
+#pragma unroll
+      for (int rb = 0; rb < NJ; rb += 2) {
+        const bool v0 = rb >= rb_lo && rb < rb_hi, v1 = rb + 1 >= rb_lo && rb + 1 < rb_hi;
+        if (!v0 && !v1) continue;
+        bf8 bb;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          bb[e] = v0 ? to_lp<P>(acc[rb][e]) : static_cast<__bf16>(0.0f);
+          bb[4 + e] = v1 ? to_lp<P>(acc[rb + 1][e]) : static_cast<__bf16>(0.0f);
+        }
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+          const T* col = reinterpret_cast<const T*>(cur) + (mb * 16 + n) * I::LCM + 4 * g;
+          const bf4 a0 = v0 ? *reinterpret_cast<const bf4*>(col + rb * 16) : zb;
+          const bf4 a1 = v1 ? *reinterpret_cast<const bf4*>(col + (rb + 1) * 16) : zb;
+          w[mb] = mfmabf(__builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7), bb, w[mb]);
+        }
+      }
+    }
+    if constexpr (PAIR) {
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w[mb][r] += static_cast<float>(c1v[mb][r]);
+    }
+    // W' = T^T W in FP32 (T upper triangular): lane (g, n) supplies
+    // T[kk][aa] for position 16 jb + 4 g + r of W and 16 ab + n of W'.
+    const float* Tq = reinterpret_cast<const float*>(cur + I::TO);
+    f4 wt[2] = {zero4f(), zero4f()};
+#pragma unroll
+    for (int ab = 0; ab < 2; ++ab)
+#pragma unroll
+      for (int jb = 0; jb <= ab; ++jb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wt[ab] = mfma32(Tq[(jb * 16 + 4 * g + r) * I::TLD + ab * 16 + n], w[jb][r], wt[ab]);
+    if constexpr (PAIR) {
+      const auto c1r = rsrc(C1g, 16 * NB * 8);
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const int off = (n * NB + c0 + mb * 16 + 2 * g) * 8;
+        gst2(c1r, off, d2{c1v[mb][0] - static_cast<double>(wt[mb][0]), c1v[mb][1] - static_cast<double>(wt[mb][1])});
+        gst2(c1r, off + 64,
+             d2{c1v[mb][2] - static_cast<double>(wt[mb][2]), c1v[mb][3] - static_cast<double>(wt[mb][3])});
+      }
+      // The next block's C1 rows (not touched by this block); their latency
+      // overlaps the second contraction.
+      if (b + 1 < NBLK) load_c1_lp<NB>(c1v, C1g, c0 + IB, true);
+    }
+    // C2 -= V W'.
+    if constexpr (P == P_F32) {
+      // Lane (g, n) supplies V at row position 16 rb + n and reflector
+      // position 16 mb + 4 g + r (one float per MFMA).
+#pragma unroll
+      for (int rb = 0; rb < NJ; rb += 2) {
+        const bool v0 = rb >= rb_lo && rb < rb_hi, v1 = rb + 1 >= rb_lo && rb + 1 < rb_hi;
+        if (!v0 && !v1) continue;
+        f4 d0 = zero4f(), d1 = zero4f();
+        const float* vr = reinterpret_cast<const float*>(cur) + 4 * g * I::LCM + rb * 16 + n;
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const float* v = vr + (mb * 16 + r) * I::LCM;
+            if (v0) d0 = mfma32(v[0], wt[mb][r], d0);
+            if (v1) d1 = mfma32(v[16], wt[mb][r], d1);
+          }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (v0) acc[rb][r] -= static_cast<double>(d0[r]);
+          if (v1) acc[rb + 1][r] -= static_cast<double>(d1[r]);
+        }
+      }
+    } else {
+      // k-slice: element e of lane (g, n) is reflector position
+      // 16 (e / 4) + 4 g + e % 4.
+      bf8 bw;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        bw[e] = static_cast<__bf16>(wt[0][e]);
+        bw[4 + e] = static_cast<__bf16>(wt[1][e]);
+      }
+#pragma unroll
+      for (int rb = 0; rb < NJ; ++rb) {
+        if (rb < rb_lo || rb >= rb_hi) continue;
+        const T* vr = reinterpret_cast<const T*>(cur + I::RM) + (rb * 16 + n) * I::SRM + 4 * g;
+        const bf4 a0 = *reinterpret_cast<const bf4*>(vr);
+        const bf4 a1 = *reinterpret_cast<const bf4*>(vr + 16);
+        const f4 d = mfmabf(__builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7), bw, zero4f());
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[rb][r] -= static_cast<double>(d[r]);
+      }
+    }
+    // The image of block b + 1 (issued a block ago) has landed in every
+    // wave's part of its slot before the barrier publishes it.
+    wait_vm();
+    __syncthreads();
+  }
+  store_strip_lp<NB>(acc, C2g);
+}
+
+// ---------------------------------------------------------------------------
 // Panel factorization of ib columns (held in LDS on entry and exit, in
 // registers in between).
 //
@@ -904,7 +1240,7 @@ __device__ __forceinline__ void panel_to_lp(double* Ps, int ldp, int K, double* 
 // The inner blocks c0 = cb, cb + ib, ... < ce are factored (all of them, or
 // one when the planner splits the task into block subtasks).
 template <int NB, int P>
-__device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm, int cb, int ce) {
+__device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm, int cb, int ce, unsigned char* img) {
   constexpr int ldp = Smem<NB>::LDP;
   double* Ps = sm + Smem<NB>::PS;
   double* Ts = sm + Smem<NB>::TS;
@@ -929,6 +1265,7 @@ __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm, int
     __syncthreads();
     build_t<NB>(Ps, ldp, K, tau, Gs, Ts);
     for (int e = tid; e < IB * IB; e += NTHREADS) gst(T + (c0 / IB) * IB * IB + e, Ts[e]);
+    if constexpr (P != P_F64 && NB >= 128) write_image<NB, P>(img + (c0 / IB) * Img<NB, P>::BYTES, Ps, ldp, c0, K, Ts);
     const int nch = (NB - c0 - IB) / 16;
     if constexpr (P != P_F64) {
       if (nch > 0) panel_to_lp<NB, P>(Ps, ldp, K, Ts);
@@ -962,7 +1299,8 @@ __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm, int
 // TT: 1 for TTQRT (A2 upper triangular), 0 for TSQRT.
 // Inner blocks cb <= c0 < ce as for geqrt_task.
 template <int NB, int P, int TT>
-__device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T, double* sm, int cb, int ce) {
+__device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T, double* sm, int cb, int ce,
+                                              unsigned char* img) {
   constexpr int tt = TT;
   constexpr int ldp = Smem<NB>::LDP;
   double* Ps = sm + Smem<NB>::PS;
@@ -996,6 +1334,7 @@ __device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T,
       unstage_block<NB, false>(Ps, ldp, A2 + c0 * NB, K, c0);
     build_t<NB>(Ps, ldp, K, tau, Gs, Ts);
     for (int e = tid; e < IB * IB; e += NTHREADS) gst(T + (c0 / IB) * IB * IB + e, Ts[e]);
+    if constexpr (P != P_F64 && NB >= 128) write_image<NB, P>(img + (c0 / IB) * Img<NB, P>::BYTES, Ps, ldp, 0, K, Ts);
     const int nch = (NB - c0 - IB) / 16;
     const int hi = tt ? (c0 + IB) / 16 : NB / 16;
     if constexpr (P != P_F64) {
@@ -1333,24 +1672,47 @@ __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T,
 // subtasks and the application of Q to right-hand sides are FP64.
 template <int NB, int P>
 __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, double* sm) {
+  // Low-precision updates at nb >= 128 run as wide subtasks from reflector
+  // images (the planner splits them into WIDE_SLAB-column slabs).
+  constexpr bool kWide = P != P_F64 && NB >= 128;
+  static_assert(!kWide || 3 * Img<NB, P>::BYTES <= Smem<NB>::TOTAL * 8, "LDS of the wide update");
+  static_assert(WSLAB == WIDE_SLAB && WSLAB == 16 * NWAVES, "wide slab width");
   // Panel subtasks: slab = the inner block to factor, or -1 for all.
   const int cb = s.slab < 0 ? 0 : s.slab * IB, ce = s.slab < 0 ? NB : cb + IB;
   switch (s.kind) {
     case D_GEQRT:
-      geqrt_task<NB, P>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), sm, cb, ce);
+      geqrt_task<NB, P>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), sm, cb, ce,
+                        kWide ? imgg_ptr<NB, P>(a, s.i, s.k) : nullptr);
       break;
     case D_UNMQR:
+      if constexpr (kWide) {
+        wide_update_task<NB, P, V_UNM>(imgg_ptr<NB, P>(a, s.i, s.k), nullptr, tile_ptr(a, s.i, s.j), s.slab * WSLAB,
+                                       reinterpret_cast<unsigned char*>(sm));
+        break;
+      }
       unmqr_task<NB, P>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), tile_ptr(a, s.i, s.j), s.slab * SLAB, NB, sm, 1);
       break;
     case D_TSQRT:
     case D_TTQRT:
       if (s.kind == D_TTQRT)
-        pair_qrt_task<NB, P, 1>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm, cb, ce);
+        pair_qrt_task<NB, P, 1>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm, cb, ce,
+                                kWide ? imgp_ptr<NB, P>(a, s.i, s.k) : nullptr);
       else
-        pair_qrt_task<NB, P, 0>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm, cb, ce);
+        pair_qrt_task<NB, P, 0>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm, cb, ce,
+                                kWide ? imgp_ptr<NB, P>(a, s.i, s.k) : nullptr);
       break;
     case D_TSMQR:
     case D_TTMQR:
+      if constexpr (kWide) {
+        unsigned char* lds = reinterpret_cast<unsigned char*>(sm);
+        if (s.kind == D_TTMQR)
+          wide_update_task<NB, P, V_TT>(imgp_ptr<NB, P>(a, s.i, s.k), tile_ptr(a, s.piv, s.j), tile_ptr(a, s.i, s.j),
+                                        s.slab * WSLAB, lds);
+        else
+          wide_update_task<NB, P, V_TS>(imgp_ptr<NB, P>(a, s.i, s.k), tile_ptr(a, s.piv, s.j), tile_ptr(a, s.i, s.j),
+                                        s.slab * WSLAB, lds);
+        break;
+      }
       if (s.kind == D_TTMQR)
         pair_mqr_task<NB, P, 1>(tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), tile_ptr(a, s.piv, s.j),
                                 tile_ptr(a, s.i, s.j), s.slab * SLAB, NB, sm, 1);
