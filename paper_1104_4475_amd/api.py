@@ -83,12 +83,12 @@ class Factors:
 
     def exec_plan(self):
         """Executor subtasks of the factorization in dispatch order: int32
-        array (n, 8) = kind, i, piv, k, j, slab, dep_begin, dep_end, and the
-        int32 predecessor array (tiledqr_exec_plan)."""
+        array (n, 10) = kind, i, piv, k, j, slab, dep_begin, dep_end, sdep,
+        pdep, and the int32 predecessor array (tiledqr_exec_plan)."""
         import numpy as np
         n, nd = ctypes.c_int64(), ctypes.c_int64()
         check(_lib.tiledqr_exec_plan(self.handle, None, ctypes.byref(n), None, ctypes.byref(nd)), "tiledqr_exec_plan")
-        sub = np.zeros((max(1, n.value), 8), dtype=np.int32)
+        sub = np.zeros((max(1, n.value), 10), dtype=np.int32)
         deps = np.zeros(max(1, nd.value), dtype=np.int32)
         P = ctypes.POINTER(ctypes.c_int32)
         check(_lib.tiledqr_exec_plan(self.handle, sub.ctypes.data_as(P), ctypes.byref(n), deps.ctypes.data_as(P),

@@ -49,6 +49,7 @@ struct DevPlan {
   DevSub* sub = nullptr;
   int32_t* deps = nullptr;
   int32_t* flags = nullptr;
+  int32_t* prog = nullptr;   // per-block progress of streamed predecessors
   int32_t* order = nullptr;
   int32_t nsub = 0;
   std::vector<int32_t> level_ptr;
@@ -58,10 +59,12 @@ struct DevPlan {
     if (sub) (void)hipFree(sub);
     if (deps) (void)hipFree(deps);
     if (flags) (void)hipFree(flags);
+    if (prog) (void)hipFree(prog);
     if (order) (void)hipFree(order);
     sub = nullptr;
     deps = nullptr;
     flags = nullptr;
+    prog = nullptr;
     order = nullptr;
   }
 };
@@ -74,13 +77,22 @@ int upload(const ExecPlan& ex, DevPlan& d) {
       return TQR_EINVAL;
     for (int32_t e = ex.sub[t].dep_begin; e < ex.sub[t].dep_end; ++e)
       if (ex.deps[e] < 0 || ex.deps[e] >= static_cast<int32_t>(t)) return TQR_EINVAL;
+    if (ex.sub[t].sdep >= static_cast<int32_t>(t)) return TQR_EINVAL;
+    if (ex.sub[t].pdep >= 0) {
+      if (ex.sub[t].pdep + ex.pblk > static_cast<int32_t>(ex.deps.size())) return TQR_EINVAL;
+      for (int b = 0; b < ex.pblk; ++b) {
+        const int32_t d = ex.deps[ex.sub[t].pdep + b];
+        if (d < 0 || d >= static_cast<int32_t>(t)) return TQR_EINVAL;
+      }
+    }
   }
   d.nsub = static_cast<int32_t>(ex.sub.size());
   d.level_ptr = ex.level_ptr;
   const size_t ns = std::max<size_t>(1, ex.sub.size());
   const size_t nd = std::max<size_t>(1, ex.deps.size());
   if (!hip_ok(hipMalloc(&d.sub, ns * sizeof(DevSub))) || !hip_ok(hipMalloc(&d.deps, nd * sizeof(int32_t))) ||
-      !hip_ok(hipMalloc(&d.flags, ns * sizeof(int32_t))) || !hip_ok(hipMalloc(&d.order, ns * sizeof(int32_t)))) {
+      !hip_ok(hipMalloc(&d.flags, ns * sizeof(int32_t))) || !hip_ok(hipMalloc(&d.prog, ns * sizeof(int32_t))) ||
+      !hip_ok(hipMalloc(&d.order, ns * sizeof(int32_t)))) {
     d.release();
     return TQR_ENOMEM;
   }
@@ -91,6 +103,7 @@ int upload(const ExecPlan& ex, DevPlan& d) {
   if (!ex.level_order.empty())
     HIP_TRY(hipMemcpy(d.order, ex.level_order.data(), ex.level_order.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(d.flags, 0, ns * sizeof(int32_t)));
+  HIP_TRY(hipMemset(d.prog, 0, ns * sizeof(int32_t)));
   return TQR_OK;
 }
 
@@ -261,6 +274,7 @@ ExecArgs base_args(const tqr_factors* F, const DevPlan& d) {
   a.sub = d.sub;
   a.deps = d.deps;
   a.flags = d.flags;
+  a.prog = d.prog;
   a.ticket = F->ctl;
   a.err = F->ctl + 1;
   a.nsub = d.nsub;
@@ -417,7 +431,11 @@ int create(const tqr_opts* o, tqr_factors** out, ExecPlan* keep = nullptr) {
   // keeps whole panel tasks).
   const char* ps = std::getenv("TQR_PANEL_SPLIT");
   const int pblk = (F->nb >= 128 && !(ps && ps[0] == '0')) ? F->nb / tqr::IB : 1;
-  tqr::make_exec_plan(F->plan, nslab, exec_order(), w, ex, pblk);
+  // Wide low-precision updates stream their reflectors and C1 tiles block by
+  // block (TQR_STREAM=0 waits for whole predecessors instead).
+  const char* sv = std::getenv("TQR_STREAM");
+  const bool stream = tqr::update_slab(F->nb, o->upd) == tqr::WIDE_SLAB && !(sv && sv[0] == '0');
+  tqr::make_exec_plan(F->plan, nslab, exec_order(), w, ex, pblk, stream);
   int st = upload(ex, F->exec);
   if (st != TQR_OK) return st;
   if (keep) *keep = ex;
@@ -714,7 +732,7 @@ int tiledqr_exec_plan(const tqr_factors* F, int32_t* sub, int64_t* nsub, int32_t
   if (sub)
     for (size_t t = 0; t < ex.sub.size(); ++t) {
       const tqr::SubTask& st = ex.sub[t];
-      int32_t* o = sub + 8 * t;
+      int32_t* o = sub + 10 * t;
       o[0] = st.kind;
       o[1] = st.i;
       o[2] = st.piv;
@@ -723,6 +741,8 @@ int tiledqr_exec_plan(const tqr_factors* F, int32_t* sub, int64_t* nsub, int32_t
       o[5] = st.slab;
       o[6] = st.dep_begin;
       o[7] = st.dep_end;
+      o[8] = st.sdep;
+      o[9] = st.pdep;
     }
   if (deps) std::copy(ex.deps.begin(), ex.deps.end(), deps);
   return TQR_OK;

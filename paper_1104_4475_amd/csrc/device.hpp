@@ -32,6 +32,8 @@ enum DevKind : int32_t {
 
 struct DevSub {
   int32_t kind, i, piv, k, j, slab, dep_begin, dep_end;
+  int32_t sdep;   // streamed predecessor (C1 writer) or -1
+  int32_t pdep;   // offset in deps of the streamed panel blocks, or -1
 };
 
 struct ExecArgs {
@@ -42,6 +44,7 @@ struct ExecArgs {
   const DevSub* sub;
   const int32_t* deps;
   int32_t* flags;       // one per subtask, set to epoch when done
+  int32_t* prog;        // one per subtask: 64 epoch + blocks done (streamed updates)
   int32_t* ticket;      // dispatch counter (reset before each launch)
   int32_t* err;         // nonzero once any wait timed out
   int32_t nsub;

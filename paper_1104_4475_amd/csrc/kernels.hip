@@ -852,6 +852,59 @@ __device__ __forceinline__ void store_strip_lp(const d4 (&acc)[NB / 16], double*
   }
 }
 
+// Block-by-block following of streamed predecessors (the planner's pdep and
+// sdep edges).  A panel block publishes its completion flag (epoch); a wide
+// update publishes 64 epoch + b + 1 in its progress word once its block b is
+// stored: C1 rows b ib .. b ib + ib - 1 (pair updates) or rows up to
+// b ib + ib - 1 of its tile (UNMQR) are then final.
+struct StreamCtl {
+  const int32_t* flags;  // completion flags
+  const int32_t* prog;   // progress words
+  int32_t* self;         // this subtask's progress word
+  const int32_t* pblk;   // dispatch indices of the streamed panel blocks, or null
+  int32_t sdep;          // streamed C1 writer, or -1
+  int32_t epoch;
+  int32_t* err;
+  int64_t spin;
+};
+
+// Wave-level wait until ok(*w) (relaxed device-scope loads).  Gives up when
+// the wait exceeds the executor's time limit or another workgroup has
+// failed, and then sets the error word (the executor stops at its next wait).
+template <class Ok>
+__device__ __forceinline__ void wait_word(const int32_t* w, Ok ok, const StreamCtl& c) {
+  const uint64_t t0 = wall_clock64();
+  for (;;) {
+    const int v = __builtin_amdgcn_readfirstlane(
+        __hip_atomic_load(const_cast<int32_t*>(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (ok(v)) return;
+    const int e = __builtin_amdgcn_readfirstlane(__hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (e != 0 || static_cast<int64_t>(wall_clock64() - t0) > c.spin) {
+      if (lane_id() == 0) __hip_atomic_store(c.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+__device__ __forceinline__ void wait_panel_block(const StreamCtl& c, int b) {
+  if (c.pblk) {
+    const int e = c.epoch;
+    wait_word(c.flags + c.pblk[b], [e](int v) { return v == e; }, c);
+  }
+}
+__device__ __forceinline__ bool c1_ready(const StreamCtl& c, int b) {
+  if (c.sdep < 0) return true;
+  const int v = __builtin_amdgcn_readfirstlane(
+      __hip_atomic_load(const_cast<int32_t*>(c.prog + c.sdep), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+  return v >= 64 * c.epoch + b + 1;
+}
+__device__ __forceinline__ void wait_c1(const StreamCtl& c, int b) {
+  if (c.sdep >= 0) {
+    const int need = 64 * c.epoch + b + 1;
+    wait_word(c.prog + c.sdep, [need](int v) { return v >= need; }, c);
+  }
+}
+
 // Update subtask on columns col0 .. col0 + 127 of the target tile(s):
 //   V_UNM  C2 <- Q^T C2 with the GEQRT set of a factored tile (C1 unused);
 //   V_TS / V_TT  [C1; C2] <- Q^T [C1; C2] with a TS / TT set.
@@ -859,7 +912,7 @@ __device__ __forceinline__ void store_strip_lp(const d4 (&acc)[NB / 16], double*
 // lds: three slots of that size.  Only Q^T (the factorization).
 template <int NB, int P, int VAR>
 __device__ __forceinline__ void wide_update_task(const unsigned char* img, double* C1, double* C2, int col0,
-                                                 unsigned char* lds) {
+                                                 unsigned char* lds, const StreamCtl& sc) {
   using I = Img<NB, P>;
   using T = typename LpV<32, P>::T;
   constexpr int NBLK = NB / IB, NJ = NB / 16, SLOT = I::BYTES;
@@ -871,20 +924,31 @@ __device__ __forceinline__ void wide_update_task(const unsigned char* img, doubl
   // Three LDS slots: block b is read from slot b % 3 while the image of
   // block b + 2 lands in slot (b + 2) % 3, which block b - 1 read before the
   // barrier that ended it.
+  wait_panel_block(sc, 0);
   img_dma<NB, P>(img, lds);
-  if (NBLK > 1) img_dma<NB, P>(img + I::BYTES, lds + SLOT);
+  if (NBLK > 1) {
+    wait_panel_block(sc, 1);
+    img_dma<NB, P>(img + I::BYTES, lds + SLOT);
+  }
   d4 acc[NJ];
   load_strip_lp<NB>(acc, C2g);
   d4 c1v[2] = {zero4(), zero4()};
-  if constexpr (PAIR) load_c1_lp<NB>(c1v, C1g, 0, true);
+  if constexpr (PAIR) {
+    wait_c1(sc, 0);
+    load_c1_lp<NB>(c1v, C1g, 0, true);
+  }
   wait_vm();
   __syncthreads();
   int scur = 0;
+  bool c1_late = false;
 #pragma unroll 1
   for (int b = 0; b < NBLK; ++b) {
     const int c0 = b * IB;
     const unsigned char* cur = lds + scur * SLOT;
-    if (b + 2 < NBLK) img_dma<NB, P>(img + static_cast<size_t>(b + 2) * I::BYTES, lds + ((scur == 0) ? 2 : scur - 1) * SLOT);
+    if (b + 2 < NBLK) {
+      wait_panel_block(sc, b + 2);
+      img_dma<NB, P>(img + static_cast<size_t>(b + 2) * I::BYTES, lds + ((scur == 0) ? 2 : scur - 1) * SLOT);
+    }
     scur = (scur == 2) ? 0 : scur + 1;
     const int rb_lo = (VAR == V_UNM) ? (c0 >> 4) : 0;
     const int rb_hi = (VAR == V_TT) ? ((c0 + IB) >> 4) : NJ;
@@ -966,8 +1030,15 @@ __device__ __forceinline__ void wide_update_task(const unsigned char* img, doubl
              d2{c1v[mb][2] - static_cast<double>(wt[mb][2]), c1v[mb][3] - static_cast<double>(wt[mb][3])});
       }
       // The next block's C1 rows (not touched by this block); their latency
-      // overlaps the second contraction.
-      if (b + 1 < NBLK) load_c1_lp<NB>(c1v, C1g, c0 + IB, true);
+      // overlaps the second contraction when the C1 writer followed (if any)
+      // is already past that block, else they are fetched after it.
+      c1_late = false;
+      if (b + 1 < NBLK) {
+        if (c1_ready(sc, b + 1))
+          load_c1_lp<NB>(c1v, C1g, c0 + IB, true);
+        else
+          c1_late = true;
+      }
     }
     // C2 -= V W'.
     if constexpr (P == P_F32) {
@@ -1013,12 +1084,32 @@ __device__ __forceinline__ void wide_update_task(const unsigned char* img, doubl
         for (int r = 0; r < 4; ++r) acc[rb][r] -= static_cast<double>(d[r]);
       }
     }
+    if constexpr (VAR == V_UNM) {
+      // Rows c0 .. c0 + 31 are final (later blocks touch rows >= c0 + 32).
+      const auto r = rsrc(C2g, 16 * NB * 8);
+#pragma unroll
+      for (int rb = 0; rb < NJ; ++rb) {
+        if ((rb >> 1) != b) continue;
+        const int off = (n * NB + rb * 16 + 2 * g) * 8;
+        gst2(r, off, d2{acc[rb][0], acc[rb][1]});
+        gst2(r, off + 64, d2{acc[rb][2], acc[rb][3]});
+      }
+    }
+    if constexpr (PAIR) {
+      if (c1_late) {
+        wait_c1(sc, b + 1);
+        load_c1_lp<NB>(c1v, C1g, c0 + IB, true);
+      }
+    }
     // The image of block b + 1 (issued a block ago) has landed in every
-    // wave's part of its slot before the barrier publishes it.
+    // wave's part of its slot, and this block's stores are complete, before
+    // the barrier publishes both.
     wait_vm();
     __syncthreads();
+    if (sc.self && threadIdx.x == 0)
+      __hip_atomic_store(sc.self, 64 * sc.epoch + b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  store_strip_lp<NB>(acc, C2g);
+  if constexpr (VAR != V_UNM) store_strip_lp<NB>(acc, C2g);
 }
 
 // ---------------------------------------------------------------------------
@@ -1671,12 +1762,18 @@ __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T,
 // P: precision of the update subtasks (UNMQR, TSMQR, TTMQR); the panel
 // subtasks and the application of Q to right-hand sides are FP64.
 template <int NB, int P>
-__device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, double* sm) {
+__device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, double* sm, int t) {
   // Low-precision updates at nb >= 128 run as wide subtasks from reflector
   // images (the planner splits them into WIDE_SLAB-column slabs).
   constexpr bool kWide = P != P_F64 && NB >= 128;
   static_assert(!kWide || 3 * Img<NB, P>::BYTES <= Smem<NB>::TOTAL * 8, "LDS of the wide update");
   static_assert(WSLAB == WIDE_SLAB && WSLAB == 16 * NWAVES, "wide slab width");
+  StreamCtl sc{};
+  if constexpr (kWide) {
+    const int pd = __builtin_amdgcn_readfirstlane(s.pdep), sd = __builtin_amdgcn_readfirstlane(s.sdep);
+    sc = StreamCtl{a.flags, a.prog, a.prog ? a.prog + t : nullptr, pd >= 0 ? a.deps + pd : nullptr,
+                   sd, a.epoch, a.err, a.spin_ticks};
+  }
   // Panel subtasks: slab = the inner block to factor, or -1 for all.
   const int cb = s.slab < 0 ? 0 : s.slab * IB, ce = s.slab < 0 ? NB : cb + IB;
   switch (s.kind) {
@@ -1687,7 +1784,7 @@ __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, doub
     case D_UNMQR:
       if constexpr (kWide) {
         wide_update_task<NB, P, V_UNM>(imgg_ptr<NB, P>(a, s.i, s.k), nullptr, tile_ptr(a, s.i, s.j), s.slab * WSLAB,
-                                       reinterpret_cast<unsigned char*>(sm));
+                                       reinterpret_cast<unsigned char*>(sm), sc);
         break;
       }
       unmqr_task<NB, P>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), tile_ptr(a, s.i, s.j), s.slab * SLAB, NB, sm, 1);
@@ -1707,10 +1804,10 @@ __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, doub
         unsigned char* lds = reinterpret_cast<unsigned char*>(sm);
         if (s.kind == D_TTMQR)
           wide_update_task<NB, P, V_TT>(imgp_ptr<NB, P>(a, s.i, s.k), tile_ptr(a, s.piv, s.j), tile_ptr(a, s.i, s.j),
-                                        s.slab * WSLAB, lds);
+                                        s.slab * WSLAB, lds, sc);
         else
           wide_update_task<NB, P, V_TS>(imgp_ptr<NB, P>(a, s.i, s.k), tile_ptr(a, s.piv, s.j), tile_ptr(a, s.i, s.j),
-                                        s.slab * WSLAB, lds);
+                                        s.slab * WSLAB, lds, sc);
         break;
       }
       if (s.kind == D_TTMQR)
@@ -1885,7 +1982,7 @@ __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
       for (int e = threadIdx.x; e < Smem<NB>::TOTAL; e += NTHREADS) sm[e] = 0.0;
       __syncthreads();
     }
-    run_sub<NB, P>(a, a.sub[t], sm);
+    run_sub<NB, P>(a, a.sub[t], sm, t);
   });
 }
 
@@ -1959,9 +2056,9 @@ __global__ __launch_bounds__(NTHREADS) void exec_batched(BatchArgs b) {
     a.nb = __builtin_amdgcn_readfirstlane(pd.nb);
     a.upd = P;
     if (a.nb == 32)
-      run_sub<32, P>(a, b.sub[t], sm);
+      run_sub<32, P>(a, b.sub[t], sm, t);
     else
-      run_sub<64, P>(a, b.sub[t], sm);
+      run_sub<64, P>(a, b.sub[t], sm, t);
   });
 }
 
@@ -2004,7 +2101,7 @@ template <int NB, int P>
 __global__ __launch_bounds__(NTHREADS) void exec_level(ExecArgs a, const int32_t* order, int begin) {
   __shared__ double sm[Smem<NB>::TOTAL];
   const int t = __builtin_amdgcn_readfirstlane(order[begin + blockIdx.x]);
-  run_sub<NB, P>(a, a.sub[t], sm);
+  run_sub<NB, P>(a, a.sub[t], sm, t);
 }
 
 __global__ void reset_kernel(int32_t* ticket, int32_t* err) {

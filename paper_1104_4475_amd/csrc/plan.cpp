@@ -348,6 +348,17 @@ bool make_plan(int p, int q, int tree, int bs, int family, Plan& plan) {
   return true;
 }
 
+// Every predecessor of subtask r of an executor plan: the ones waited for
+// before it starts, the streamed C1 writer and the streamed panel blocks.
+std::vector<int32_t> stream_preds(const ExecPlan& ex, size_t r) {
+  const SubTask& st = ex.sub[r];
+  std::vector<int32_t> v(ex.deps.begin() + st.dep_begin, ex.deps.begin() + st.dep_end);
+  if (st.sdep >= 0) v.push_back(st.sdep);
+  if (st.pdep >= 0)
+    for (int b = 0; b < ex.pblk; ++b) v.push_back(ex.deps[st.pdep + b]);
+  return v;
+}
+
 // ---------------------------------------------------------------------------
 // Executor plan.  An update task on column slab s of its C tiles only touches
 // slab s, so dependencies are tracked per (tile, slab); the panel tasks touch
@@ -364,7 +375,21 @@ bool make_plan(int p, int q, int tree, int bs, int family, Plan& plan) {
 // the whole task: consecutive panel tasks on a pivot pipeline block by
 // block.  Block 0 waits for the task's other (update) predecessors, block b
 // for block b - 1, and later tasks depend on the last block.
-void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex, int pblk) {
+//
+// With stream, two kinds of edges are streamed: the subtask starts without
+// waiting for the predecessor to finish and follows it block by block
+// inside the kernel.
+//   pdep: an update subtask applies the ib-blocks of reflectors of one panel
+//   task in order, and block b only needs panel block b (its reflectors and
+//   T); it waits for each block's flag before it fetches that block.
+//   sdep: block b of a pair update (TSMQR, TTMQR) reads and writes only rows
+//   b ib .. b ib + ib - 1 of its C1 tile.  If the previous writer of that
+//   tile slab is a pair update with the same pivot row (C1 in both) or the
+//   UNMQR of the pivot row (whose block b finishes rows up to b ib + ib - 1
+//   for good), block b only needs the previous writer's progress past its
+//   own block b; writers publish their progress after every block.
+// Streamed predecessors still count in the priorities and the level order.
+void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex, int pblk, bool stream) {
   const int p = plan.p, q = plan.q, S = nslab;
   ex = ExecPlan();
   ex.nslab = S;
@@ -376,18 +401,35 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
   std::vector<SubTask> sub;  // emission order
   std::vector<std::vector<int32_t>> pre;
   std::vector<int32_t> task_of;
+  std::vector<int32_t> sdep, pfirst;  // streamed C1 writer, panel block 0 (emission order), or -1
   sub.reserve(plan.tasks.size() * 2);
+  stream = stream && pblk > 1;
 
   std::vector<int32_t> first_blk;  // panel subtasks: id of block 0 of the task; -1 otherwise
   auto add = [&](const Task& t, int32_t tidx, int slab, std::vector<int32_t>&& d) {
     std::sort(d.begin(), d.end());
     d.erase(std::unique(d.begin(), d.end()), d.end());
     if (!d.empty() && d.front() < 0) d.erase(d.begin(), std::upper_bound(d.begin(), d.end(), -1));
-    sub.push_back({t.kind, t.i - 1, t.piv > 0 ? t.piv - 1 : 0, t.k - 1, t.j > 0 ? t.j - 1 : 0, slab, 0, 0});
+    sub.push_back({t.kind, t.i - 1, t.piv > 0 ? t.piv - 1 : 0, t.k - 1, t.j > 0 ? t.j - 1 : 0, slab, 0, 0, -1, -1});
     pre.push_back(std::move(d));
     task_of.push_back(tidx);
     first_blk.push_back(-1);
+    sdep.push_back(-1);
+    pfirst.push_back(-1);
     return static_cast<int32_t>(sub.size()) - 1;
+  };
+  // The last panel block subtask w among the reflector writers d (a panel
+  // task split into pblk blocks): returns its block 0, and drops w from d.
+  auto take_panel = [&](std::vector<int32_t>& d) -> int32_t {
+    if (!stream) return -1;
+    int32_t w = -1;
+    for (int32_t x : d)
+      if (x >= 0 && first_blk[x] >= 0) w = (w < 0 || x > w) ? x : w;
+    if (w < 0) return -1;
+    const int32_t f = first_blk[w];
+    if (w != f + pblk - 1) return -1;
+    d.erase(std::remove(d.begin(), d.end(), w), d.end());
+    return f;
   };
   // A panel task: one subtask, or pblk block subtasks; returns the id of the
   // last.  d_full: writers the task waits for as a whole (from block 0);
@@ -460,27 +502,42 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
       }
       case K_UNMQR: {
         for (int s = 0; s < S; ++s) {
-          std::vector<int32_t> d;
-          for (int s2 = 0; s2 < S; ++s2) d.push_back(lo[slot(t.i, t.k, s2)]);
+          std::vector<int32_t> dv, d;
+          for (int s2 = 0; s2 < S; ++s2) dv.push_back(lo[slot(t.i, t.k, s2)]);
+          const int32_t pf = take_panel(dv);
+          d = dv;
           d.push_back(up[slot(t.i, t.j, s)]);
           d.push_back(lo[slot(t.i, t.j, s)]);
           const int32_t id = add(t, tid, s, std::move(d));
+          pfirst[id] = pf;
           up[slot(t.i, t.j, s)] = lo[slot(t.i, t.j, s)] = id;
         }
         break;
       }
       default: {  // TSMQR / TTMQR
         for (int s = 0; s < S; ++s) {
-          std::vector<int32_t> d;
+          std::vector<int32_t> dv, d;
           for (int s2 = 0; s2 < S; ++s2) {
-            d.push_back(up[slot(t.i, t.k, s2)]);
-            if (t.kind == K_TSMQR) d.push_back(lo[slot(t.i, t.k, s2)]);
+            dv.push_back(up[slot(t.i, t.k, s2)]);
+            if (t.kind == K_TSMQR) dv.push_back(lo[slot(t.i, t.k, s2)]);
           }
-          d.push_back(up[slot(t.piv, t.j, s)]);
-          d.push_back(lo[slot(t.piv, t.j, s)]);
-          d.push_back(up[slot(t.i, t.j, s)]);
-          d.push_back(lo[slot(t.i, t.j, s)]);
+          const int32_t pf = take_panel(dv);
+          d = dv;
+          const int32_t c2u = up[slot(t.i, t.j, s)], c2l = lo[slot(t.i, t.j, s)];
+          int32_t c1 = up[slot(t.piv, t.j, s)];
+          const bool c1_stream = stream && c1 >= 0 && c1 == lo[slot(t.piv, t.j, s)] && c1 != c2u && c1 != c2l &&
+                                 std::find(d.begin(), d.end(), c1) == d.end() &&
+                                 ((sub[c1].kind == K_UNMQR && sub[c1].i == t.piv - 1) ||
+                                  ((sub[c1].kind == K_TSMQR || sub[c1].kind == K_TTMQR) && sub[c1].piv == t.piv - 1));
+          if (!c1_stream) {
+            d.push_back(c1);
+            d.push_back(lo[slot(t.piv, t.j, s)]);
+          }
+          d.push_back(c2u);
+          d.push_back(c2l);
           const int32_t id = add(t, tid, s, std::move(d));
+          pfirst[id] = pf;
+          if (c1_stream) sdep[id] = c1;
           up[slot(t.piv, t.j, s)] = lo[slot(t.piv, t.j, s)] = id;
           up[slot(t.i, t.j, s)] = lo[slot(t.i, t.j, s)] = id;
         }
@@ -499,16 +556,24 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
     const bool is_upd = (kd == K_UNMQR || kd == K_TSMQR || kd == K_TTMQR);
     wt[s] = is_upd ? w[kd] / S : w[kd] / (sub[s].slab >= 0 ? pblk : 1);
   }
+  // All predecessors, the streamed ones included, order the subtasks.
+  std::vector<std::vector<int32_t>> allp(n);
+  for (size_t s = 0; s < n; ++s) {
+    allp[s] = pre[s];
+    if (sdep[s] >= 0) allp[s].push_back(sdep[s]);
+    if (pfirst[s] >= 0)
+      for (int b = 0; b < pblk; ++b) allp[s].push_back(pfirst[s] + b);
+  }
   double span = 0.0;
   for (size_t s = 0; s < n; ++s) {
     double st = 0.0;
-    for (int32_t d : pre[s]) st = std::max(st, est[d] + wt[d]);
+    for (int32_t d : allp[s]) st = std::max(st, est[d] + wt[d]);
     est[s] = st;
     span = std::max(span, st + wt[s]);
   }
   std::vector<std::vector<int32_t>> succ(n);
   for (size_t s = 0; s < n; ++s)
-    for (int32_t d : pre[s]) succ[d].push_back(static_cast<int32_t>(s));
+    for (int32_t d : allp[s]) succ[d].push_back(static_cast<int32_t>(s));
   for (size_t s = n; s-- > 0;) {
     double lf = span;
     for (int32_t c : succ[s]) lf = std::min(lf, lst[c]);
@@ -543,15 +608,22 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
     st.dep_begin = static_cast<int32_t>(ex.deps.size());
     for (int32_t d : pre[s]) ex.deps.push_back(pos[d]);
     st.dep_end = static_cast<int32_t>(ex.deps.size());
+    st.sdep = sdep[s] >= 0 ? pos[sdep[s]] : -1;
+    st.pdep = -1;
+    if (pfirst[s] >= 0) {
+      st.pdep = static_cast<int32_t>(ex.deps.size());
+      for (int b = 0; b < pblk; ++b) ex.deps.push_back(pos[pfirst[s] + b]);
+    }
     ex.sub[r] = st;
   }
 
-  // Depth levels for the level-synchronous launch path.
+  // Depth levels for the level-synchronous launch path (streamed
+  // predecessors run in earlier levels).
   std::vector<int32_t> depth(n, 0);
   int32_t maxd = 0;
   for (size_t r = 0; r < n; ++r) {
     int32_t dd = 0;
-    for (int32_t e = ex.sub[r].dep_begin; e < ex.sub[r].dep_end; ++e) dd = std::max(dd, depth[ex.deps[e]] + 1);
+    for (int32_t d : stream_preds(ex, r)) dd = std::max(dd, depth[d] + 1);
     depth[r] = dd;
     maxd = std::max(maxd, dd);
   }
@@ -581,7 +653,7 @@ void make_apply_plan(const Plan& plan, int trans, int nslab, ExecPlan& ex) {
     const Task& tk = plan.tasks[t];
     const int kind = tk.kind == K_GEQRT ? 6 : (tk.kind == K_TSQRT ? 7 : 8);
     for (int s = 0; s < nslab; ++s) {
-      SubTask st{kind, tk.i - 1, tk.piv > 0 ? tk.piv - 1 : 0, tk.k - 1, 0, s, 0, 0};
+      SubTask st{kind, tk.i - 1, tk.piv > 0 ? tk.piv - 1 : 0, tk.k - 1, 0, s, 0, 0, -1, -1};
       st.dep_begin = static_cast<int32_t>(ex.deps.size());
       const int32_t a = last[static_cast<size_t>(tk.i - 1) * nslab + s];
       const int32_t b = tk.piv > 0 ? last[static_cast<size_t>(tk.piv - 1) * nslab + s] : -1;
@@ -624,7 +696,7 @@ void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, co
     if ((s.kind == K_GEQRT || s.kind == K_TSQRT || s.kind == K_TTQRT) && (s.slab < 0 || s.slab == fac.pblk - 1))
       panel[{s.kind, s.i, s.k}] = static_cast<int32_t>(t);
   }
-  std::vector<std::vector<int32_t>> pre(n);
+  std::vector<std::vector<int32_t>> pre(n), allp(n);
   for (size_t t = 0; t < nf; ++t)
     for (int32_t e = fac.sub[t].dep_begin; e < fac.sub[t].dep_end; ++e) pre[t].push_back(fac.deps[e]);
   for (size_t a = 0; a < na; ++a) {
@@ -634,6 +706,7 @@ void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, co
     auto it = panel.find({fk, s.i, s.k});
     if (it != panel.end()) pre[nf + a].push_back(it->second);
   }
+  for (size_t t = 0; t < n; ++t) allp[t] = t < nf ? stream_preds(fac, t) : pre[t];
   std::vector<double> wt(n);
   const double S = static_cast<double>(nslab);
   for (size_t t = 0; t < nf; ++t) {
@@ -647,7 +720,7 @@ void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, co
   // application subtasks in theirs), so one backward sweep suffices.
   std::vector<std::vector<int32_t>> succ(n);
   for (size_t t = 0; t < n; ++t)
-    for (int32_t d : pre[t]) succ[d].push_back(static_cast<int32_t>(t));
+    for (int32_t d : allp[t]) succ[d].push_back(static_cast<int32_t>(t));
   std::vector<double> bl(n, 0.0);
   for (size_t t = n; t-- > 0;) {
     double m = 0.0;
@@ -682,6 +755,12 @@ void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, co
     st.dep_begin = static_cast<int32_t>(out.deps.size());
     for (int32_t d : pre[t]) out.deps.push_back(pos[d]);
     st.dep_end = static_cast<int32_t>(out.deps.size());
+    if (st.sdep >= 0) st.sdep = pos[st.sdep];
+    if (st.pdep >= 0) {
+      const int32_t old = st.pdep;
+      st.pdep = static_cast<int32_t>(out.deps.size());
+      for (int b = 0; b < fac.pblk; ++b) out.deps.push_back(pos[fac.deps[old + b]]);
+    }
     out.sub[r] = st;
     out.key[r] = -bl[t];
   }
@@ -689,7 +768,7 @@ void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, co
   int32_t maxd = 0;
   for (size_t r = 0; r < n; ++r) {
     int32_t dd = 0;
-    for (int32_t e = out.sub[r].dep_begin; e < out.sub[r].dep_end; ++e) dd = std::max(dd, depth[out.deps[e]] + 1);
+    for (int32_t d : stream_preds(out, r)) dd = std::max(dd, depth[d] + 1);
     depth[r] = dd;
     maxd = std::max(maxd, dd);
   }

@@ -42,7 +42,11 @@ struct SubTask {
   int32_t kind, i, piv, k, j;   // 0-based tile indices (i, piv, k, j)
   int32_t slab;                 // column slab of the C tiles (updates); for panel
                                 // tasks the inner block it factors, -1 = all
-  int32_t dep_begin, dep_end;   // range in deps[]
+  int32_t dep_begin, dep_end;   // range in deps[] of the predecessors waited for
+                                // before the subtask starts
+  int32_t sdep;                 // streamed predecessor (see make_exec_plan), or -1
+  int32_t pdep;                 // offset in deps[] of the nb/ib panel block
+                                // subtasks whose reflectors it streams, or -1
 };
 
 struct ExecPlan {
@@ -60,7 +64,11 @@ struct ExecPlan {
 // w: per-kind weights used for the priority (any positive values).
 // pblk > 1 splits every panel task (GEQRT, TSQRT, TTQRT) into its pblk inner
 // blocks of columns, one subtask each (see plan.cpp).
-void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex, int pblk = 1);
+// stream (with pblk > 1): update subtasks follow their reflectors block by
+// block (pdep) and pair updates follow the previous writer of their C1 tile
+// block by block (sdep) instead of waiting for them to finish (plan.cpp).
+void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex, int pblk = 1,
+                    bool stream = false);
 
 // One executor plan for the factorization and Q^T B together: the
 // subtasks of fac (built by make_exec_plan with the same nslab and weights

@@ -191,6 +191,23 @@ def test_executor_trace_respects_dag(torch_cuda, case, upd):
             assert np.all(d < t)
             late = end[d] > ready[t]
             assert not late.any(), ("subtask", t, "ready before predecessors", d[late])
+    # 1b. streamed predecessors (FP32 / BF16 updates at nb >= 128): an update
+    # applies panel block b after that block's flag, so it ends after every
+    # streamed panel block has ended; it ends after its C1 writer started.
+    nblk = nb // 32
+    streamed = set()  # (predecessor subtask, successor subtask)
+    for t in range(len(sub)):
+        if sub[t, 9] >= 0:
+            pb = deps[sub[t, 9]:sub[t, 9] + nblk]
+            assert np.all(pb < t)
+            assert np.all(end[pb] <= end[t]), ("subtask", t, "ended before a streamed panel block")
+            streamed.update((int(u), t) for u in pb)
+        if sub[t, 8] >= 0:
+            u = int(sub[t, 8])
+            assert u < t and ready[u] <= end[t]
+            streamed.add((u, t))
+    if upd == 0 or nb < 128:
+        assert not streamed
     # 2. every edge of the oracle's task DAG: each subtask of a task became
     # ready after some subtask of each predecessor task had finished
     p, q = m // nb, n // nb
@@ -205,9 +222,19 @@ def test_executor_trace_respects_dag(torch_cuda, case, upd):
         keys.append(_task_key(kind, i - 1, piv - 1 if piv else 0, k - 1, j - 1 if j else 0))
     assert set(keys) == set(subs_of), "executor tasks differ from the oracle's DAG"
     first_end = {key: end[v].min() for key, v in subs_of.items()}
+    first_ready = {key: ready[v].min() for key, v in subs_of.items()}
+    task_of = {}
+    for key, v in subs_of.items():
+        for t in v:
+            task_of[t] = key
+    streamed_tasks = {(task_of[u], task_of[t]) for u, t in streamed}
     for v, pv in enumerate(preds):
         rv = ready[subs_of[keys[v]]]
         for u in pv:
+            if (keys[u], keys[v]) in streamed_tasks:
+                # followed block by block: v cannot end before u has started
+                assert first_ready[keys[u]] <= end[subs_of[keys[v]]].max(), ("streamed edge", tasks[u], tasks[v])
+                continue
             assert first_end[keys[u]] <= rv.min(), ("DAG edge violated", tasks[u], tasks[v])
 
 
@@ -261,3 +288,37 @@ def test_batch_rerun_refreshes_solve_tables(torch_cuda):
             err = np.max(np.abs(X.cpu().numpy() - Xo)) / np.max(np.abs(Xo))
             _say("  run %d problem %d: max rel diff %.2e" % (rnd, i, err))
             assert err <= 1e-11
+
+
+STREAM_CASES = [
+    # (m, n, nb, tree, bs, kernels, upd): long TS chains, TT merges, both tile sizes
+    (2560, 2560, 256, trees.FLAT, 1, dag.KERN_TS, 1),
+    (2048, 1024, 256, trees.PLASMA, 4, dag.KERN_TS, 2),
+    (2048, 1280, 256, trees.GREEDY, 1, dag.KERN_TT, 1),
+    (1536, 1024, 128, trees.FLAT, 1, dag.KERN_TS, 2),
+]
+
+
+@pytest.mark.parametrize("case", STREAM_CASES, ids=lambda c: "%dx%d_nb%d_t%d_bs%d_k%d_u%d" % c)
+def test_streamed_factors_bit_identical(torch_cuda, case, monkeypatch):
+    """Updates that follow their reflectors and C1 writers block by block do
+    the same arithmetic as updates that wait for whole predecessors, so the
+    factors must agree bit for bit (a read of C1 rows or of a reflector block
+    before its writer finished would show up here)."""
+    import paper_1104_4475_amd as tqr
+    m, n, nb, tree, bs, kern, upd = case
+    _say("streamed vs whole-predecessor %s" % (case,))
+    A = _gpu(torch_cuda, tqr_inputs.gaussian(m, n, seed=97))
+    out = []
+    for stream in ("0", "1"):
+        monkeypatch.setenv("TQR_STREAM", stream)
+        F = tqr.factor(A, nb, tree, bs, kern, upd)
+        F.sync()
+        sub, _ = F.exec_plan()
+        assert (sub[:, 8:] >= 0).any() == (stream == "1")
+        for _ in range(2):
+            F.refactor(A)
+            F.sync()
+            out.append(F.packed().cpu().numpy())
+    for P in out[1:]:
+        assert np.array_equal(P.view(np.uint64), out[0].view(np.uint64))
