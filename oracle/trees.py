@@ -14,6 +14,8 @@ Trees (Sec. 3.1 and Sec. 3.2):
                            row k, then a binary merge of the domain heads.
   ASAP, GRASAP(k)          run-time pairings of the tiled model
                            (oracle/dynamic.py).
+  Hadri(BS)                PlasmaTree with fixed domains (rows 1..BS, ...):
+                           the top domain shrinks (Sec. 4).
 
 Readings where the text leaves room (each pinned by Table 3 of the paper):
   * BinaryTree is re-rooted at row k in every column (offsets from k).
@@ -28,10 +30,10 @@ tests/golden/), by the list identities PT(1) == BinaryTree, PT(p) == FlatTree,
 and by the validity conditions of Sec. 2.2 and Lemma 1.
 """
 
-FLAT, SAMEH_KUCK, BINARY, FIBONACCI, GREEDY, PLASMA, ASAP, GRASAP = 0, 1, 2, 3, 4, 5, 6, 7
+FLAT, SAMEH_KUCK, BINARY, FIBONACCI, GREEDY, PLASMA, ASAP, GRASAP, HADRI = 0, 1, 2, 3, 4, 5, 6, 7, 8
 TREE_NAMES = {FLAT: "FlatTree", SAMEH_KUCK: "Sameh-Kuck", BINARY: "BinaryTree",
               FIBONACCI: "Fibonacci", GREEDY: "Greedy", PLASMA: "PlasmaTree",
-              ASAP: "ASAP", GRASAP: "GRASAP"}
+              ASAP: "ASAP", GRASAP: "GRASAP", HADRI: "Hadri (Semi/Fully-Parallel)"}
 
 
 def _check(p, q):
@@ -176,6 +178,34 @@ def plasma_tree(p, q, bs):
     return out
 
 
+def hadri_tree(p, q, bs):
+    """The Semi-Parallel / Fully-Parallel tile CAQR trees of Hadri et al., as
+    Sec. 4 describes them: flat trees inside domains of BS rows, then a
+    binary tree over the domain heads, as PlasmaTree, except that the
+    domains stay where they are (rows 1..BS, BS+1..2BS, ...) so that the top
+    domain, not the bottom one, shrinks as the columns advance.  Semi- and
+    Fully-Parallel differ only in the kernel family (TS or TT, Sec. 2.1).
+    Emission order as PlasmaTree: the flat trees of a column, then its
+    merges."""
+    _check(p, q)
+    if bs < 1 or bs > p:
+        raise ValueError("BS must be in [1, p]")
+    out = []
+    for k in range(1, min(p, q) + 1):
+        heads = [k] + [h for h in range(bs + 1, p + 1, bs) if h > k]
+        for n, h in enumerate(heads):
+            end = heads[n + 1] - 1 if n + 1 < len(heads) else p
+            for i in range(h + 1, end + 1):
+                out.append((i, h, k))
+        nd = len(heads)
+        half = 1
+        while half < nd:
+            for d in range(half, nd, 2 * half):
+                out.append((heads[d], heads[d - half], k))
+            half *= 2
+    return out
+
+
 def elim_list(p, q, tree, bs=1):
     """Dispatch by tree id (FLAT and SAMEH_KUCK give the same list)."""
     if tree in (FLAT, SAMEH_KUCK):
@@ -188,6 +218,8 @@ def elim_list(p, q, tree, bs=1):
         return greedy_tree(p, q)
     if tree == PLASMA:
         return plasma_tree(p, q, bs)
+    if tree == HADRI:
+        return hadri_tree(p, q, bs)
     if tree in (ASAP, GRASAP):
         from . import dynamic  # the run-time pairings (their own module)
         return dynamic.asap(p, q) if tree == ASAP else dynamic.grasap(p, q, bs)

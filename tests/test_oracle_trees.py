@@ -219,3 +219,51 @@ def test_dag_edges_respect_emission_order_and_tiles():
                 for t, ps in enumerate(preds):
                     assert all(d < t for d in ps)
                     assert len(ps) <= 3
+
+
+# ---- Hadri et al.'s Semi/Fully-Parallel trees (Sec. 4) ---------------------
+# The paper prints no numbers for these trees (they ran no better than
+# PlasmaTree, Sec. 4), so their critical paths are unpinned; what Sec. 4
+# states is pinned: PlasmaTree's flat domains and binary merge, with the
+# domains fixed so that the top one shrinks.
+
+def test_hadri_identities():
+    for p in range(1, 20):
+        for q in range(1, p + 1):
+            assert trees.hadri_tree(p, q, 1) == trees.binary_tree(p, q)
+            assert trees.hadri_tree(p, q, p) == trees.flat_tree(p, q)
+            assert trees.elim_list(p, q, trees.HADRI, 3 if p >= 3 else 1) == trees.hadri_tree(p, q, 3 if p >= 3 else 1)
+
+
+def test_hadri_top_domain_shrinks():
+    for p in range(2, 24):
+        for bs in range(1, p + 1):
+            lst = trees.hadri_tree(p, p, bs)
+            for k in range(1, p + 1):
+                col = [e for e in lst if e[2] == k]
+                # domains: the fixed blocks of BS rows that meet rows k..p; the
+                # top one is cut at row k, the others are whole (or cut at p)
+                blocks = sorted({(r - 1) // bs for r in range(k, p + 1)})
+                heads = [max(k, b * bs + 1) for b in blocks]
+                assert heads[0] == k and all((h - 1) % bs == 0 for h in heads[1:])
+                flat = [(i, piv) for (i, piv, _) in col if (i - 1) // bs == (piv - 1) // bs]
+                merge = [(i, piv) for (i, piv, _) in col if (i - 1) // bs != (piv - 1) // bs]
+                for i, piv in flat:  # each domain is a flat tree rooted at its head
+                    assert piv == heads[blocks.index((i - 1) // bs)], (p, bs, k, i, piv)
+                assert sorted(i for i, _ in merge) == heads[1:], (p, bs, k)
+                top = [i for i, piv in flat if piv == k]
+                assert len(top) == min(p, (blocks[0] + 1) * bs) - k
+                # where the boundaries coincide with row k, PlasmaTree's column
+                if (k - 1) % bs == 0:
+                    assert col == [e for e in trees.plasma_tree(p, p, bs) if e[2] == k]
+
+
+def test_hadri_valid_and_total_work():
+    for p in range(1, 16):
+        for q in range(1, p + 1):
+            for bs in range(1, p + 1):
+                lst = trees.hadri_tree(p, q, bs)
+                assert trees.validate(p, q, lst) == []
+                for kern in (TT, TS):
+                    tasks, _ = dag.build_tasks(p, q, lst, kern)
+                    assert dag.total_work_units(tasks) == 6 * p * q * q - 2 * q ** 3
