@@ -58,8 +58,12 @@ typedef enum {
   TQR_TREE_GREEDY = 4,
   TQR_TREE_PLASMA = 5,     /* needs bs in [1, p] (domain size)             */
   TQR_TREE_ASAP = 6,       /* run-time pairing of the tiled model (Sec. 3.2) */
-  TQR_TREE_GRASAP = 7      /* Greedy for the first q - bs columns, ASAP for
+  TQR_TREE_GRASAP = 7,     /* Greedy for the first q - bs columns, ASAP for
                               the last bs (bs in [0, q]; Sec. 3.2)         */
+  TQR_TREE_HADRI = 8       /* Hadri et al.'s Semi-Parallel (TS kernels) /
+                              Fully-Parallel (TT) trees: PlasmaTree with the
+                              domains fixed at rows 1..bs, bs+1..2 bs, ...,
+                              so the top domain shrinks (Sec. 4); bs in [1, p] */
 } tqr_tree;
 
 /* Kernel family (Sec. 2.1): TT = triangle on top of triangle (Algorithm 3),
@@ -82,8 +86,8 @@ typedef struct {
   int32_t nb;       /* tile size: 32, 64, 128 or 256 (512: TQR_EUNSUPPORTED) */
   int32_t ib;       /* inner block size: 0 = default (32); must be 32      */
   int32_t tree;     /* tqr_tree                                            */
-  int32_t bs;       /* PlasmaTree domain size; GRASAP: ASAP columns k;
-                       ignored for other trees                             */
+  int32_t bs;       /* PlasmaTree / Hadri domain size; GRASAP: ASAP columns
+                       k; ignored for other trees                          */
   int32_t kernels;  /* tqr_kernels                                         */
   int32_t upd;      /* tqr_update_prec                                     */
 } tqr_opts;

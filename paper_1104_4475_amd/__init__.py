@@ -9,7 +9,7 @@ the factorization runs in the library's kernels; there is no fallback.
 """
 
 from ._lib import (  # noqa: F401
-    TREE_FLAT, TREE_SAMEH_KUCK, TREE_BINARY, TREE_FIBONACCI, TREE_GREEDY, TREE_PLASMA, TREE_ASAP, TREE_GRASAP,
+    TREE_FLAT, TREE_SAMEH_KUCK, TREE_BINARY, TREE_FIBONACCI, TREE_GREEDY, TREE_PLASMA, TREE_ASAP, TREE_GRASAP, TREE_HADRI,
     KERN_DEFAULT, KERN_TT, KERN_TS, UPD_F64, UPD_F32, UPD_BF16,
     TQR_OK, TQR_EINVAL, TQR_ENOMEM, TQR_EHIP, TQR_ENOTCONV, TQR_EUNSUPPORTED, TQR_EEXEC,
     TiledQRError, lib, lib_path, Opts, RefineOpts, RefineInfo,

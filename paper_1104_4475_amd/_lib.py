@@ -9,7 +9,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(HERE, "libtiledqr.so")
 
-TREE_FLAT, TREE_SAMEH_KUCK, TREE_BINARY, TREE_FIBONACCI, TREE_GREEDY, TREE_PLASMA, TREE_ASAP, TREE_GRASAP = range(8)
+TREE_FLAT, TREE_SAMEH_KUCK, TREE_BINARY, TREE_FIBONACCI, TREE_GREEDY, TREE_PLASMA, TREE_ASAP, TREE_GRASAP, TREE_HADRI = \
+    range(9)
 KERN_DEFAULT, KERN_TT, KERN_TS = 0, 1, 2
 UPD_F64, UPD_F32, UPD_BF16 = 0, 1, 2
 TQR_OK, TQR_EINVAL, TQR_ENOMEM, TQR_EHIP, TQR_ENOTCONV, TQR_EUNSUPPORTED, TQR_EEXEC = 0, -1, -2, -3, -4, -5, -6

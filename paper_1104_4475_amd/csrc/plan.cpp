@@ -21,8 +21,8 @@ namespace tqr {
 
 bool valid_shape(int p, int q, int tree, int bs) {
   if (q < 1 || p < q) return false;
-  if (tree < T_FLAT || tree > T_GRASAP) return false;
-  if (tree == T_PLASMA && (bs < 1 || bs > p)) return false;
+  if (tree < T_FLAT || tree > T_HADRI) return false;
+  if ((tree == T_PLASMA || tree == T_HADRI) && (bs < 1 || bs > p)) return false;
   if (tree == T_GRASAP && (bs < 0 || bs > q)) return false;
   return true;
 }
@@ -114,6 +114,27 @@ void plasma(int p, int q, int bs, std::vector<Elim>& out) {
     for (int h : heads)
       for (int i = h + 1; i <= std::min(h + bs - 1, p); ++i) out.push_back({i, h, k});
     const int nd = static_cast<int>(heads.size());
+    for (int stride = 1; stride < nd; stride <<= 1)
+      for (int d = stride; d < nd; d += 2 * stride) out.push_back({heads[d], heads[d - stride], k});
+  }
+}
+
+// Hadri et al.'s Semi-Parallel (TS) / Fully-Parallel (TT) tile CAQR trees as
+// Sec. 4 describes them: PlasmaTree's flat domains of BS rows and binary
+// merge of the domain heads, but with the domains fixed at rows 1..BS,
+// BS+1..2BS, ..., so the top domain shrinks as the columns advance.
+void hadri(int p, int q, int bs, std::vector<Elim>& out) {
+  const int kmax = std::min(p, q);
+  std::vector<int> heads;
+  for (int k = 1; k <= kmax; ++k) {
+    heads.assign(1, k);
+    for (int h = bs + 1; h <= p; h += bs)
+      if (h > k) heads.push_back(h);
+    const int nd = static_cast<int>(heads.size());
+    for (int d = 0; d < nd; ++d) {
+      const int end = (d + 1 < nd) ? heads[d + 1] - 1 : p;
+      for (int i = heads[d] + 1; i <= end; ++i) out.push_back({i, heads[d], k});
+    }
     for (int stride = 1; stride < nd; stride <<= 1)
       for (int d = stride; d < nd; d += 2 * stride) out.push_back({heads[d], heads[d - stride], k});
   }
@@ -235,6 +256,7 @@ bool make_elims(int p, int q, int tree, int bs, std::vector<Elim>& out) {
     case T_PLASMA: plasma(p, q, bs, out); break;
     case T_ASAP: dynamic_pairs(p, q, std::min(p, q), out); break;
     case T_GRASAP: dynamic_pairs(p, q, bs, out); break;
+    case T_HADRI: hadri(p, q, bs, out); break;
     default: return false;
   }
   return true;

@@ -9,7 +9,8 @@ namespace tqr {
 
 enum Kind : int32_t { K_GEQRT = 0, K_UNMQR = 1, K_TSQRT = 2, K_TSMQR = 3, K_TTQRT = 4, K_TTMQR = 5 };
 enum Tree : int32_t {
-  T_FLAT = 0, T_SAMEH_KUCK = 1, T_BINARY = 2, T_FIBONACCI = 3, T_GREEDY = 4, T_PLASMA = 5, T_ASAP = 6, T_GRASAP = 7
+  T_FLAT = 0, T_SAMEH_KUCK = 1, T_BINARY = 2, T_FIBONACCI = 3, T_GREEDY = 4, T_PLASMA = 5, T_ASAP = 6, T_GRASAP = 7,
+  T_HADRI = 8
 };
 enum Family : int32_t { F_DEFAULT = 0, F_TT = 1, F_TS = 2 };
 

@@ -79,6 +79,8 @@ SMALL = [
     # that pipeline along a pivot: TS leaves, TT merges)
     (1024, 512, 256, trees.PLASMA, 2, dag.KERN_TS),
     (768, 768, 128, trees.GREEDY, 1, dag.KERN_TS),
+    (1024, 768, 256, trees.ASAP, 1, dag.KERN_TT),
+    (1280, 768, 256, trees.HADRI, 2, dag.KERN_TS),
 ]
 
 
@@ -95,7 +97,10 @@ def test_small_shapes_match_oracle(torch_cuda, case):
 
 C1 = [(trees.GREEDY, 1, dag.KERN_TT), (trees.FLAT, 1, dag.KERN_TS), (trees.SAMEH_KUCK, 1, dag.KERN_TT),
       (trees.BINARY, 1, dag.KERN_TT), (trees.FIBONACCI, 1, dag.KERN_TT), (trees.PLASMA, 2, dag.KERN_TT),
-      (trees.PLASMA, 3, dag.KERN_TS), (trees.GREEDY, 1, dag.KERN_TS)]
+      (trees.PLASMA, 3, dag.KERN_TS), (trees.GREEDY, 1, dag.KERN_TS),
+      # run-time pairings (Sec. 3.2) and Hadri's Semi/Fully-Parallel trees (Sec. 4)
+      (trees.ASAP, 1, dag.KERN_TT), (trees.GRASAP, 2, dag.KERN_TT), (trees.HADRI, 3, dag.KERN_TS),
+      (trees.HADRI, 3, dag.KERN_TT)]
 
 
 @pytest.mark.parametrize("tree,bs,kern", C1)

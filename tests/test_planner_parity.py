@@ -33,11 +33,13 @@ def test_lists_identical(p, q):
     for bs in sorted(b for b in {1, 2, 3, max(1, p // 2), p} if b <= p):
         want = np.array(trees.plasma_tree(p, q, bs), dtype=np.int32).reshape(-1, 3)
         assert np.array_equal(tqr.elim_list(p, q, tqr.TREE_PLASMA, bs), want), (p, q, bs)
+        want = np.array(trees.hadri_tree(p, q, bs), dtype=np.int32).reshape(-1, 3)
+        assert np.array_equal(tqr.elim_list(p, q, tqr.TREE_HADRI, bs), want), (p, q, bs)
 
 
 @pytest.mark.parametrize("p,q", _cases())
 def test_schedules_identical(p, q):
-    for t in TREES + [trees.PLASMA]:
+    for t in TREES + [trees.PLASMA, trees.HADRI]:
         for kern in (dag.KERN_DEFAULT, dag.KERN_TT, dag.KERN_TS):
             bs = max(1, p // 3)
             rows, cp = dag.schedule(p, q, t, bs, kern)
@@ -76,7 +78,7 @@ def test_table5_best_bs_all_q():
 
 def test_invalid_arguments_rejected():
     for args in ((3, 4, tqr.TREE_GREEDY, 1), (0, 0, tqr.TREE_GREEDY, 1), (5, 2, 9, 1), (5, 2, tqr.TREE_PLASMA, 0),
-                 (5, 2, tqr.TREE_PLASMA, 6)):
+                 (5, 2, tqr.TREE_PLASMA, 6), (5, 2, tqr.TREE_HADRI, 0), (5, 2, tqr.TREE_HADRI, 6)):
         with pytest.raises(tqr.TiledQRError):
             tqr.elim_list(*args)
 
