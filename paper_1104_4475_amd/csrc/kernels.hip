@@ -820,10 +820,12 @@ __device__ __forceinline__ void img_dma(const unsigned char* img, unsigned char*
   using I = Img<NB, P>;
   const auto r = rsrc_b(img, I::BYTES);
   const int lane = lane_id(), w = wave_id();
+  // Every wave issues the same number of transfers (the last KB may be
+  // moved twice, with the same data), so the count is known at compile time.
 #pragma unroll
   for (int j0 = 0; j0 < I::NKB; j0 += NWAVES) {
-    const int j = j0 + w;
-    if (j < I::NKB) lds_load16(r, slot + 1024 * j, 1024 * j + 16 * lane);
+    const int j = (j0 + w < I::NKB) ? j0 + w : I::NKB - 1;
+    lds_load16(r, slot + 1024 * j, 1024 * j + 16 * lane);
   }
 }
 
@@ -854,9 +856,9 @@ __device__ __forceinline__ void store_strip_lp(const d4 (&acc)[NB / 16], double*
 
 // Block-by-block following of streamed predecessors (the planner's pdep and
 // sdep edges).  A panel block publishes its completion flag (epoch); a wide
-// update publishes 64 epoch + b + 1 in its progress word once its block b is
-// stored: C1 rows b ib .. b ib + ib - 1 (pair updates) or rows up to
-// b ib + ib - 1 of its tile (UNMQR) are then final.
+// pair update publishes 64 epoch + b + 1 in its progress word once its block
+// b is stored (its C1 rows b ib .. b ib + ib - 1 are then final), a wide
+// UNMQR 64 epoch + nb / ib once all its rows are stored.
 struct StreamCtl {
   const int32_t* flags;  // completion flags
   const int32_t* prog;   // progress words
@@ -892,12 +894,6 @@ __device__ __forceinline__ void wait_panel_block(const StreamCtl& c, int b) {
     wait_word(c.flags + c.pblk[b], [e](int v) { return v == e; }, c);
   }
 }
-__device__ __forceinline__ bool c1_ready(const StreamCtl& c, int b) {
-  if (c.sdep < 0) return true;
-  const int v = __builtin_amdgcn_readfirstlane(
-      __hip_atomic_load(const_cast<int32_t*>(c.prog + c.sdep), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  return v >= 64 * c.epoch + b + 1;
-}
 __device__ __forceinline__ void wait_c1(const StreamCtl& c, int b) {
   if (c.sdep >= 0) {
     const int need = 64 * c.epoch + b + 1;
@@ -923,33 +919,37 @@ __device__ __forceinline__ void wide_update_task(const unsigned char* img, doubl
   double* C1g = PAIR ? C1 + colo : nullptr;
   // Three LDS slots: block b is read from slot b % 3 while the image of
   // block b + 2 lands in slot (b + 2) % 3, which block b - 1 read before the
-  // barrier that ended it.
+  // barrier that ended it.  Streamed predecessors are polled only where this
+  // wave has no memory access in flight (a poll waits for all of them): at
+  // the start, and at the end of each block, for what the next block starts
+  // with (the image two blocks ahead, the next C1 rows).  A block issues its
+  // C1 rows first and the image copy second, so the wait for the C1 rows
+  // after the first contraction leaves the copy in flight (the last two
+  // blocks copy nothing: a separate instance of the block body, so that the
+  // count of transfers in flight is known at compile time).
   wait_panel_block(sc, 0);
+  if (NBLK > 1) wait_panel_block(sc, 1);
+  if (NBLK > 2) wait_panel_block(sc, 2);
+  if constexpr (PAIR) wait_c1(sc, 0);
+  d4 c1v[2] = {zero4(), zero4()};
+  if constexpr (PAIR) load_c1_lp<NB>(c1v, C1g, 0, true);
   img_dma<NB, P>(img, lds);
-  if (NBLK > 1) {
-    wait_panel_block(sc, 1);
-    img_dma<NB, P>(img + I::BYTES, lds + SLOT);
-  }
+  if (NBLK > 1) img_dma<NB, P>(img + I::BYTES, lds + SLOT);
   d4 acc[NJ];
   load_strip_lp<NB>(acc, C2g);
-  d4 c1v[2] = {zero4(), zero4()};
-  if constexpr (PAIR) {
-    wait_c1(sc, 0);
-    load_c1_lp<NB>(c1v, C1g, 0, true);
-  }
   wait_vm();
   __syncthreads();
   int scur = 0;
-  bool c1_late = false;
-#pragma unroll 1
-  for (int b = 0; b < NBLK; ++b) {
+  auto block = [&](int b, auto copy_tag) __attribute__((always_inline)) {
+    constexpr bool COPY = decltype(copy_tag)::value;
     const int c0 = b * IB;
     const unsigned char* cur = lds + scur * SLOT;
-    if (b + 2 < NBLK) {
-      wait_panel_block(sc, b + 2);
-      img_dma<NB, P>(img + static_cast<size_t>(b + 2) * I::BYTES, lds + ((scur == 0) ? 2 : scur - 1) * SLOT);
-    }
+    unsigned char* nxt = lds + ((scur == 0) ? 2 : scur - 1) * SLOT;
     scur = (scur == 2) ? 0 : scur + 1;
+    if constexpr (PAIR) {
+      if (b > 0) load_c1_lp<NB>(c1v, C1g, c0, true);
+    }
+    if constexpr (COPY) img_dma<NB, P>(img + static_cast<size_t>(b + 2) * I::BYTES, nxt);
     const int rb_lo = (VAR == V_UNM) ? (c0 >> 4) : 0;
     const int rb_hi = (VAR == V_TT) ? ((c0 + IB) >> 4) : NJ;
     // W = V^T C2 (+ C1 rows c0 .. c0 + 31): w[mb] holds positions
@@ -1029,16 +1029,6 @@ __device__ __forceinline__ void wide_update_task(const unsigned char* img, doubl
         gst2(c1r, off + 64,
              d2{c1v[mb][2] - static_cast<double>(wt[mb][2]), c1v[mb][3] - static_cast<double>(wt[mb][3])});
       }
-      // The next block's C1 rows (not touched by this block); their latency
-      // overlaps the second contraction when the C1 writer followed (if any)
-      // is already past that block, else they are fetched after it.
-      c1_late = false;
-      if (b + 1 < NBLK) {
-        if (c1_ready(sc, b + 1))
-          load_c1_lp<NB>(c1v, C1g, c0 + IB, true);
-        else
-          c1_late = true;
-      }
     }
     // C2 -= V W'.
     if constexpr (P == P_F32) {
@@ -1084,32 +1074,34 @@ __device__ __forceinline__ void wide_update_task(const unsigned char* img, doubl
         for (int r = 0; r < 4; ++r) acc[rb][r] -= static_cast<double>(d[r]);
       }
     }
-    if constexpr (VAR == V_UNM) {
-      // Rows c0 .. c0 + 31 are final (later blocks touch rows >= c0 + 32).
-      const auto r = rsrc(C2g, 16 * NB * 8);
-#pragma unroll
-      for (int rb = 0; rb < NJ; ++rb) {
-        if ((rb >> 1) != b) continue;
-        const int off = (n * NB + rb * 16 + 2 * g) * 8;
-        gst2(r, off, d2{acc[rb][0], acc[rb][1]});
-        gst2(r, off + 64, d2{acc[rb][2], acc[rb][3]});
-      }
-    }
-    if constexpr (PAIR) {
-      if (c1_late) {
-        wait_c1(sc, b + 1);
-        load_c1_lp<NB>(c1v, C1g, c0 + IB, true);
-      }
-    }
     // The image of block b + 1 (issued a block ago) has landed in every
     // wave's part of its slot, and this block's stores are complete, before
-    // the barrier publishes both.
+    // the barrier publishes both; then the streamed predecessors are far
+    // enough for the next block.
+    wait_vm();
+    if (b + 3 < NBLK) wait_panel_block(sc, b + 3);
+    if constexpr (PAIR) {
+      if (b + 1 < NBLK) wait_c1(sc, b + 1);
+    }
+    __syncthreads();
+    if constexpr (PAIR) {
+      if (sc.self && threadIdx.x == 0)
+        __hip_atomic_store(sc.self, 64 * sc.epoch + b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  };
+#pragma unroll 1
+  for (int b = 0; b + 2 < NBLK; ++b) block(b, std::true_type{});
+#pragma unroll 1
+  for (int b = NBLK > 2 ? NBLK - 2 : 0; b < NBLK; ++b) block(b, std::false_type{});
+  store_strip_lp<NB>(acc, C2g);
+  if constexpr (!PAIR) {
+    // An UNMQR keeps its rows in registers to the end: its followers see all
+    // of them at once.
     wait_vm();
     __syncthreads();
     if (sc.self && threadIdx.x == 0)
-      __hip_atomic_store(sc.self, 64 * sc.epoch + b + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(sc.self, 64 * sc.epoch + NBLK, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
-  if constexpr (VAR != V_UNM) store_strip_lp<NB>(acc, C2g);
 }
 
 // ---------------------------------------------------------------------------
