@@ -32,7 +32,8 @@ import time
 
 METRIC = "tiled-QR GFLOP/s & % MFMA peak: mixed+refined vs FP64 at equal LS accuracy"
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
-TREES = {"flat": 0, "sameh-kuck": 1, "binary": 2, "fibonacci": 3, "greedy": 4, "plasma": 5}
+HBM_TBPS = 8.0
+TREES = {"flat": 0, "sameh-kuck": 1, "binary": 2, "fibonacci": 3, "greedy": 4, "plasma": 5, "asap": 6, "grasap": 7, "hadri": 8}
 UPD = {"f64": 0, "f32": 1, "bf16": 2}
 KERNS = {"default": 0, "tt": 1, "ts": 2}
 # Candidates of the bench's exhaustive autotuner: (tree, BS, kernel family).
@@ -40,10 +41,17 @@ KERNS = {"default": 0, "tt": 1, "ts": 2}
 # the earliest in this list wins, so that equivalent trees do not flip from
 # run to run.
 TUNE_CANDIDATES = [("plasma", 16, "ts"), ("flat", 1, "ts"), ("plasma", 8, "ts"), ("plasma", 32, "ts"),
-                   ("greedy", 1, "tt"), ("greedy", 1, "ts"), ("fibonacci", 1, "ts")]
+                   ("greedy", 1, "tt"), ("greedy", 1, "ts"), ("fibonacci", 1, "ts"), ("asap", 1, "ts")]
 TUNE_TIE = 0.01
 # Table 1 weights by task kind (GEQRT, UNMQR, TSQRT, TSMQR, TTQRT, TTMQR).
 UNITS = (4, 6, 6, 12, 2, 6)
+# Algorithmic HBM bytes per task in FP64 tiles (nb^2 * 8 bytes), each operand
+# read once and each result written once: GEQRT reads and writes a tile;
+# UNMQR reads half a tile of reflectors and reads and writes its target;
+# TSQRT reads and writes two tiles; TSMQR reads a tile of reflectors and two
+# targets and writes the targets; TTQRT reads and writes two triangles;
+# TTMQR reads a triangle of reflectors and two targets, writes the targets.
+TILE_RW = (2.0, 2.5, 4.0, 5.0, 2.0, 4.5)
 # HBM bytes per launch of the executor from rocprofv3 FETCH_SIZE + WRITE_SIZE
 # (calibrated by a plain copy; profiles/hbm_traffic_square10240_nb256.md),
 # keyed by (workload, update precision, tree, BS, kernels, nb) and valid for
@@ -79,6 +87,8 @@ def parse():
     ap.add_argument("--nrhs", type=int, default=4)
     ap.add_argument("--tol", type=float, default=1e-12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the other update precision and the condition-number sweep")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 256 MiB device copy first (HBM counter calibration under rocprofv3 --pmc)")
     return ap.parse_args()
@@ -98,26 +108,40 @@ def update_flop_fraction(p, q, tree, bs, kern):
     return sum(upd) / sum(units)
 
 
+def algorithmic_bytes(p, q, nb, tree, bs, kern):
+    """HBM bytes of one factorization: TILE_RW tiles per task of the task list
+    of (tree, BS, kernel family), FP64 tiles of nb^2 doubles."""
+    from paper_1104_4475_amd import _lib
+    tasks, _ = _lib.schedule(p, q, tree, bs, kern)
+    return sum(TILE_RW[k] for k in tasks[:, 0]) * nb * nb * 8.0
+
+
 def cpu_baseline(nb, tree, bs, kern, kappa):
     """The FP64 oracle (plain NumPy tiled QR) on a bounded sample of the same
     workload: the conditioned matrix at 1792 x 1792 (p = q = 7 tiles of the
-    same nb), BLAS limited to one thread."""
+    same nb), with BLAS on all host cores of this process, and once more on
+    one thread."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     import tqr_inputs
     from oracle import tiled
     n = 7 * nb
-    bs = min(bs, 7)  # PlasmaTree's domain size is at most p = 7 in the sample
+    bs = min(bs, 7)  # PlasmaTree's domain size (GRASAP's k) is at most 7 in the sample
     A = tqr_inputs.conditioned(n, kappa, 102, 103)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        tiled.tiled_qr(A, nb, tree, bs, kern)
-        dt = time.perf_counter() - t0
-    return {"value": flops(n, n) / dt / 1e9, "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+    cores = len(os.sched_getaffinity(0))
+    out = {}
+    for threads in (cores, 1):
+        with threadpool_limits(limits=threads):
+            t0 = time.perf_counter()
+            tiled.tiled_qr(A, nb, tree, bs, kern)
+            out[threads] = time.perf_counter() - t0
+    dt = out[cores]
+    return {"value": flops(n, n) / dt / 1e9, "unit": "GFLOP/s", "cores": cores, "kind": "oracle",
             "sample": "oracle tiled QR of a %dx%d conditioned matrix (kappa %g), nb=%d, same tree (BS %d) and "
-                      "kernels, 1 BLAS thread, %.1f s" % (n, n, kappa, nb, bs, dt),
-            "seconds": dt, "host_cpus": len(os.sched_getaffinity(0))}
+                      "kernels, %d BLAS threads, %.1f s" % (n, n, kappa, nb, bs, cores, dt),
+            "seconds": dt, "value_1_thread": flops(n, n) / out[1] / 1e9, "seconds_1_thread": out[1],
+            "host_cpus": cores}
 
 
 def main():
@@ -135,9 +159,13 @@ def main():
 
     dev = "cuda"
     nb, nrhs = args.nb, args.nrhs
+
+    def square_matrix(kappa):
+        return tqr_inputs.conditioned_device(10240, kappa, tqr_inputs.SEED_C3, tqr_inputs.SEED_C3 + 1, dev).t()
+
     if args.workload == "square" and args.matrix == "conditioned":
         m = n = 10240
-        A = tqr_inputs.conditioned_device(n, args.kappa, tqr_inputs.SEED_C3, tqr_inputs.SEED_C3 + 1, dev).t()
+        A = square_matrix(args.kappa)
         workload = "square LS %dx%d, kappa %g, nb %d, %d rhs" % (m, n, args.kappa, nb, nrhs)
     elif args.workload == "square":
         m = n = 10240
@@ -150,7 +178,11 @@ def main():
     g = torch.Generator(device=dev)
     g.manual_seed(tqr_inputs.SEED_C3_RHS)
     Xt = torch.randn((nrhs, n), generator=g, dtype=torch.float64, device=dev).t()
-    B = (A @ Xt).t().contiguous().t()
+
+    def rhs(Am):
+        return (Am @ Xt).t().contiguous().t()
+
+    B = rhs(A)
     torch.cuda.synchronize()
     if args.copy_calibration:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -161,11 +193,11 @@ def main():
     p, q = m // nb, n // nb
     F = flops(m, n)
 
-    def step(Fh, tol):
+    def step(Fh, Am, Bm, tol):
         # One step: factorization with Q^T B in the same executor launch, then
         # the triangular solve and (mixed) refinement against A.
-        QtB = Fh.refactor_qtb(A, B)
-        return Fh.lstsq(B, A0=A, tol=tol, QtB=QtB)
+        QtB = Fh.refactor_qtb(Am, Bm)
+        return Fh.lstsq(Bm, A0=Am, tol=tol, QtB=QtB)
 
     def tune(upd, refine):
         """Exhaustive autotuner over TUNE_CANDIDATES: the best of two timed
@@ -178,12 +210,12 @@ def main():
             if bs > p:
                 continue
             Fh = tqr.factor(A, nb, TREES[tname], bs, KERNS[kname], UPD[upd])
-            step(Fh, tol)
+            step(Fh, A, B, tol)
             best = float("inf")
             for _ in range(2):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                step(Fh, tol)
+                step(Fh, A, B, tol)
                 torch.cuda.synchronize()
                 best = min(best, time.perf_counter() - t0)
             Fh.sync()
@@ -192,32 +224,45 @@ def main():
         best = min(t for _, t in table)
         return next(c for c, t in table if t <= best * (1.0 + TUNE_TIE)), table
 
-    def run(upd, refine):
-        choice, table = tune(upd, refine)
+    def measure(upd, refine, choice, Am, Bm, steps, warmup):
         tname, bs, kname = choice
-        Fh = tqr.factor(A, nb, TREES[tname], bs, KERNS[kname], UPD[upd])
+        Fh = tqr.factor(Am, nb, TREES[tname], bs, KERNS[kname], UPD[upd])
         Fh.sync()
         tol = args.tol if refine else 0.0
-        for _ in range(args.warmup):
-            X, info = step(Fh, tol)
+        for _ in range(warmup):
+            X, info = step(Fh, Am, Bm, tol)
         torch.cuda.synchronize()
         times, execs, infos = [], [], []
-        for _ in range(args.steps):
+        for _ in range(steps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            X, info = step(Fh, tol)
+            X, info = step(Fh, Am, Bm, tol)
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             execs.append(Fh.exec_ms())
             infos.append(info)
         Fh.sync()
-        r = B - A @ X
+        r = Bm - Am @ X
         eta = (torch.linalg.norm(r, dim=0) /
-               (torch.linalg.norm(A) * torch.linalg.norm(X, dim=0) + torch.linalg.norm(B, dim=0))).max().item()
+               (torch.linalg.norm(Am) * torch.linalg.norm(X, dim=0) + torch.linalg.norm(Bm, dim=0))).max().item()
+        del Fh
         return {"ms_per_step": 1e3 * sum(times) / len(times), "exec_ms": sum(execs) / len(execs),
                 "gflops": F / (sum(times) / len(times)) / 1e9, "backward_err": eta,
                 "refine_iters": infos[-1]["iters"], "converged": infos[-1]["converged"], "X": X,
-                "choice": choice, "tune": table}
+                "choice": choice}
+
+    def run(upd, refine):
+        choice, table = tune(upd, refine)
+        res = measure(upd, refine, choice, A, B, args.steps, args.warmup)
+        res["tune"] = table
+        return res
+
+    def peak_for(upd, choice):
+        if upd == "f64":
+            return PEAK_TFLOPS["f64"]
+        tname, bs, kname = choice
+        fu = update_flop_fraction(p, q, TREES[tname], bs, KERNS[kname])
+        return 1.0 / (fu / PEAK_TFLOPS[upd] + (1.0 - fu) / PEAK_TFLOPS["f64"])
 
     fp64 = run("f64", refine=False)
     main_res = fp64 if args.upd == "f64" else run(args.upd, refine=True)
@@ -226,16 +271,29 @@ def main():
     # Dominant kernel: the executor (all tile kernels of the factorization).
     exec_s = main_res["exec_ms"] / 1e3
     tname, bs, kname = main_res["choice"]
-    if args.upd == "f64":
-        peak = PEAK_TFLOPS["f64"]
-    else:
-        fu = update_flop_fraction(p, q, TREES[tname], bs, KERNS[kname])
-        peak = 1.0 / (fu / PEAK_TFLOPS[args.upd] + (1.0 - fu) / PEAK_TFLOPS["f64"])
+    peak = peak_for(args.upd, main_res["choice"])
     achieved = F / exec_s / 1e12
+    alg_bytes = algorithmic_bytes(p, q, nb, TREES[tname], bs, KERNS[kname])
     traffic = None
     key = (args.workload, args.upd, tname, bs, kname, nb)
     if key in TRAFFIC and TRAFFIC[key][1] == executor_source_hash():
         traffic = TRAFFIC[key][0]
+    # The floor that binds the executor: compute at the MFMA peak, or HBM
+    # bytes (the measured traffic when it is current, else the algorithmic
+    # bytes) at 8 TB/s.
+    t_mfma = F / (peak * 1e12)
+    t_hbm = (traffic if traffic is not None else alg_bytes) / (HBM_TBPS * 1e12)
+    bound = "hbm" if t_hbm > t_mfma else "mfma"
+    if bound == "mfma":
+        roof = {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4)}
+    else:
+        gbps = alg_bytes / exec_s / 1e9  # algorithmic bytes per launch over its duration
+        roof = {"bound": "hbm", "achieved": round(gbps, 1), "peak": HBM_TBPS * 1e3, "unit": "GB/s",
+                "frac": round(gbps / (HBM_TBPS * 1e3), 4)}
+    roof.update({"traffic": traffic, "algorithmic_bytes": alg_bytes, "floor_ms": {"mfma": round(1e3 * t_mfma, 3),
+                 "hbm": round(1e3 * t_hbm, 3)}, "kernel": "exec_persistent<%d>" % nb,
+                 "kernel_ms": round(main_res["exec_ms"], 3), "tflops": round(achieved, 3)})
     line = {
         "metric": METRIC,
         "value": round(main_res["gflops"], 2),
@@ -252,9 +310,7 @@ def main():
         "config": {"workload": workload, "tree": tname, "bs": bs, "kernels": kname, "nb": nb, "m": m, "n": n,
                    "upd": args.upd, "refine_tol": args.tol if args.upd != "f64" else None,
                    "tuned": args.tree == "auto"},
-        "roofline": {"bound": "mfma", "achieved": round(achieved, 3), "peak": round(peak, 1), "unit": "TFLOP/s",
-                     "frac": round(achieved / peak, 4), "traffic": traffic,
-                     "kernel": "exec_persistent<%d>" % nb, "kernel_ms": round(main_res["exec_ms"], 3)},
+        "roofline": roof,
         "fp64": {"gflops": round(fp64["gflops"], 2), "ms_per_step": round(fp64["ms_per_step"], 3),
                  "exec_ms": round(fp64["exec_ms"], 3), "backward_err": fp64["backward_err"],
                  "tree": "%s bs %d %s" % fp64["choice"],
@@ -267,6 +323,41 @@ def main():
         line["autotune_ms_per_step"] = {"fp64": {"%s bs %d %s" % c: t for c, t in fp64["tune"]}}
         if args.upd != "f64":
             line["autotune_ms_per_step"][args.upd] = {"%s bs %d %s" % c: t for c, t in main_res["tune"]}
+    # The other update precision at the same kappa, tuned the same way.
+    if args.upd in ("f32", "bf16") and not args.no_extra:
+        other = "bf16" if args.upd == "f32" else "f32"
+        o = run(other, refine=True)
+        ofwd = (torch.linalg.norm(o["X"] - fp64["X"]) / torch.linalg.norm(fp64["X"])).item()
+        line[other] = {"gflops": round(o["gflops"], 2), "ms_per_step": round(o["ms_per_step"], 3),
+                       "exec_ms": round(o["exec_ms"], 3), "tree": "%s bs %d %s" % o["choice"],
+                       "speedup_vs_fp64": round(o["gflops"] / fp64["gflops"], 3),
+                       "frac_blended_peak": round(F / (o["exec_ms"] / 1e3) / 1e12 / peak_for(other, o["choice"]), 4),
+                       "backward_err": o["backward_err"], "refine_iters": o["refine_iters"],
+                       "converged": o["converged"], "fwd_diff_vs_fp64": ofwd,
+                       "autotune_ms_per_step": {"%s bs %d %s" % c: t for c, t in o["tune"]}}
+        # Harder conditioning of the square workload: each precision with its
+        # tree from the tuning above, FP64 beside it.
+        if args.workload == "square" and args.matrix == "conditioned":
+            sweep = {}
+            choices = {"f64": fp64["choice"], args.upd: main_res["choice"], other: o["choice"]}
+            del A, B
+            for kappa in (1e6, 1e10):
+                Ak = square_matrix(kappa)
+                Bk = rhs(Ak)
+                ref = measure("f64", False, choices["f64"], Ak, Bk, 2, 1)
+                cell = {"fp64": {"ms_per_step": round(ref["ms_per_step"], 3), "backward_err": ref["backward_err"]}}
+                for u in ("f32", "bf16"):
+                    r = measure(u, True, choices[u], Ak, Bk, 2, 1)
+                    cell[u] = {"ms_per_step": round(r["ms_per_step"], 3), "exec_ms": round(r["exec_ms"], 3),
+                               "speedup_vs_fp64": round(ref["ms_per_step"] / r["ms_per_step"], 3),
+                               "backward_err": r["backward_err"], "refine_iters": r["refine_iters"],
+                               "converged": r["converged"],
+                               "fwd_diff_vs_fp64": (torch.linalg.norm(r["X"] - ref["X"]) /
+                                                    torch.linalg.norm(ref["X"])).item()}
+                sweep["%g" % kappa] = cell
+                del Ak, Bk
+                torch.cuda.empty_cache()
+            line["kappa_sweep"] = sweep
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(nb, TREES[tname], bs, KERNS[kname], args.kappa)
     print(json.dumps(line), flush=True)
