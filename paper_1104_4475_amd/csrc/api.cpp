@@ -154,8 +154,8 @@ int exec_order() {
 void exec_weights(int nb, int upd, double w[6]) {
   static const double table1[6] = {4, 6, 6, 12, 2, 6};
   static const double nb256[3][6] = {{600, 364, 735, 480, 533, 412},
-                                     {610, 300, 770, 430, 560, 396},
-                                     {620, 268, 775, 372, 568, 352}};
+                                     {600, 144, 560, 212, 466, 156},
+                                     {560, 110, 500, 144, 456, 122}};
   static const double nb128[6] = {199, 164, 260, 300, 213, 228};
   const double* src = table1;
   if (nb == 256 && upd >= 0 && upd < 3) src = nb256[upd];
