@@ -112,9 +112,12 @@ int tiledqr_last_hip_error(void);
  * slab (128 columns for FP32 / BF16 updates at nb >= 128) and, for nb >= 128,
  * panel tasks per inner block of ib columns, block b waiting only for block b
  * of the previous panel task on the same triangle (environment
- * TQR_PANEL_SPLIT=0 keeps whole panel tasks).  FP32 / BF16 updates at
- * nb >= 128 also stream their reflectors and C1 rows block by block
- * (tiledqr_exec_plan; TQR_STREAM=0 waits for whole predecessors).
+ * TQR_PANEL_SPLIT=0 keeps whole panel tasks).  A panel block subtask
+ * releases its successors once it has applied its block to the next
+ * block's columns and updates the rest of its tiles after that
+ * (tiledqr_exec_plan; TQR_EARLY=0 releases them only when it ends).
+ * FP32 / BF16 updates at nb >= 128 also stream their reflectors and C1 rows
+ * block by block (TQR_STREAM=0 waits for whole predecessors).
  * Errors: TQR_EINVAL (null pointer, m % nb, n % nb, m < n, nb or ib not
  * valid, bs outside [1, p] for PlasmaTree, lda < m), TQR_EUNSUPPORTED
  * (nb = 512: a valid tile size without kernels here), TQR_ENOMEM,
@@ -174,15 +177,20 @@ int tiledqr_get_trace(tqr_factors* F, int64_t* out, int64_t* n, double* ticks_pe
  * order): sub (host, 10 int32 per subtask, may be NULL) = kind, i, piv, k, j
  * (0-based tiles), slab (column slab of an update, inner block of a panel
  * subtask or -1 for a whole panel task), dep_begin, dep_end, sdep, pdep;
- * deps (host, may be NULL) = the predecessor indices of subtask t that it
- * waits for before it starts, in deps[dep_begin .. dep_end - 1], all smaller
- * than t.  Low-precision updates at nb >= 128 also follow streamed
- * predecessors block by block while they run: sdep (or -1) is the previous
- * writer of a pair update's C1 tile, and pdep (or -1) is the offset in deps
- * of the nb/ib panel block subtasks whose reflectors an update applies
- * (block b of the update waits for the flag of panel block b, and for the
- * C1 writer's progress past its block b).  These are the edges of the DAG
- * of Sec. 2.3 refined to subtasks and inner blocks.  Errors: TQR_EINVAL. */
+ * deps (host, may be NULL) = the predecessor entries of subtask t, in
+ * deps[dep_begin .. dep_end - 1]: the low 28 bits hold a predecessor index
+ * smaller than t.  Bits 28-29 (stage) say when it is waited for: 0 before
+ * the subtask starts; on panel block subtasks that release early, 1 before
+ * the look-ahead update of the next block's columns and 2 before the
+ * update of the rest of the tiles.  Bit 30 (early) asks for the
+ * predecessor's early release instead of its completion.  Low-precision
+ * updates at nb >= 128 also follow streamed predecessors block by block
+ * while they run: sdep (or -1) is the previous writer of a pair update's C1
+ * tile, and pdep (or -1) is the offset in deps of the nb/ib panel block
+ * subtasks whose reflectors an update applies (block b of the update waits
+ * for panel block b, its early release when bit 30 is set, and for the C1
+ * writer's progress past its block b).  These are the edges of the DAG of
+ * Sec. 2.3 refined to subtasks and inner blocks.  Errors: TQR_EINVAL. */
 int tiledqr_exec_plan(const tqr_factors* F, int32_t* sub, int64_t* nsub, int32_t* deps, int64_t* ndeps);
 
 /* X (device, n x nrhs, ldx >= n) <- R^{-1} X (trans 'N') or R^{-T} X (trans

@@ -13,6 +13,10 @@ TREE_FLAT, TREE_SAMEH_KUCK, TREE_BINARY, TREE_FIBONACCI, TREE_GREEDY, TREE_PLASM
     range(9)
 KERN_DEFAULT, KERN_TT, KERN_TS = 0, 1, 2
 UPD_F64, UPD_F32, UPD_BF16 = 0, 1, 2
+# Fields of an executor predecessor entry (tiledqr_exec_plan): index, stage
+# (0 at the start, 1 before the look-ahead, 2 before the rest of the tiles)
+# and the early-release bit.
+DEP_INDEX, DEP_STAGE_SHIFT, DEP_EARLY = (1 << 28) - 1, 28, 1 << 30
 TQR_OK, TQR_EINVAL, TQR_ENOMEM, TQR_EHIP, TQR_ENOTCONV, TQR_EUNSUPPORTED, TQR_EEXEC = 0, -1, -2, -3, -4, -5, -6
 
 if not os.path.exists(lib_path):

@@ -84,7 +84,8 @@ class Factors:
     def exec_plan(self):
         """Executor subtasks of the factorization in dispatch order: int32
         array (n, 10) = kind, i, piv, k, j, slab, dep_begin, dep_end, sdep,
-        pdep, and the int32 predecessor array (tiledqr_exec_plan)."""
+        pdep, and the int32 predecessor entries (index, stage and early bit:
+        _lib.DEP_INDEX, DEP_STAGE_SHIFT, DEP_EARLY; tiledqr_exec_plan)."""
         import numpy as np
         n, nd = ctypes.c_int64(), ctypes.c_int64()
         check(_lib.tiledqr_exec_plan(self.handle, None, ctypes.byref(n), None, ctypes.byref(nd)), "tiledqr_exec_plan")

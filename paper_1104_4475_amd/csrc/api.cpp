@@ -75,14 +75,21 @@ int upload(const ExecPlan& ex, DevPlan& d) {
     if (ex.sub[t].dep_begin < 0 || ex.sub[t].dep_end > static_cast<int32_t>(ex.deps.size()) ||
         ex.sub[t].dep_begin > ex.sub[t].dep_end)
       return TQR_EINVAL;
-    for (int32_t e = ex.sub[t].dep_begin; e < ex.sub[t].dep_end; ++e)
-      if (ex.deps[e] < 0 || ex.deps[e] >= static_cast<int32_t>(t)) return TQR_EINVAL;
+    // Entries waited for inside a subtask (stages 1 and 2) only occur on
+    // panel block subtasks, which are the only ones that wait there.
+    const int kd = ex.sub[t].kind;
+    const bool panel_blk = (kd == tqr::K_GEQRT || kd == tqr::K_TSQRT || kd == tqr::K_TTQRT) && ex.sub[t].slab >= 0;
+    for (int32_t e = ex.sub[t].dep_begin; e < ex.sub[t].dep_end; ++e) {
+      const int32_t d = ex.deps[e];
+      if (d < 0 || tqr::dep_index(d) >= static_cast<int32_t>(t) || tqr::dep_stage(d) == 3) return TQR_EINVAL;
+      if (tqr::dep_stage(d) != 0 && !panel_blk) return TQR_EINVAL;
+    }
     if (ex.sub[t].sdep >= static_cast<int32_t>(t)) return TQR_EINVAL;
     if (ex.sub[t].pdep >= 0) {
       if (ex.sub[t].pdep + ex.pblk > static_cast<int32_t>(ex.deps.size())) return TQR_EINVAL;
       for (int b = 0; b < ex.pblk; ++b) {
         const int32_t d = ex.deps[ex.sub[t].pdep + b];
-        if (d < 0 || d >= static_cast<int32_t>(t)) return TQR_EINVAL;
+        if (d < 0 || tqr::dep_index(d) >= static_cast<int32_t>(t) || tqr::dep_stage(d) != 0) return TQR_EINVAL;
       }
     }
   }
@@ -166,6 +173,17 @@ void exec_weights(int nb, int upd, double w[6]) {
     if (std::sscanf(e, "%lf,%lf,%lf,%lf,%lf,%lf", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 6)
       for (int k = 0; k < 6; ++k) w[k] = v[k];
   }
+}
+
+// Priority bonus of the updates on the column right of their panel (the
+// next panel's column), in the units of exec_weights; TQR_LOOKAHEAD
+// overrides it for diagnostics.
+double lookahead_bonus(int nb, int upd) {
+  (void)nb;
+  (void)upd;
+  double b = 0.0;
+  if (const char* e = std::getenv("TQR_LOOKAHEAD")) b = std::atof(e);
+  return b;
 }
 
 }  // namespace
@@ -435,7 +453,11 @@ int create(const tqr_opts* o, tqr_factors** out, ExecPlan* keep = nullptr) {
   // block (TQR_STREAM=0 waits for whole predecessors instead).
   const char* sv = std::getenv("TQR_STREAM");
   const bool stream = tqr::update_slab(F->nb, o->upd) == tqr::WIDE_SLAB && !(sv && sv[0] == '0');
-  tqr::make_exec_plan(F->plan, nslab, exec_order(), w, ex, pblk, stream);
+  // Panel block subtasks release their successors after their look-ahead
+  // update (TQR_EARLY=0: only when they finish).
+  const char* ev = std::getenv("TQR_EARLY");
+  const bool early = pblk > 1 && !(ev && ev[0] == '0');
+  tqr::make_exec_plan(F->plan, nslab, exec_order(), w, ex, pblk, stream, early, lookahead_bonus(o->nb, o->upd));
   int st = upload(ex, F->exec);
   if (st != TQR_OK) return st;
   if (keep) *keep = ex;
@@ -873,7 +895,7 @@ int tiledqr_refactor_qtb(tqr_factors* F, const double* A, int64_t lda, double* B
     exec_weights(F->nb, F->o.upd, w);
     const int nslab = std::max(1, F->nb / tqr::update_slab(F->nb, F->o.upd));
     ExecPlan ex;
-    tqr::make_factor_apply_plan(F->plan, F->exec_host, nslab, w, 1, 0.1 * w[1], ex);
+    tqr::make_factor_apply_plan(F->plan, F->exec_host, nslab, 1, 0.1 * w[1], ex);
     const int st = upload(ex, F->fused);
     if (st != TQR_OK) return st;
     if (!hip_ok(hipMalloc(&F->Bt16, static_cast<size_t>(F->p) * F->nb * 16 * sizeof(double)))) return TQR_ENOMEM;

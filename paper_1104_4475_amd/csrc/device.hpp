@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "depcode.hpp"
+
 namespace tqr {
 
 constexpr int IB = 32;        // inner block size of every kernel (Sec. 4: ib = 32)

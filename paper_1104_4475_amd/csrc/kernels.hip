@@ -874,24 +874,73 @@ struct StreamCtl {
 // the wait exceeds the executor's time limit or another workgroup has
 // failed, and then sets the error word (the executor stops at its next wait).
 template <class Ok>
-__device__ __forceinline__ void wait_word(const int32_t* w, Ok ok, const StreamCtl& c) {
+__device__ __forceinline__ void wait_until(const int32_t* w, Ok ok, int32_t* err, int64_t spin) {
   const uint64_t t0 = wall_clock64();
   for (;;) {
     const int v = __builtin_amdgcn_readfirstlane(
         __hip_atomic_load(const_cast<int32_t*>(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
     if (ok(v)) return;
-    const int e = __builtin_amdgcn_readfirstlane(__hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    if (e != 0 || static_cast<int64_t>(wall_clock64() - t0) > c.spin) {
-      if (lane_id() == 0) __hip_atomic_store(c.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int e = __builtin_amdgcn_readfirstlane(__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    if (e != 0 || static_cast<int64_t>(wall_clock64() - t0) > spin) {
+      if (lane_id() == 0) __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
     __builtin_amdgcn_s_sleep(1);
   }
 }
+template <class Ok>
+__device__ __forceinline__ void wait_word(const int32_t* w, Ok ok, const StreamCtl& c) {
+  wait_until(w, ok, c.err, c.spin);
+}
+
+// Early release of a panel block subtask (its predecessor entries carry
+// stage fields): the waits before its look-ahead update (stage 1) and
+// before the update of the rest of its tiles (stage 2), and the release
+// after the look-ahead.  on = false for a whole panel task (or the batched
+// executor): no waits and no release.
+struct PanelSync {
+  bool on;
+  const int32_t* deps;
+  int32_t db, de;
+  const int32_t* flags;
+  int32_t* self;  // this subtask's progress word
+  int32_t epoch;
+  int32_t* err;
+  int64_t spin;
+};
+
+// Wave 0 waits for the completion of the stage-st predecessors; the
+// workgroup then meets at a barrier.
+__device__ __forceinline__ void panel_wait(const PanelSync& ps, int st) {
+  if (ps.on && wave_id() == 0) {
+    for (int e = ps.db; e < ps.de; ++e) {
+      const int32_t d = __builtin_amdgcn_readfirstlane(ps.deps[e]);
+      if (dep_stage(d) != st) continue;
+      const int32_t ep = ps.epoch;
+      wait_until(ps.flags + dep_index(d), [ep](int v) { return v == ep; }, ps.err, ps.spin);
+    }
+  }
+  __syncthreads();
+}
+
+// Every store of the subtask so far has completed in every wave before the
+// progress word announces the early release (as for the completion flag).
+__device__ __forceinline__ void panel_release(const PanelSync& ps) {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (ps.on && threadIdx.x == 0)
+    __hip_atomic_store(ps.self, early_word(ps.epoch), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 __device__ __forceinline__ void wait_panel_block(const StreamCtl& c, int b) {
   if (c.pblk) {
-    const int e = c.epoch;
-    wait_word(c.flags + c.pblk[b], [e](int v) { return v == e; }, c);
+    const int32_t d = __builtin_amdgcn_readfirstlane(c.pblk[b]);
+    if (dep_early(d)) {
+      const int need = early_word(c.epoch);
+      wait_word(c.prog + dep_index(d), [need](int v) { return v >= need; }, c);
+    } else {
+      const int e = c.epoch;
+      wait_word(c.flags + dep_index(d), [e](int v) { return v == e; }, c);
+    }
   }
 }
 __device__ __forceinline__ void wait_c1(const StreamCtl& c, int b) {
@@ -1323,7 +1372,8 @@ __device__ __forceinline__ void panel_to_lp(double* Ps, int ldp, int K, double* 
 // The inner blocks c0 = cb, cb + ib, ... < ce are factored (all of them, or
 // one when the planner splits the task into block subtasks).
 template <int NB, int P>
-__device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm, int cb, int ce, unsigned char* img) {
+__device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm, int cb, int ce, unsigned char* img,
+                                           const PanelSync& ps) {
   constexpr int ldp = Smem<NB>::LDP;
   double* Ps = sm + Smem<NB>::PS;
   double* Ts = sm + Smem<NB>::TS;
@@ -1353,25 +1403,37 @@ __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm, int
     if constexpr (P != P_F64) {
       if (nch > 0) panel_to_lp<NB, P>(Ps, ldp, K, Ts);
     }
+    // The rest of the tile in chunks of 16 columns, four at a time.  With
+    // early release: the next block's columns (chunks 0 and 1) first, then
+    // the release, then the rest.
+    const int la = ps.on ? (nch < 2 ? nch : 2) : nch;
 #pragma unroll 1
-    for (int base = 0; base < nch; base += 4) {
-      const int ch = base + gw;
-      const bool active = ch < nch;
-      d4 acc[NB / 32];
-      const d4 none[2] = {zero4(), zero4()};
-      if constexpr (P == P_F64) {
-        double* C = A + (c0 + IB + ch * 16 + (lane & 15)) * NB;
-        if (active) load_cols<NB>(acc, C, c0 / 16, NB / 16);
-        apply_block<NB, V_UNM>(Ps, ldp, Ts, c0, acc, nullptr, none, active, 1, wx);
-        if (active) store_cols<NB>(acc, C, c0 / 16, NB / 16);
-      } else {
-        double* Cg = A + static_cast<size_t>(c0 + IB + ch * 16) * NB;
-        if (active) load_cols_lp<NB>(acc, Cg, c0 / 16, NB / 16);
-        apply_block_lp<NB, V_UNM, P>(reinterpret_cast<const unsigned char*>(Ps), Ts, c0, acc, nullptr, none, active, 1,
-                                     reinterpret_cast<float*>(wx));
-        if (active) store_cols_lp<NB>(acc, Cg, c0 / 16, NB / 16);
+    for (int ph = 0; ph < (ps.on ? 2 : 1); ++ph) {
+      if (ps.on) {
+        if (ph == 1) panel_release(ps);
+        panel_wait(ps, ph + 1);
       }
-      __syncthreads();
+      const int ch1 = ph == 0 ? la : nch;
+#pragma unroll 1
+      for (int base = ph == 0 ? 0 : la; base < ch1; base += 4) {
+        const int ch = base + gw;
+        const bool active = ch < ch1;
+        d4 acc[NB / 32];
+        const d4 none[2] = {zero4(), zero4()};
+        if constexpr (P == P_F64) {
+          double* C = A + (c0 + IB + ch * 16 + (lane & 15)) * NB;
+          if (active) load_cols<NB>(acc, C, c0 / 16, NB / 16);
+          apply_block<NB, V_UNM>(Ps, ldp, Ts, c0, acc, nullptr, none, active, 1, wx);
+          if (active) store_cols<NB>(acc, C, c0 / 16, NB / 16);
+        } else {
+          double* Cg = A + static_cast<size_t>(c0 + IB + ch * 16) * NB;
+          if (active) load_cols_lp<NB>(acc, Cg, c0 / 16, NB / 16);
+          apply_block_lp<NB, V_UNM, P>(reinterpret_cast<const unsigned char*>(Ps), Ts, c0, acc, nullptr, none, active, 1,
+                                       reinterpret_cast<float*>(wx));
+          if (active) store_cols_lp<NB>(acc, Cg, c0 / 16, NB / 16);
+        }
+        __syncthreads();
+      }
     }
     __syncthreads();
   }
@@ -1383,7 +1445,7 @@ __device__ __forceinline__ void geqrt_task(double* A, double* T, double* sm, int
 // Inner blocks cb <= c0 < ce as for geqrt_task.
 template <int NB, int P, int TT>
 __device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T, double* sm, int cb, int ce,
-                                              unsigned char* img) {
+                                              unsigned char* img, const PanelSync& ps) {
   constexpr int tt = TT;
   constexpr int ldp = Smem<NB>::LDP;
   double* Ps = sm + Smem<NB>::PS;
@@ -1423,34 +1485,44 @@ __device__ __forceinline__ void pair_qrt_task(double* R1, double* A2, double* T,
     if constexpr (P != P_F64) {
       if (nch > 0) panel_to_lp<NB, P>(Ps, ldp, K, Ts);
     }
+    // As for geqrt_task: look-ahead chunks first with early release.
+    const int la = ps.on ? (nch < 2 ? nch : 2) : nch;
 #pragma unroll 1
-    for (int base = 0; base < nch; base += 4) {
-      const int ch = base + gw;
-      const bool active = ch < nch;
-      d4 acc[NB / 32], c1v[2];
-      if constexpr (P == P_F64) {
-        const int col = c0 + IB + ch * 16 + (lane & 15);
-        double* C2 = A2 + col * NB;
-        load_c1(c1v, R1 + col * NB, c0, active);
-        if (active) load_cols<NB>(acc, C2, 0, hi);
-        if (tt)
-          apply_block<NB, V_TT>(Ps, ldp, Ts, c0, acc, R1 + col * NB, c1v, active, 1, wx);
-        else
-          apply_block<NB, V_TS>(Ps, ldp, Ts, c0, acc, R1 + col * NB, c1v, active, 1, wx);
-        if (active) store_cols<NB>(acc, C2, 0, hi);
-      } else {
-        const size_t colg = static_cast<size_t>(c0 + IB + ch * 16) * NB;
-        const unsigned char* vl = reinterpret_cast<const unsigned char*>(Ps);
-        float* wxf = reinterpret_cast<float*>(wx);
-        load_c1_lp<NB>(c1v, R1 + colg, c0, active);
-        if (active) load_cols_lp<NB>(acc, A2 + colg, 0, hi);
-        if (tt)
-          apply_block_lp<NB, V_TT, P>(vl, Ts, c0, acc, R1 + colg, c1v, active, 1, wxf);
-        else
-          apply_block_lp<NB, V_TS, P>(vl, Ts, c0, acc, R1 + colg, c1v, active, 1, wxf);
-        if (active) store_cols_lp<NB>(acc, A2 + colg, 0, hi);
+    for (int ph = 0; ph < (ps.on ? 2 : 1); ++ph) {
+      if (ps.on) {
+        if (ph == 1) panel_release(ps);
+        panel_wait(ps, ph + 1);
       }
-      __syncthreads();
+      const int ch1 = ph == 0 ? la : nch;
+#pragma unroll 1
+      for (int base = ph == 0 ? 0 : la; base < ch1; base += 4) {
+        const int ch = base + gw;
+        const bool active = ch < ch1;
+        d4 acc[NB / 32], c1v[2];
+        if constexpr (P == P_F64) {
+          const int col = c0 + IB + ch * 16 + (lane & 15);
+          double* C2 = A2 + col * NB;
+          load_c1(c1v, R1 + col * NB, c0, active);
+          if (active) load_cols<NB>(acc, C2, 0, hi);
+          if (tt)
+            apply_block<NB, V_TT>(Ps, ldp, Ts, c0, acc, R1 + col * NB, c1v, active, 1, wx);
+          else
+            apply_block<NB, V_TS>(Ps, ldp, Ts, c0, acc, R1 + col * NB, c1v, active, 1, wx);
+          if (active) store_cols<NB>(acc, C2, 0, hi);
+        } else {
+          const size_t colg = static_cast<size_t>(c0 + IB + ch * 16) * NB;
+          const unsigned char* vl = reinterpret_cast<const unsigned char*>(Ps);
+          float* wxf = reinterpret_cast<float*>(wx);
+          load_c1_lp<NB>(c1v, R1 + colg, c0, active);
+          if (active) load_cols_lp<NB>(acc, A2 + colg, 0, hi);
+          if (tt)
+            apply_block_lp<NB, V_TT, P>(vl, Ts, c0, acc, R1 + colg, c1v, active, 1, wxf);
+          else
+            apply_block_lp<NB, V_TS, P>(vl, Ts, c0, acc, R1 + colg, c1v, active, 1, wxf);
+          if (active) store_cols_lp<NB>(acc, A2 + colg, 0, hi);
+        }
+        __syncthreads();
+      }
     }
     __syncthreads();
   }
@@ -1768,10 +1840,14 @@ __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, doub
   }
   // Panel subtasks: slab = the inner block to factor, or -1 for all.
   const int cb = s.slab < 0 ? 0 : s.slab * IB, ce = s.slab < 0 ? NB : cb + IB;
+  PanelSync ps{};
+  if ((s.kind == D_GEQRT || s.kind == D_TSQRT || s.kind == D_TTQRT) && s.slab >= 0 && a.prog)
+    ps = PanelSync{true, a.deps, __builtin_amdgcn_readfirstlane(s.dep_begin), __builtin_amdgcn_readfirstlane(s.dep_end),
+                   a.flags, a.prog + t, a.epoch, a.err, a.spin_ticks};
   switch (s.kind) {
     case D_GEQRT:
       geqrt_task<NB, P>(tile_ptr(a, s.i, s.k), tg_ptr(a, s.i, s.k), sm, cb, ce,
-                        kWide ? imgg_ptr<NB, P>(a, s.i, s.k) : nullptr);
+                        kWide ? imgg_ptr<NB, P>(a, s.i, s.k) : nullptr, ps);
       break;
     case D_UNMQR:
       if constexpr (kWide) {
@@ -1785,10 +1861,10 @@ __device__ __forceinline__ void run_sub(const ExecArgs& a, const DevSub& s, doub
     case D_TTQRT:
       if (s.kind == D_TTQRT)
         pair_qrt_task<NB, P, 1>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm, cb, ce,
-                                kWide ? imgp_ptr<NB, P>(a, s.i, s.k) : nullptr);
+                                kWide ? imgp_ptr<NB, P>(a, s.i, s.k) : nullptr, ps);
       else
         pair_qrt_task<NB, P, 0>(tile_ptr(a, s.piv, s.k), tile_ptr(a, s.i, s.k), tp_ptr(a, s.i, s.k), sm, cb, ce,
-                                kWide ? imgp_ptr<NB, P>(a, s.i, s.k) : nullptr);
+                                kWide ? imgp_ptr<NB, P>(a, s.i, s.k) : nullptr, ps);
       break;
     case D_TSMQR:
     case D_TTMQR:
@@ -1846,6 +1922,7 @@ struct LoopCtl {
   const DevSub* sub;
   const int32_t* deps;
   int32_t* flags;
+  const int32_t* prog;  // progress words (early releases), or null
   int32_t* ticket;
   int32_t* err;
   int32_t nsub;
@@ -1854,18 +1931,24 @@ struct LoopCtl {
   int64_t* trace;
 };
 
-// Wave 0 of a workgroup waits until every predecessor of subtask t has
-// published its flag; returns t, or c.nsub after a timeout (which sets
-// *err) or when another workgroup has set *err.
+// Wave 0 of a workgroup waits until every predecessor of subtask t that is
+// due before it starts has published its flag (or, for an early entry, its
+// early release); returns t, or c.nsub after a timeout (which sets *err) or
+// when another workgroup has set *err.
 __device__ __forceinline__ int wait_deps(const LoopCtl& c, int t, int lane) {
   const int db = c.sub[t].dep_begin, de = c.sub[t].dep_end;
   const uint64_t t0 = wall_clock64();
   if (c.trace && lane == 0) c.trace[4 * static_cast<int64_t>(t)] = static_cast<int64_t>(t0);
   for (int e = db; e < de && t < c.nsub; ++e) {
-    int32_t* f = c.flags + c.deps[e];
+    const int32_t d = __builtin_amdgcn_readfirstlane(c.deps[e]);
+    if (dep_stage(d) != 0) continue;  // waited for inside the panel subtask
+    const bool early = dep_early(d) && c.prog;
+    const int32_t* f = (early ? c.prog : c.flags) + dep_index(d);
+    const int32_t need = early ? early_word(c.epoch) : c.epoch;
     for (;;) {
-      const int v = __builtin_amdgcn_readfirstlane(__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-      if (v == c.epoch) break;
+      const int v = __builtin_amdgcn_readfirstlane(
+          __hip_atomic_load(const_cast<int32_t*>(f), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      if (early ? v >= need : v == need) break;
       const int err = __builtin_amdgcn_readfirstlane(
           __hip_atomic_load(c.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
       if (err != 0 || static_cast<int64_t>(wall_clock64() - t0) > c.spin_ticks) {
@@ -1968,7 +2051,7 @@ __device__ __forceinline__ void exec_loop_pre(const LoopCtl& c, Pre pre, Run run
 template <int NB, int P>
 __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
   __shared__ double sm[Smem<NB>::TOTAL];
-  const LoopCtl c{a.sub, a.deps, a.flags, a.ticket, a.err, a.nsub, a.epoch, a.spin_ticks, a.trace};
+  const LoopCtl c{a.sub, a.deps, a.flags, a.prog, a.ticket, a.err, a.nsub, a.epoch, a.spin_ticks, a.trace};
   exec_loop(c, [&](int t) {
     if (a.debug & 1) {
       for (int e = threadIdx.x; e < Smem<NB>::TOTAL; e += NTHREADS) sm[e] = 0.0;
@@ -1983,7 +2066,7 @@ __global__ __launch_bounds__(NTHREADS) void exec_persistent(ExecArgs a) {
 template <int NB>
 __global__ __launch_bounds__(NTHREADS) void exec_apply(ExecArgs a) {
   __shared__ double sm[Smem<NB>::TOTAL];
-  const LoopCtl c{a.sub, a.deps, a.flags, a.ticket, a.err, a.nsub, a.epoch, a.spin_ticks, a.trace};
+  const LoopCtl c{a.sub, a.deps, a.flags, a.prog, a.ticket, a.err, a.nsub, a.epoch, a.spin_ticks, a.trace};
   if (a.ncolB == 16) {
     // Narrow right-hand sides: the first reflector block (written by the
     // factorization, never by a predecessor) is loaded before the wait.
@@ -2036,7 +2119,7 @@ __global__ __launch_bounds__(NTHREADS) void exec_batched(BatchArgs b) {
   __shared__ double sm[Smem<64>::TOTAL];
   const int epoch = __builtin_amdgcn_readfirstlane(
       __hip_atomic_load(b.ctl + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-  const LoopCtl c{b.sub, b.deps, b.flags, b.ctl, b.ctl + 1, b.nsub, epoch, b.spin_ticks, nullptr};
+  const LoopCtl c{b.sub, b.deps, b.flags, nullptr, b.ctl, b.ctl + 1, b.nsub, epoch, b.spin_ticks, nullptr};
   exec_loop(c, [&](int t) {
     const ProbDesc& pd = b.prob[__builtin_amdgcn_readfirstlane(b.prob_of[t])];
     ExecArgs a{};
@@ -2094,6 +2177,10 @@ __global__ __launch_bounds__(NTHREADS) void exec_level(ExecArgs a, const int32_t
   __shared__ double sm[Smem<NB>::TOTAL];
   const int t = __builtin_amdgcn_readfirstlane(order[begin + blockIdx.x]);
   run_sub<NB, P>(a, a.sub[t], sm, t);
+  // Streamed and early-release waits inside later levels read the flags.
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(a.flags + t, a.epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ void reset_kernel(int32_t* ticket, int32_t* err) {

@@ -374,10 +374,11 @@ bool make_plan(int p, int q, int tree, int bs, int family, Plan& plan) {
 // before it starts, the streamed C1 writer and the streamed panel blocks.
 std::vector<int32_t> stream_preds(const ExecPlan& ex, size_t r) {
   const SubTask& st = ex.sub[r];
-  std::vector<int32_t> v(ex.deps.begin() + st.dep_begin, ex.deps.begin() + st.dep_end);
+  std::vector<int32_t> v;
+  for (int32_t e = st.dep_begin; e < st.dep_end; ++e) v.push_back(dep_index(ex.deps[e]));
   if (st.sdep >= 0) v.push_back(st.sdep);
   if (st.pdep >= 0)
-    for (int b = 0; b < ex.pblk; ++b) v.push_back(ex.deps[st.pdep + b]);
+    for (int b = 0; b < ex.pblk; ++b) v.push_back(dep_index(ex.deps[st.pdep + b]));
   return v;
 }
 
@@ -411,7 +412,23 @@ std::vector<int32_t> stream_preds(const ExecPlan& ex, size_t r) {
 //   for good), block b only needs the previous writer's progress past its
 //   own block b; writers publish their progress after every block.
 // Streamed predecessors still count in the priorities and the level order.
-void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex, int pblk, bool stream) {
+//
+// early (with pblk > 1): a panel block subtask releases its successors once
+// it has factored its block and applied it to the next block's columns
+// (the look-ahead), and updates the rest of its tiles after that.  Block b
+// of a panel task then starts after the early release of block b - 1 and of
+// block b of the earlier panel tasks on its triangles (their factored
+// columns and look-ahead columns are final, and so is everything their own
+// earlier blocks wrote); it waits for the completion of block b - 1 before
+// its look-ahead (block b - 1 updated the next block's columns last) and
+// for the completion of block b of the earlier panel tasks before the rest
+// of its tiles (they updated the same rows of those columns last).  Every
+// block waits at both points even when it has nothing to update, so the
+// completion of block b still implies the completion of everything block b
+// waited for.  Streamed update subtasks only read the reflectors and T of
+// panel block b, which are final at its early release.
+void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex, int pblk, bool stream,
+                    bool early, double lookahead) {
   const int p = plan.p, q = plan.q, S = nslab;
   ex = ExecPlan();
   ex.nslab = S;
@@ -426,12 +443,23 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
   std::vector<int32_t> sdep, pfirst;  // streamed C1 writer, panel block 0 (emission order), or -1
   sub.reserve(plan.tasks.size() * 2);
   stream = stream && pblk > 1;
+  early = early && pblk > 1;
 
   std::vector<int32_t> first_blk;  // panel subtasks: id of block 0 of the task; -1 otherwise
   auto add = [&](const Task& t, int32_t tidx, int slab, std::vector<int32_t>&& d) {
     std::sort(d.begin(), d.end());
     d.erase(std::unique(d.begin(), d.end()), d.end());
     if (!d.empty() && d.front() < 0) d.erase(d.begin(), std::upper_bound(d.begin(), d.end(), -1));
+    // an entry that is also waited for in full at the start needs no other
+    // entry for the same predecessor
+    std::vector<int32_t> plain;
+    for (int32_t x : d)
+      if (dep_bits(x) == 0) plain.push_back(x);
+    d.erase(std::remove_if(d.begin(), d.end(),
+                           [&](int32_t x) {
+                             return dep_bits(x) != 0 && std::binary_search(plain.begin(), plain.end(), dep_index(x));
+                           }),
+            d.end());
     sub.push_back({t.kind, t.i - 1, t.piv > 0 ? t.piv - 1 : 0, t.k - 1, t.j > 0 ? t.j - 1 : 0, slab, 0, 0, -1, -1});
     pre.push_back(std::move(d));
     task_of.push_back(tidx);
@@ -479,8 +507,19 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
     for (int b = 0; b < pblk; ++b) {
       std::vector<int32_t> db;
       if (b == 0) db = other;
-      if (prev >= 0) db.push_back(prev);
-      for (int32_t f : panel_first) db.push_back(f + b);
+      if (early) {
+        if (prev >= 0) {
+          db.push_back(prev | DEP_EARLY);
+          db.push_back(prev | DEP_STAGE1);
+        }
+        for (int32_t f : panel_first) {
+          db.push_back((f + b) | DEP_EARLY);
+          db.push_back((f + b) | DEP_STAGE2);
+        }
+      } else {
+        if (prev >= 0) db.push_back(prev);
+        for (int32_t f : panel_first) db.push_back(f + b);
+      }
       prev = add(t, tidx, b, std::move(db));
       if (b == 0) first = prev;
       first_blk[prev] = first;
@@ -570,18 +609,22 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
 
   // Priorities: ASAP start (order 0), ALAP start (order 1) or largest bottom
   // level first (order 2) of each subtask, with per-kind weights (updates
-  // divided among their slabs, panel tasks among their blocks).
+  // divided among their slabs, panel tasks among their blocks).  Updates of
+  // the column right of their panel get the look-ahead bonus: the next
+  // column's panel tasks wait for them, and with a plain bottom level they
+  // are dispatched behind the updates of columns further right.
   const size_t n = sub.size();
   std::vector<double> wt(n), est(n, 0.0), lst(n, 0.0);
   for (size_t s = 0; s < n; ++s) {
     const int kd = sub[s].kind;
     const bool is_upd = (kd == K_UNMQR || kd == K_TSMQR || kd == K_TTMQR);
     wt[s] = is_upd ? w[kd] / S : w[kd] / (sub[s].slab >= 0 ? pblk : 1);
+    if (is_upd && sub[s].j == sub[s].k + 1) wt[s] += lookahead;
   }
   // All predecessors, the streamed ones included, order the subtasks.
   std::vector<std::vector<int32_t>> allp(n);
   for (size_t s = 0; s < n; ++s) {
-    allp[s] = pre[s];
+    for (int32_t d : pre[s]) allp[s].push_back(dep_index(d));
     if (sdep[s] >= 0) allp[s].push_back(sdep[s]);
     if (pfirst[s] >= 0)
       for (int b = 0; b < pblk; ++b) allp[s].push_back(pfirst[s] + b);
@@ -623,18 +666,22 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
   ex.sub.resize(n);
   ex.deps.clear();
   ex.key.resize(n);
-  for (size_t r = 0; r < n; ++r) ex.key[r] = key[perm[r]];
+  ex.wt.resize(n);
+  for (size_t r = 0; r < n; ++r) {
+    ex.key[r] = key[perm[r]];
+    ex.wt[r] = wt[perm[r]];
+  }
   for (size_t r = 0; r < n; ++r) {
     const int32_t s = perm[r];
     SubTask st = sub[s];
     st.dep_begin = static_cast<int32_t>(ex.deps.size());
-    for (int32_t d : pre[s]) ex.deps.push_back(pos[d]);
+    for (int32_t d : pre[s]) ex.deps.push_back(pos[dep_index(d)] | dep_bits(d));
     st.dep_end = static_cast<int32_t>(ex.deps.size());
     st.sdep = sdep[s] >= 0 ? pos[sdep[s]] : -1;
     st.pdep = -1;
     if (pfirst[s] >= 0) {
       st.pdep = static_cast<int32_t>(ex.deps.size());
-      for (int b = 0; b < pblk; ++b) ex.deps.push_back(pos[pfirst[s] + b]);
+      for (int b = 0; b < pblk; ++b) ex.deps.push_back(pos[pfirst[s] + b] | (early ? DEP_EARLY : 0));
     }
     ex.sub[r] = st;
   }
@@ -705,8 +752,8 @@ void make_apply_plan(const Plan& plan, int trans, int nslab, ExecPlan& ex) {
   for (size_t r = 0; r < n; ++r) ex.level_order[fill[depth[r]]++] = static_cast<int32_t>(r);
 }
 
-void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, const double w[6], int nslab_b,
-                            double w_apply, ExecPlan& out) {
+void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, int nslab_b, double w_apply,
+                            ExecPlan& out) {
   ExecPlan ap;
   make_apply_plan(plan, 1, nslab_b, ap);
   const size_t nf = fac.sub.size(), na = ap.sub.size(), n = nf + na;
@@ -730,12 +777,7 @@ void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, co
   }
   for (size_t t = 0; t < n; ++t) allp[t] = t < nf ? stream_preds(fac, t) : pre[t];
   std::vector<double> wt(n);
-  const double S = static_cast<double>(nslab);
-  for (size_t t = 0; t < nf; ++t) {
-    const int kd = fac.sub[t].kind;
-    const bool is_upd = (kd == K_UNMQR || kd == K_TSMQR || kd == K_TTMQR);
-    wt[t] = is_upd ? w[kd] / S : w[kd] / (fac.sub[t].slab >= 0 ? fac.pblk : 1);
-  }
+  for (size_t t = 0; t < nf; ++t) wt[t] = fac.wt[t];
   for (size_t a = 0; a < na; ++a) wt[nf + a] = w_apply;
   // Bottom levels: successors have larger indices in this numbering
   // (factorization subtasks first, in their own topological order, then the
@@ -775,13 +817,16 @@ void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, co
     const int32_t t = perm[r];
     SubTask st = t < static_cast<int32_t>(nf) ? fac.sub[t] : ap.sub[t - nf];
     st.dep_begin = static_cast<int32_t>(out.deps.size());
-    for (int32_t d : pre[t]) out.deps.push_back(pos[d]);
+    for (int32_t d : pre[t]) out.deps.push_back(pos[dep_index(d)] | dep_bits(d));
     st.dep_end = static_cast<int32_t>(out.deps.size());
     if (st.sdep >= 0) st.sdep = pos[st.sdep];
     if (st.pdep >= 0) {
       const int32_t old = st.pdep;
       st.pdep = static_cast<int32_t>(out.deps.size());
-      for (int b = 0; b < fac.pblk; ++b) out.deps.push_back(pos[fac.deps[old + b]]);
+      for (int b = 0; b < fac.pblk; ++b) {
+        const int32_t d = fac.deps[old + b];
+        out.deps.push_back(pos[dep_index(d)] | dep_bits(d));
+      }
     }
     out.sub[r] = st;
     out.key[r] = -bl[t];

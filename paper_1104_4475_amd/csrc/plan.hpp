@@ -5,6 +5,8 @@
 #include <cstdint>
 #include <vector>
 
+#include "depcode.hpp"
+
 namespace tqr {
 
 enum Kind : int32_t { K_GEQRT = 0, K_UNMQR = 1, K_TSQRT = 2, K_TSMQR = 3, K_TTQRT = 4, K_TTMQR = 5 };
@@ -56,6 +58,7 @@ struct ExecPlan {
   std::vector<int32_t> level_ptr;    // subtasks grouped by DAG depth
   std::vector<int32_t> level_order;  // indices into sub, level by level
   std::vector<double> key;           // priority key of each subtask (ascending = earlier)
+  std::vector<double> wt;            // weight of each subtask in the priorities
   int32_t nslab = 1;
   int32_t pblk = 1;                  // subtasks per panel task (inner blocks)
 };
@@ -68,17 +71,25 @@ struct ExecPlan {
 // stream (with pblk > 1): update subtasks follow their reflectors block by
 // block (pdep) and pair updates follow the previous writer of their C1 tile
 // block by block (sdep) instead of waiting for them to finish (plan.cpp).
+// early (with pblk > 1): panel block subtasks release their successors
+// after their look-ahead update and wait for the rest of their
+// predecessors inside (plan.cpp); predecessor entries then carry the fields
+// of depcode.hpp.
+// lookahead: extra priority weight of the update subtasks on the column
+// right of their panel (j = k + 1), which the next column's panel tasks
+// wait for.
 void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex, int pblk = 1,
-                    bool stream = false);
+                    bool stream = false, bool early = false, double lookahead = 0.0);
 
 // One executor plan for the factorization and Q^T B together: the
-// subtasks of fac (built by make_exec_plan with the same nslab and weights
-// w) and those of the Q^T application plan (make_apply_plan, trans = 1,
-// nslab_b slabs of B), each application subtask also depending on the panel
-// subtask that produces its reflectors.  Ordered by largest bottom level in
-// the joint graph (application subtasks weigh w_apply).
-void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, const double w[6], int nslab_b,
-                            double w_apply, ExecPlan& out);
+// subtasks of fac (built by make_exec_plan with the same nslab; their
+// priority weights are fac.wt) and those of the Q^T application plan
+// (make_apply_plan, trans = 1, nslab_b slabs of B), each application
+// subtask also depending on the panel subtask that produces its
+// reflectors.  Ordered by largest bottom level in the joint graph
+// (application subtasks weigh w_apply).
+void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, int nslab_b, double w_apply,
+                            ExecPlan& out);
 
 // Application of Q^T (trans = 1) or Q (trans = 0) to p row tiles of a
 // right-hand side with nslab column slabs: the reflector set of every panel

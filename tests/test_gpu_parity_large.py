@@ -180,34 +180,56 @@ def test_executor_trace_respects_dag(torch_cuda, case, upd):
     F.sync()
     tr, _ = F.trace()
     sub, deps = F.exec_plan()
+    from paper_1104_4475_amd import _lib
     assert len(tr) == len(sub)
     assert np.array_equal(tr[:, :6], sub[:, :6].astype(np.int64))
     ticket, ready, end = tr[:, 6], tr[:, 7], tr[:, 8]
     assert np.all(ticket > 0) and np.all(ready >= ticket) and np.all(end >= ready)
     # 1. the executor's own subtask dependencies
+    streamed = set()  # (predecessor subtask, successor subtask) not waited for in full at the start
+    nearly = 0
     for t in range(len(sub)):
-        d = deps[sub[t, 6]:sub[t, 7]]
-        if len(d):
-            assert np.all(d < t)
-            late = end[d] > ready[t]
-            assert not late.any(), ("subtask", t, "ready before predecessors", d[late])
+        e = deps[sub[t, 6]:sub[t, 7]]
+        if len(e):
+            d = e & _lib.DEP_INDEX
+            stage = (e >> _lib.DEP_STAGE_SHIFT) & 3
+            early = (e & _lib.DEP_EARLY) != 0
+            assert np.all(d < t) and np.all(stage < 3)
+            plain = (stage == 0) & ~early
+            late = end[d[plain]] > ready[t]
+            assert not late.any(), ("subtask", t, "ready before predecessors", d[plain][late])
+            # an early release comes after the predecessor started; a wait
+            # inside a panel block subtask makes it end after the predecessor
+            assert np.all(ready[d[early]] <= ready[t]), ("subtask", t, "ready before an early predecessor started")
+            assert np.all(end[d[stage > 0]] <= end[t]), ("subtask", t, "ended before a predecessor waited inside")
+            if (stage > 0).any():
+                assert sub[t, 0] in (0, 2, 4) and sub[t, 5] >= 0
+            streamed.update((int(u), t) for u in d[~plain])
+            nearly += int(early.sum())
     # 1b. streamed predecessors (FP32 / BF16 updates at nb >= 128): an update
-    # applies panel block b after that block's flag, so it ends after every
-    # streamed panel block has ended; it ends after its C1 writer started.
+    # applies panel block b after that block's flag (or early release), so it
+    # ends after every streamed panel block started (and, without early
+    # release, after it ended); it ends after its C1 writer started.
     nblk = nb // 32
-    streamed = set()  # (predecessor subtask, successor subtask)
     for t in range(len(sub)):
         if sub[t, 9] >= 0:
-            pb = deps[sub[t, 9]:sub[t, 9] + nblk]
+            pe = deps[sub[t, 9]:sub[t, 9] + nblk]
+            pb = pe & _lib.DEP_INDEX
             assert np.all(pb < t)
-            assert np.all(end[pb] <= end[t]), ("subtask", t, "ended before a streamed panel block")
+            whole = (pe & _lib.DEP_EARLY) == 0
+            assert np.all(end[pb[whole]] <= end[t]), ("subtask", t, "ended before a streamed panel block")
+            assert np.all(ready[pb] <= end[t]), ("subtask", t, "ended before a streamed panel block started")
             streamed.update((int(u), t) for u in pb)
         if sub[t, 8] >= 0:
             u = int(sub[t, 8])
             assert u < t and ready[u] <= end[t]
             streamed.add((u, t))
-    if upd == 0 or nb < 128:
+    if nb < 128:
         assert not streamed
+    else:
+        assert nearly > 0  # panel block subtasks release early at nb >= 128
+    if upd == 0:
+        assert (sub[:, 8:] < 0).all()  # FP64 updates wait for whole predecessors
     # 2. every edge of the oracle's task DAG: each subtask of a task became
     # ready after some subtask of each predecessor task had finished
     p, q = m // nb, n // nb
@@ -320,5 +342,46 @@ def test_streamed_factors_bit_identical(torch_cuda, case, monkeypatch):
             F.refactor(A)
             F.sync()
             out.append(F.packed().cpu().numpy())
+    for P in out[1:]:
+        assert np.array_equal(P.view(np.uint64), out[0].view(np.uint64))
+
+
+EARLY_CASES = [
+    # (m, n, nb, tree, bs, kernels, upd): TS chains, TT merges, GEQRT-only
+    # columns, every update precision and both split tile sizes
+    (2560, 2560, 256, trees.FLAT, 1, dag.KERN_TS, 1),
+    (2048, 1024, 256, trees.PLASMA, 4, dag.KERN_TS, 0),
+    (2048, 1280, 256, trees.GREEDY, 1, dag.KERN_TT, 2),
+    (1536, 1024, 128, trees.HADRI, 3, dag.KERN_TS, 1),
+    (1024, 1024, 128, trees.BINARY, 1, dag.KERN_TT, 0),
+]
+
+
+@pytest.mark.parametrize("case", EARLY_CASES, ids=lambda c: "%dx%d_nb%d_t%d_bs%d_k%d_u%d" % c)
+def test_early_release_bit_identical(torch_cuda, case, monkeypatch):
+    """Panel block subtasks that release their successors after the
+    look-ahead (and wait for the rest of their predecessors inside) do the
+    same arithmetic in the same order on every tile element as subtasks
+    that wait for whole predecessors: the factors must agree bit for bit.
+    The level-synchronous executor (which runs the same plan level by level)
+    must agree too."""
+    import paper_1104_4475_amd as tqr
+    from paper_1104_4475_amd import _lib
+    m, n, nb, tree, bs, kern, upd = case
+    _say("early release vs whole blocks %s" % (case,))
+    A = _gpu(torch_cuda, tqr_inputs.gaussian(m, n, seed=98))
+    out = []
+    for early, path in (("0", "persistent"), ("1", "persistent"), ("1", "level")):
+        monkeypatch.setenv("TQR_EARLY", early)
+        monkeypatch.setenv("TQR_EXEC", path)
+        F = tqr.factor(A, nb, tree, bs, kern, upd)
+        F.sync()
+        sub, deps = F.exec_plan()
+        assert ((deps & _lib.DEP_EARLY) != 0).any() == (early == "1")
+        for _ in range(2 if path == "persistent" else 1):
+            F.refactor(A)
+            F.sync()
+            out.append(F.packed().cpu().numpy())
+        del F
     for P in out[1:]:
         assert np.array_equal(P.view(np.uint64), out[0].view(np.uint64))
