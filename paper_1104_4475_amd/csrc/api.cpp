@@ -143,14 +143,19 @@ bool use_level_path() {
   return e && std::strcmp(e, "level") == 0;
 }
 
-// Dispatch priority of the executor: largest bottom level first (the
-// longest remaining path through the DAG), or for diagnostics (TQR_ORDER)
-// the ASAP or ALAP start time.
+// Dispatch order of the executor: the start order of a list schedule
+// simulated on the executor's workgroups, which starts the ready subtask of
+// largest bottom level (longest remaining path through the DAG) whenever a
+// workgroup is free; or (TQR_ORDER) the plain bottom-level order ("bl"), or
+// the ASAP or ALAP start time.  At 10240^2 the simulated order is 6% faster
+// than the bottom-level order: a subtask's ticket is taken about when it can
+// run, so fewer workgroups sit waiting on subtasks that are far from ready.
 int exec_order() {
   const char* e = std::getenv("TQR_ORDER");
   if (e && std::strcmp(e, "asap") == 0) return 0;
   if (e && std::strcmp(e, "alap") == 0) return 1;
-  return 2;
+  if (e && std::strcmp(e, "bl") == 0) return 2;
+  return 3;
 }
 
 // Per-kind task weights (GEQRT, UNMQR, TSQRT, TSMQR, TTQRT, TTMQR) for the
@@ -173,17 +178,6 @@ void exec_weights(int nb, int upd, double w[6]) {
     if (std::sscanf(e, "%lf,%lf,%lf,%lf,%lf,%lf", &v[0], &v[1], &v[2], &v[3], &v[4], &v[5]) == 6)
       for (int k = 0; k < 6; ++k) w[k] = v[k];
   }
-}
-
-// Priority bonus of the updates on the column right of their panel (the
-// next panel's column), in the units of exec_weights; TQR_LOOKAHEAD
-// overrides it for diagnostics.
-double lookahead_bonus(int nb, int upd) {
-  (void)nb;
-  (void)upd;
-  double b = 0.0;
-  if (const char* e = std::getenv("TQR_LOOKAHEAD")) b = std::atof(e);
-  return b;
 }
 
 }  // namespace
@@ -457,7 +451,8 @@ int create(const tqr_opts* o, tqr_factors** out, ExecPlan* keep = nullptr) {
   // update (TQR_EARLY=0: only when they finish).
   const char* ev = std::getenv("TQR_EARLY");
   const bool early = pblk > 1 && !(ev && ev[0] == '0');
-  tqr::make_exec_plan(F->plan, nslab, exec_order(), w, ex, pblk, stream, early, lookahead_bonus(o->nb, o->upd));
+  const int workers = device_cus() * tqr::persistent_occupancy(o->nb, o->upd);
+  tqr::make_exec_plan(F->plan, nslab, exec_order(), w, ex, pblk, stream, early, workers);
   int st = upload(ex, F->exec);
   if (st != TQR_OK) return st;
   if (keep) *keep = ex;

@@ -1169,25 +1169,34 @@ __device__ __forceinline__ void wide_update_task(const unsigned char* img, doubl
 // Look-ahead: while reflector jj is applied, the owner of column jj + 1
 // updates that column first and computes reflector jj + 1 at once, before
 // its other columns, so one barrier per column separates consecutive
-// reflectors and the chain between them is a single column update.
+// reflectors and the chain between them is a single column update.  A
+// wave's other columns take their dot products with v together, so their
+// wavefront reductions overlap.  For the pair kernels the rows of the
+// triangle block stay in registers during the loop (lane a holds row a of
+// each owned column) and go back to Rs at the end.
 template <int NB, int PAIR>
 __device__ __forceinline__ void panel_factor(double* Ps, int ldp, int K, double* Rs, double* tau, double* vbuf,
                                              int tt, int c0) {
   constexpr int RCH = (NB + 63) / 64;
   const int lane = lane_id(), wave = wave_id();
   double pc[4][RCH];
+  double rs[4];
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < 4; ++q) {
 #pragma unroll
     for (int u = 0; u < RCH; ++u) {
       const int r = lane + 64 * u;
       pc[q][u] = r < K ? Ps[r + (wave + NWAVES * q) * ldp] : 0.0;
     }
+    rs[q] = (PAIR && lane < IB) ? Rs[lane + (wave + NWAVES * q) * IB] : 0.0;
+  }
 
-  // Reflector of column jj (owned by this wave, held in register slot x):
-  // writes v to vbuf[jj & 1], tau[jj], and (pairs) beta to Rs.  jj < 64, so
-  // the diagonal row jj of a GEQRT panel is in row chunk 0.
-  auto reflector = [&](int jj, double (&x)[RCH]) {
+  // Reflector of column jj (owned by this wave, held in register slot q):
+  // writes v to vbuf[jj & 1], tau[jj], and (pairs) beta to row jj of the
+  // triangle.  jj < 64, so the diagonal row jj of a GEQRT panel is in row
+  // chunk 0.
+  auto reflector = [&](int jj, int q) {
+    double (&x)[RCH] = pc[q];
     const int r0 = PAIR ? 0 : jj + 1;
     const int r1 = PAIR ? (tt ? c0 + jj + 1 : K) : K;
     double* vb = vbuf + (jj & 1) * NB;
@@ -1198,7 +1207,7 @@ __device__ __forceinline__ void panel_factor(double* Ps, int ldp, int K, double*
       if (r >= r0 && r < r1) ssq += x[u] * x[u];
     }
     ssq = wave_sum(ssq);
-    const double alpha = PAIR ? Rs[jj + jj * IB] : lane_d(x[0], jj);
+    const double alpha = PAIR ? lane_d(rs[q], jj) : lane_d(x[0], jj);
     double beta = alpha, t = 0.0, scale = 0.0;
     if (ssq != 0.0) {
       const double nrm = sqrt(alpha * alpha + ssq);
@@ -1214,30 +1223,30 @@ __device__ __forceinline__ void panel_factor(double* Ps, int ldp, int K, double*
       if (!PAIR && u == 0 && r == jj) x[u] = beta;
       if (r < NB) vb[r] = in ? x[u] : 0.0;
     }
-    if (lane == 0) {
-      tau[jj] = t;
-      if (PAIR) Rs[jj + jj * IB] = beta;
-    }
+    if (PAIR && lane == jj) rs[q] = beta;
+    if (lane == 0) tau[jj] = t;
   };
 
-  // Apply reflector jj (v, t) to this wave's register column slot q2.
-  auto update = [&](int jj, int q2, const double (&v)[RCH], double t) {
-    const int c = wave + NWAVES * q2;
-    double d = 0.0;
-#pragma unroll
-    for (int u = 0; u < RCH; ++u) d += v[u] * pc[q2][u];
-    d = wave_sum(d);
-    d += PAIR ? Rs[jj + c * IB] : lane_d(pc[q2][0], jj);
+  // Reflector jj (v, t) applied to this wave's column slot q2, given the
+  // wavefront sum d of v . (its rows in registers).
+  auto apply_col = [&](int jj, int q2, const double (&v)[RCH], double d, double t) {
+    d += PAIR ? lane_d(rs[q2], jj) : lane_d(pc[q2][0], jj);
     d *= t;
 #pragma unroll
     for (int u = 0; u < RCH; ++u) {
       pc[q2][u] -= v[u] * d;
       if (!PAIR && u == 0 && lane == jj) pc[q2][u] -= d;
     }
-    if (PAIR && lane == 0) Rs[jj + c * IB] -= d;
+    if (PAIR && lane == jj) rs[q2] -= d;
+  };
+  auto dot = [&](int q2, const double (&v)[RCH]) {
+    double d = 0.0;
+#pragma unroll
+    for (int u = 0; u < RCH; ++u) d += v[u] * pc[q2][u];
+    return d;
   };
 
-  if (wave == 0) reflector(0, pc[0]);
+  if (wave == 0) reflector(0, 0);
   // Column jj = 8 q + w: slot q of wave w.  The owner of column jj + 1
   // (wave w + 1, slot q; or wave 0, slot q + 1) updates it first, computes
   // its reflector at raised priority, then updates its other columns.
@@ -1260,30 +1269,40 @@ __device__ __forceinline__ void panel_factor(double* Ps, int ldp, int K, double*
       if (own_next) {
         __builtin_amdgcn_s_setprio(3);
         if (nq == q) {
-          if (t != 0.0) update(jj, q, v, t);
-          reflector(nxt, pc[q]);
+          if (t != 0.0) apply_col(jj, q, v, wave_sum(dot(q, v)), t);
+          reflector(nxt, q);
         } else if (q + 1 < 4) {
-          if (t != 0.0) update(jj, (q + 1 < 4) ? q + 1 : q, v, t);
-          reflector(nxt, pc[(q + 1 < 4) ? q + 1 : q]);
+          const int qn = (q + 1 < 4) ? q + 1 : q;
+          if (t != 0.0) apply_col(jj, qn, v, wave_sum(dot(qn, v)), t);
+          reflector(nxt, qn);
         }
         __builtin_amdgcn_s_setprio(0);
       }
       if (t != 0.0) {
+        // this wave's columns right of nxt: the dot products first, then
+        // their reductions side by side, then the updates
+        double dd[4];
+#pragma unroll
+        for (int q2 = q; q2 < 4; ++q2) dd[q2] = dot(q2, v);
+#pragma unroll
+        for (int q2 = q; q2 < 4; ++q2) dd[q2] = wave_sum(dd[q2]);
 #pragma unroll
         for (int q2 = q; q2 < 4; ++q2) {
           const int c = wave + NWAVES * q2;
-          if (c > nxt) update(jj, q2, v, t);
+          if (c > nxt) apply_col(jj, q2, v, dd[q2], t);
         }
       }
     }
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < 4; ++q) {
 #pragma unroll
     for (int u = 0; u < RCH; ++u) {
       const int r = lane + 64 * u;
       if (r < K) Ps[r + (wave + NWAVES * q) * ldp] = pc[q][u];
     }
+    if (PAIR && lane < IB) Rs[lane + (wave + NWAVES * q) * IB] = rs[q];
+  }
   __syncthreads();
 }
 

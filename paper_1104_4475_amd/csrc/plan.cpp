@@ -382,6 +382,86 @@ std::vector<int32_t> stream_preds(const ExecPlan& ex, size_t r) {
   return v;
 }
 
+// Start order of a list schedule of the executor subtasks (emission order,
+// predecessor entries pre, streamed C1 writer sdep, first streamed panel
+// block pfirst) on `workers` workgroups: whenever a workgroup is free it
+// starts the ready subtask of largest bottom level bl.  A subtask is ready
+// once its plain predecessors have ended, its early ones have released
+// (a panel block releases after 0.65 of its weight, the last block of a
+// panel task at its end), and its streamed predecessors have started
+// (every block of a streamed panel task, so that the dispatch order keeps
+// them ahead of the update).  Waits inside a panel block subtask (stages 1
+// and 2) pair with early entries for the same predecessors and are not
+// start conditions.  Durations are the weights wt.  Returns each subtask's
+// rank, a topological order.
+static std::vector<double> sim_order(const std::vector<SubTask>& sub, const std::vector<std::vector<int32_t>>& pre,
+                                     const std::vector<int32_t>& sdep, const std::vector<int32_t>& pfirst, int pblk,
+                                     const std::vector<double>& wt, const std::vector<double>& bl, int workers) {
+  const size_t n = sub.size();
+  std::vector<int32_t> nwait(n, 0);
+  std::vector<std::vector<int32_t>> on_start(n), on_early(n), on_end(n);
+  for (size_t s = 0; s < n; ++s) {
+    for (int32_t d : pre[s]) {
+      if (dep_stage(d) != 0) continue;
+      (dep_early(d) ? on_early : on_end)[dep_index(d)].push_back(static_cast<int32_t>(s));
+      ++nwait[s];
+    }
+    if (sdep[s] >= 0) {
+      on_start[sdep[s]].push_back(static_cast<int32_t>(s));
+      ++nwait[s];
+    }
+    if (pfirst[s] >= 0)
+      for (int b = 0; b < pblk; ++b) {
+        on_start[pfirst[s] + b].push_back(static_cast<int32_t>(s));
+        ++nwait[s];
+      }
+  }
+  // ready subtasks: largest bottom level first, then emission order
+  auto cmp = [&](int32_t a, int32_t b) { return bl[a] != bl[b] ? bl[a] < bl[b] : a > b; };
+  std::priority_queue<int32_t, std::vector<int32_t>, decltype(cmp)> ready(cmp);
+  // events: (time, kind 0 = early release / 1 = end, subtask), earliest first
+  using Ev = std::tuple<double, int, int32_t>;
+  std::priority_queue<Ev, std::vector<Ev>, std::greater<Ev>> ev;
+  auto notify = [&](const std::vector<int32_t>& v) {
+    for (int32_t c : v)
+      if (--nwait[c] == 0) ready.push(c);
+  };
+  for (size_t s = 0; s < n; ++s)
+    if (nwait[s] == 0) ready.push(static_cast<int32_t>(s));
+  std::vector<double> rank(n, 0.0);
+  size_t started = 0;
+  int free = workers;
+  double now = 0.0;
+  while (started < n) {
+    while (free > 0 && !ready.empty()) {
+      const int32_t s = ready.top();
+      ready.pop();
+      rank[s] = static_cast<double>(started++);
+      --free;
+      const int kd = sub[s].kind;
+      const bool panel_blk = (kd == K_GEQRT || kd == K_TSQRT || kd == K_TTQRT) && sub[s].slab >= 0;
+      const double rel = (panel_blk && sub[s].slab < pblk - 1) ? 0.65 : 1.0;
+      ev.emplace(now + rel * wt[s], 0, s);
+      ev.emplace(now + wt[s], 1, s);
+      notify(on_start[s]);
+    }
+    if (ev.empty()) break;  // cannot happen for a DAG
+    now = std::get<0>(ev.top());
+    while (!ev.empty() && std::get<0>(ev.top()) <= now) {
+      const int kind = std::get<1>(ev.top());
+      const int32_t s = std::get<2>(ev.top());
+      ev.pop();
+      if (kind == 0) {
+        notify(on_early[s]);
+      } else {
+        notify(on_end[s]);
+        ++free;
+      }
+    }
+  }
+  return rank;
+}
+
 // ---------------------------------------------------------------------------
 // Executor plan.  An update task on column slab s of its C tiles only touches
 // slab s, so dependencies are tracked per (tile, slab); the panel tasks touch
@@ -428,7 +508,7 @@ std::vector<int32_t> stream_preds(const ExecPlan& ex, size_t r) {
 // waited for.  Streamed update subtasks only read the reflectors and T of
 // panel block b, which are final at its early release.
 void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex, int pblk, bool stream,
-                    bool early, double lookahead) {
+                    bool early, int workers) {
   const int p = plan.p, q = plan.q, S = nslab;
   ex = ExecPlan();
   ex.nslab = S;
@@ -609,17 +689,16 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
 
   // Priorities: ASAP start (order 0), ALAP start (order 1) or largest bottom
   // level first (order 2) of each subtask, with per-kind weights (updates
-  // divided among their slabs, panel tasks among their blocks).  Updates of
-  // the column right of their panel get the look-ahead bonus: the next
-  // column's panel tasks wait for them, and with a plain bottom level they
-  // are dispatched behind the updates of columns further right.
+  // divided among their slabs, panel tasks among their blocks); or (order 3)
+  // the start order of a list schedule of the subtasks on `workers`
+  // workgroups that starts, whenever a workgroup is free, the ready subtask
+  // of largest bottom level (sim_order).
   const size_t n = sub.size();
   std::vector<double> wt(n), est(n, 0.0), lst(n, 0.0);
   for (size_t s = 0; s < n; ++s) {
     const int kd = sub[s].kind;
     const bool is_upd = (kd == K_UNMQR || kd == K_TSMQR || kd == K_TTMQR);
     wt[s] = is_upd ? w[kd] / S : w[kd] / (sub[s].slab >= 0 ? pblk : 1);
-    if (is_upd && sub[s].j == sub[s].k + 1) wt[s] += lookahead;
   }
   // All predecessors, the streamed ones included, order the subtasks.
   std::vector<std::vector<int32_t>> allp(n);
@@ -653,7 +732,9 @@ void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], E
   }
   std::vector<double> negbl(n);
   for (size_t s = 0; s < n; ++s) negbl[s] = -bl[s];
-  const std::vector<double>& key = (order == 1) ? lst : (order == 2 ? negbl : est);
+  std::vector<double> simk;
+  if (order == 3 && workers > 0) simk = sim_order(sub, pre, sdep, pfirst, pblk, wt, bl, workers);
+  const std::vector<double>& key = (order == 1) ? lst : (order == 2 ? negbl : (order == 3 && workers > 0 ? simk : est));
   std::vector<int32_t> perm(n);
   std::iota(perm.begin(), perm.end(), 0);
   std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
@@ -765,7 +846,7 @@ void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, in
     if ((s.kind == K_GEQRT || s.kind == K_TSQRT || s.kind == K_TTQRT) && (s.slab < 0 || s.slab == fac.pblk - 1))
       panel[{s.kind, s.i, s.k}] = static_cast<int32_t>(t);
   }
-  std::vector<std::vector<int32_t>> pre(n), allp(n);
+  std::vector<std::vector<int32_t>> pre(n);
   for (size_t t = 0; t < nf; ++t)
     for (int32_t e = fac.sub[t].dep_begin; e < fac.sub[t].dep_end; ++e) pre[t].push_back(fac.deps[e]);
   for (size_t a = 0; a < na; ++a) {
@@ -775,35 +856,25 @@ void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, in
     auto it = panel.find({fk, s.i, s.k});
     if (it != panel.end()) pre[nf + a].push_back(it->second);
   }
-  for (size_t t = 0; t < n; ++t) allp[t] = t < nf ? stream_preds(fac, t) : pre[t];
+  // Dispatch order: the factorization subtasks keep theirs; an application
+  // subtask goes right behind the last of its predecessors (its panel
+  // subtask, the previous application on its rows), so the Q^T B chain
+  // advances with the factorization instead of trailing it.
+  std::vector<double> key(n);
+  for (size_t t = 0; t < nf; ++t) key[t] = static_cast<double>(t);
+  const double eps = 1.0 / static_cast<double>(na + 2);
+  for (size_t a = 0; a < na; ++a) {
+    double k = -1.0;
+    for (int32_t d : pre[nf + a]) k = std::max(k, key[d]);
+    key[nf + a] = k + eps;
+  }
   std::vector<double> wt(n);
   for (size_t t = 0; t < nf; ++t) wt[t] = fac.wt[t];
   for (size_t a = 0; a < na; ++a) wt[nf + a] = w_apply;
-  // Bottom levels: successors have larger indices in this numbering
-  // (factorization subtasks first, in their own topological order, then the
-  // application subtasks in theirs), so one backward sweep suffices.
-  std::vector<std::vector<int32_t>> succ(n);
-  for (size_t t = 0; t < n; ++t)
-    for (int32_t d : allp[t]) succ[d].push_back(static_cast<int32_t>(t));
-  std::vector<double> bl(n, 0.0);
-  for (size_t t = n; t-- > 0;) {
-    double m = 0.0;
-    for (int32_t c : succ[t]) m = std::max(m, bl[c]);
-    bl[t] = m + wt[t];
-  }
-  // An application subtask is dispatched right behind the last of its
-  // predecessors (its panel subtask, the previous application on its rows):
-  // its key is just below theirs, so the Q^T B chain advances with the
-  // factorization instead of trailing it.
-  for (size_t a = 0; a < na; ++a) {
-    double k = INFINITY;
-    for (int32_t d : pre[nf + a]) k = std::min(k, bl[d]);
-    bl[nf + a] = (k == INFINITY ? 0.0 : std::nextafter(k, -INFINITY));
-  }
   std::vector<int32_t> perm(n);
   std::iota(perm.begin(), perm.end(), 0);
   std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
-    if (bl[a] != bl[b]) return bl[a] > bl[b];
+    if (key[a] != key[b]) return key[a] < key[b];
     return a < b;
   });
   std::vector<int32_t> pos(n);
@@ -813,6 +884,7 @@ void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, in
   out.pblk = fac.pblk;
   out.sub.resize(n);
   out.key.resize(n);
+  out.wt.resize(n);
   for (size_t r = 0; r < n; ++r) {
     const int32_t t = perm[r];
     SubTask st = t < static_cast<int32_t>(nf) ? fac.sub[t] : ap.sub[t - nf];
@@ -829,7 +901,8 @@ void make_factor_apply_plan(const Plan& plan, const ExecPlan& fac, int nslab, in
       }
     }
     out.sub[r] = st;
-    out.key[r] = -bl[t];
+    out.key[r] = key[t];
+    out.wt[r] = wt[t];
   }
   std::vector<int32_t> depth(n, 0);
   int32_t maxd = 0;

@@ -64,7 +64,9 @@ struct ExecPlan {
 };
 
 // order: 0 = ascending ASAP start time, 1 = ascending ALAP start time,
-// 2 = descending bottom level (longest remaining path).
+// 2 = descending bottom level (longest remaining path), 3 = start order of a
+// list schedule on `workers` workgroups by descending bottom level among
+// the ready subtasks (plan.cpp; needs workers > 0, else as 0).
 // w: per-kind weights used for the priority (any positive values).
 // pblk > 1 splits every panel task (GEQRT, TSQRT, TTQRT) into its pblk inner
 // blocks of columns, one subtask each (see plan.cpp).
@@ -75,11 +77,8 @@ struct ExecPlan {
 // after their look-ahead update and wait for the rest of their
 // predecessors inside (plan.cpp); predecessor entries then carry the fields
 // of depcode.hpp.
-// lookahead: extra priority weight of the update subtasks on the column
-// right of their panel (j = k + 1), which the next column's panel tasks
-// wait for.
 void make_exec_plan(const Plan& plan, int nslab, int order, const double w[6], ExecPlan& ex, int pblk = 1,
-                    bool stream = false, bool early = false, double lookahead = 0.0);
+                    bool stream = false, bool early = false, int workers = 0);
 
 // One executor plan for the factorization and Q^T B together: the
 // subtasks of fac (built by make_exec_plan with the same nslab; their

@@ -130,10 +130,11 @@ def test_level_executor_matches_persistent(torch_cuda, monkeypatch):
     monkeypatch.setenv("TQR_EXEC", "persistent")
 
 
-@pytest.mark.parametrize("order", ["asap", "alap"])
+@pytest.mark.parametrize("order", ["asap", "alap", "bl"])
 def test_other_dispatch_orders_match(torch_cuda, monkeypatch, order):
-    """The default dispatch order is largest bottom level first; the ASAP
-    and ALAP orders must give the same factors."""
+    """The default dispatch order is the start order of a simulated list
+    schedule; the ASAP, ALAP and plain bottom-level orders must give the
+    same factors."""
     _say("%s order" % order)
     A = tqr_inputs.gaussian(512, 256, seed=4)
     monkeypatch.setenv("TQR_ORDER", order)

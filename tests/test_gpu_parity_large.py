@@ -363,17 +363,19 @@ def test_early_release_bit_identical(torch_cuda, case, monkeypatch):
     look-ahead (and wait for the rest of their predecessors inside) do the
     same arithmetic in the same order on every tile element as subtasks
     that wait for whole predecessors: the factors must agree bit for bit.
-    The level-synchronous executor (which runs the same plan level by level)
-    must agree too."""
+    So must the plain bottom-level dispatch order and the level-synchronous
+    executor (which runs the same plan level by level)."""
     import paper_1104_4475_amd as tqr
     from paper_1104_4475_amd import _lib
     m, n, nb, tree, bs, kern, upd = case
     _say("early release vs whole blocks %s" % (case,))
     A = _gpu(torch_cuda, tqr_inputs.gaussian(m, n, seed=98))
     out = []
-    for early, path in (("0", "persistent"), ("1", "persistent"), ("1", "level")):
+    for early, path, order in (("0", "persistent", "sim"), ("1", "persistent", "sim"), ("1", "persistent", "bl"),
+                               ("1", "level", "sim")):
         monkeypatch.setenv("TQR_EARLY", early)
         monkeypatch.setenv("TQR_EXEC", path)
+        monkeypatch.setenv("TQR_ORDER", order)
         F = tqr.factor(A, nb, tree, bs, kern, upd)
         F.sync()
         sub, deps = F.exec_plan()
