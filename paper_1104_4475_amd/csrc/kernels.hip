@@ -119,6 +119,49 @@ __device__ __forceinline__ double wave_sum(double v) {
   return lane_d(v, 63);
 }
 
+// x[l] + x[l ^ 16] (SWAP = 16) or x[l] + x[l ^ 32] (SWAP = 32) in every lane.
+// The gfx950 lane swaps exchange the odd rows of their first operand with
+// the even rows of their second (16) or the upper half of the first with
+// the lower half of the second (32); with both operands x, the two results
+// hold, in every lane, x[l] and x[l ^ SWAP] in some order (measured).
+template <int SWAP>
+__device__ __forceinline__ double add_swapped(double x) {
+  const long long b = __double_as_longlong(x);
+  const unsigned lo = static_cast<unsigned>(b), hi = static_cast<unsigned>(b >> 32);
+  const auto l2 = SWAP == 16 ? __builtin_amdgcn_permlane16_swap(lo, lo, false, false)
+                             : __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto h2 = SWAP == 16 ? __builtin_amdgcn_permlane16_swap(hi, hi, false, false)
+                             : __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  const double f = __longlong_as_double((static_cast<long long>(h2[0]) << 32) | l2[0]);
+  const double g = __longlong_as_double((static_cast<long long>(h2[1]) << 32) | l2[1]);
+  return f + g;
+}
+
+// The four sums over the 64 lanes of a wave of a[0..3], returned in a
+// (uniform).  A butterfly over each quad leaves lane l with the quad's sum
+// of value m(l) = 2 (l & 1) + ((l >> 1) & 1): lanes exchange the two values
+// they do not keep, so four values cost two steps instead of eight.  Row
+// rotations by 4 and 8 then add the lanes of the row with the same l & 3,
+// and the 16- and 32-lane swaps the other rows: lanes 0, 2, 1, 3 then hold
+// the totals of values 0, 1, 2, 3.
+__device__ __forceinline__ void wave_sum4(double (&a)[4]) {
+  const int l = lane_id();
+  const bool odd = (l & 1) != 0, up = (l & 2) != 0;
+  // lane pairs (xor 1): even lanes keep values 0 and 1, odd lanes 2 and 3
+  const double b0 = (odd ? a[2] : a[0]) + dpp_d<0xb1, 0xf>(odd ? a[0] : a[2]);
+  const double b1 = (odd ? a[3] : a[1]) + dpp_d<0xb1, 0xf>(odd ? a[1] : a[3]);
+  // lane pairs (xor 2): lanes with bit 1 clear keep b0, the others b1
+  double c = (up ? b1 : b0) + dpp_d<0x4e, 0xf>(up ? b0 : b1);
+  c += dpp_d<0x124, 0xf>(c);  // row_ror:4
+  c += dpp_d<0x128, 0xf>(c);  // row_ror:8
+  c = add_swapped<16>(c);
+  c = add_swapped<32>(c);
+  a[0] = lane_d(c, 0);
+  a[1] = lane_d(c, 2);
+  a[2] = lane_d(c, 1);
+  a[3] = lane_d(c, 3);
+}
+
 __device__ __forceinline__ double* tile_ptr(const ExecArgs& a, int r, int c) {
   return a.tiles + (static_cast<size_t>(c) * a.p + r) * static_cast<size_t>(a.nb) * a.nb;
 }
@@ -1170,8 +1213,8 @@ __device__ __forceinline__ void wide_update_task(const unsigned char* img, doubl
 // updates that column first and computes reflector jj + 1 at once, before
 // its other columns, so one barrier per column separates consecutive
 // reflectors and the chain between them is a single column update.  A
-// wave's other columns take their dot products with v together, so their
-// wavefront reductions overlap.  For the pair kernels the rows of the
+// wave's other columns take their dot products with v together and reduce
+// them in one pass (wave_sum4).  For the pair kernels the rows of the
 // triangle block stay in registers during the loop (lane a holds row a of
 // each owned column) and go back to Rs at the end.
 template <int NB, int PAIR>
@@ -1280,12 +1323,14 @@ __device__ __forceinline__ void panel_factor(double* Ps, int ldp, int K, double*
       }
       if (t != 0.0) {
         // this wave's columns right of nxt: the dot products first, then
-        // their reductions side by side, then the updates
+        // one reduction of all of them, then the updates
         double dd[4];
 #pragma unroll
-        for (int q2 = q; q2 < 4; ++q2) dd[q2] = dot(q2, v);
-#pragma unroll
-        for (int q2 = q; q2 < 4; ++q2) dd[q2] = wave_sum(dd[q2]);
+        for (int q2 = 0; q2 < 4; ++q2) dd[q2] = q2 < q ? 0.0 : dot(q2, v);
+        if (q < 3)
+          wave_sum4(dd);
+        else
+          dd[3] = wave_sum(dd[3]);
 #pragma unroll
         for (int q2 = q; q2 < 4; ++q2) {
           const int c = wave + NWAVES * q2;
