@@ -193,7 +193,7 @@ struct tqr_factors {
   double* Tp = nullptr;
   unsigned char* imgg = nullptr;  // low-precision reflector images (nb >= 128, upd != FP64)
   unsigned char* imgp = nullptr;
-  int32_t* ctl = nullptr;  // [0] ticket, [1] executor err, [2] solve err, [3..3+4q) solve flags
+  int32_t* ctl = nullptr;  // [0] ticket, [1] executor err, [2] solve err, [3..3+8q) solve flags
   ExecPlan exec_host;      // host copy of the factorization plan (joint plans are built from it)
   DevPlan fused;           // factorization + Q^T B (16 columns) in one executor plan
   double* Bt16 = nullptr;  // packed right-hand sides of the joint plan (p row tiles of nb x 16)
@@ -326,7 +326,7 @@ const double* diag_inverses(const tqr_factors* F, hipStream_t s, hipError_t* e) 
     }
   }
   if (!F->wn) {
-    *e = hipMalloc(&F->wn, bytes);
+    *e = hipMalloc(&F->wn, 2 * bytes);  // coupling at distances 1 and 2
     if (*e != hipSuccess) {
       F->wn = nullptr;
       return nullptr;
@@ -371,7 +371,7 @@ hipError_t solve_rt(const tqr_factors* F, double* X, int64_t ldx, int64_t nrhs, 
       }
     }
     if (!F->wnt) {
-      e = hipMalloc(&F->wnt, static_cast<size_t>(F->q) * tile * sizeof(double));
+      e = hipMalloc(&F->wnt, 2 * static_cast<size_t>(F->q) * tile * sizeof(double));  // distances 1 and 2
       if (e != hipSuccess) {
         F->wnt = nullptr;
         return e;
@@ -462,7 +462,7 @@ int create(const tqr_opts* o, tqr_factors** out, ExecPlan* keep = nullptr) {
   if (!hip_ok(hipMalloc(&F->tiles, ntile * nbb * nbb * sizeof(double))) ||
       !hip_ok(hipMalloc(&F->Tg, ntile * tqr::IB * nbb * sizeof(double))) ||
       !hip_ok(hipMalloc(&F->Tp, ntile * tqr::IB * nbb * sizeof(double))) ||
-      !hip_ok(hipMalloc(&F->ctl, (3 + 4 * F->q) * sizeof(int32_t))))
+      !hip_ok(hipMalloc(&F->ctl, (3 + 8 * F->q) * sizeof(int32_t))))
     return TQR_ENOMEM;
   HIP_TRY(hipMemset(F->Tg, 0, ntile * tqr::IB * nbb * sizeof(double)));
   HIP_TRY(hipMemset(F->Tp, 0, ntile * tqr::IB * nbb * sizeof(double)));
@@ -470,7 +470,7 @@ int create(const tqr_opts* o, tqr_factors** out, ExecPlan* keep = nullptr) {
     const size_t ib = ntile * static_cast<size_t>(F->nb / tqr::IB) * tqr::image_bytes(F->nb, o->upd);
     if (!hip_ok(hipMalloc(&F->imgg, ib)) || !hip_ok(hipMalloc(&F->imgp, ib))) return TQR_ENOMEM;
   }
-  HIP_TRY(hipMemset(F->ctl, 0, (3 + 4 * F->q) * sizeof(int32_t)));
+  HIP_TRY(hipMemset(F->ctl, 0, (3 + 8 * F->q) * sizeof(int32_t)));
   F->grid = device_cus() * tqr::persistent_occupancy(F->nb, F->o.upd);
   *out = F.release();
   return TQR_OK;

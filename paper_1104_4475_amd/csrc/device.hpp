@@ -102,10 +102,10 @@ hipError_t launch_unpack_b(const double* Bt, double* B, int64_t ldb, int64_t nrh
 // X = R^{-1} Y in place (Y: n x nrhs, column-major).  Rinv: inverses of
 // the q diagonal tiles from launch_trinv, or null (substitution inside the
 // diagonal tiles).  Wn: coupling tiles from launch_coupling (trans 0), or
-// null; used with Rinv only.  flags: 4 q int32 owned by the caller (one per
-// tile row and part of a row), compared
-// with the per-launch epoch (*epoch is advanced); err: set when a wait
-// exceeds spin_ticks.
+// null; used with Rinv only.  flags: 8 q int32 owned by the caller (per
+// tile row and part of a row: the part's rows of X, then its partial sum),
+// compared with the per-launch epoch (*epoch is advanced); err: set when a
+// wait exceeds spin_ticks.
 hipError_t launch_trsm_upper(const double* tiles, const double* Rinv, const double* Wn, int p, int q, int nb, double* Y,
                              int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch, int32_t* err,
                              int64_t spin_ticks, hipStream_t s);
@@ -115,8 +115,9 @@ hipError_t launch_trsm_upper(const double* tiles, const double* Rinv, const doub
 hipError_t launch_trsm_upper_t(const double* tiles, const double* Rt, const double* Rinv, const double* Wn, int p,
                                int q, int nb, double* Y, int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch,
                                int32_t* err, int64_t spin_ticks, hipStream_t s);
-// Wn (q tiles) = coupling tiles -op(R_ii)^{-1} N_i of the solve with R
-// (trans 0: N_i = R_{i,i+1}) or R^T (trans 1: N_i = tile (i, i-1) of Rt).
+// Wn = coupling tiles -op(R_ii)^{-1} N_i of the solve with R (trans 0: N_i
+// = R_{i,i+d}) or R^T (trans 1: N_i = tile (i, i-d) of Rt): tiles 0 .. q - 1
+// for d = 1 and, at nb >= 128, tiles q .. 2q - 1 for d = 2 (2q tiles).
 hipError_t launch_coupling(const double* tiles, const double* Rt, int p, int q, int nb, int trans, double* Wn,
                            hipStream_t s);
 // Rt (q x q tile grid, tiles (i, k) with k <= i) = tiles of R^T, and RinvT

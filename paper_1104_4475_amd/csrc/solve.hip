@@ -325,21 +325,21 @@ __global__ __launch_bounds__(TR_THREADS) void trinv_kernel(const double* tiles, 
 
 // Coupling tiles of the triangular solves: block (i, c) writes columns
 // 16 c .. 16 c + 15 of Wn_i = -op(R_ii)^{-1} N_i into tile i of Wn, where
-// N_i is the tile coupling row i to the row solved just before it: for R
-// (back substitution) N_i = R_{i,i+1}, i < q - 1; for R^T (forward) N_i =
-// (R^T)_{i,i-1}, tile (i, i - 1) of Rt, i >= 1.  By diag_solve on the
-// columns of N_i.
+// N_i is the tile coupling row i to the row solved dist rows before it: for
+// R (back substitution) N_i = R_{i,i+dist}, i < q - dist; for R^T (forward)
+// N_i = (R^T)_{i,i-dist}, tile (i, i - dist) of Rt, i >= dist.  By
+// diag_solve on the columns of N_i.
 template <int NB, bool TRANS>
 __global__ __launch_bounds__(TR_THREADS) void coupling_kernel(const double* tiles, const double* Rt, int p, int q,
-                                                              double* Wn) {
+                                                              int dist, double* Wn) {
   __shared__ double ys[NB * TR_COLS];
   __shared__ double ps[TR_THREADS * TR_COLS];
-  const int i = TRANS ? static_cast<int>(blockIdx.x) + 1 : static_cast<int>(blockIdx.x);
+  const int i = TRANS ? static_cast<int>(blockIdx.x) + dist : static_cast<int>(blockIdx.x);
   const int c0 = blockIdx.y * TR_COLS;
   const int tid = threadIdx.x, lane = tid & 63, rr = lane & 31, half = lane >> 5;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const double* N = TRANS ? Rt + (static_cast<size_t>(i - 1) * q + i) * NB * NB
-                          : tiles + (static_cast<size_t>(i + 1) * p + i) * NB * NB;
+  const double* N = TRANS ? Rt + (static_cast<size_t>(i - dist) * q + i) * NB * NB
+                          : tiles + (static_cast<size_t>(i + dist) * p + i) * NB * NB;
   for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) ys[e] = N[static_cast<size_t>(c0) * NB + e];
   const double* Rd = tiles + (static_cast<size_t>(i) * p + i) * NB * NB;
   double xinv[32];
@@ -368,21 +368,15 @@ __global__ __launch_bounds__(TR_THREADS) void coupling_kernel(const double* tile
 // row i forms z_i = op(inv(R_ii)) (Y_i - sum over the rows solved before
 // the last one) before it waits for that last row, then X_i = z_i + Wn_i
 // X_last: one tile product per step on the solve's critical chain instead
-// of two.  GP > 1 (with Wn): GP workgroups per tile row, each computing
-// the whole of z_i (off the chain) but only its NB / GP = 64 rows of X_i
-// from the coupling product, so that product on the chain reads 1/GP of
-// Wn_i; flags are per (row, part).  The right-hand sides are read from Yin
-// (ld ldin): with GP > 1 a copy of Y, since a part of a row is written
-// while other parts of the row may still read it.  Up to TR_COLS
-// right-hand sides per launch.  A wait longer than spin_ticks sets *err and
-// the workgroup leaves.
-template <int NB, bool TRANS, bool INV, int GP>
+// of two (trsm_part_kernel splits each row over several workgroups at
+// NB >= 128).  Up to TR_COLS right-hand sides per launch.  A wait longer
+// than spin_ticks sets *err and the workgroup leaves.
+template <int NB, bool TRANS, bool INV>
 __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* tiles, const double* Rt,
                                                                const double* Rinv, const double* Wn, int p, int q,
-                                                               const double* Yin, int64_t ldin, double* Y,
-                                                               int64_t ldy, int nc, int32_t* flags, int32_t epoch,
-                                                               int64_t spin_ticks, int32_t* err) {
-  static_assert(GP == 1 || NB / GP == 64, "parts of 64 rows");
+                                                               double* Y, int64_t ldy, int nc, int32_t* flags,
+                                                               int32_t epoch, int64_t spin_ticks, int32_t* err) {
+  constexpr int GP = 1;
   __shared__ double ys[NB * TR_COLS];
   __shared__ double xs[NB * TR_COLS];
   __shared__ double ps[TR_THREADS * TR_COLS];  // partial sums of tr_update; block inverses for TRANS
@@ -393,7 +387,7 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
   const int64_t r0 = static_cast<int64_t>(i) * NB;
   for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
     const int c = e / NB, r = e % NB;
-    ys[e] = c < nc ? Yin[c * ldin + r0 + r] : 0.0;
+    ys[e] = c < nc ? Y[c * ldy + r0 + r] : 0.0;
   }
   if (tid == 0) s_abort = 0;
   const double* Rd = tiles + (static_cast<size_t>(i) * p + i) * NB * NB;
@@ -458,12 +452,9 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
       tile_gemv<NB, TRANS>(ys, xs, Rinv + static_cast<size_t>(i) * NB * NB, nc, ps);
     sign = -1.0;
     if (coupled) {
-      // ys = -z_i - Wn_i X_last = -X_i (this part's rows with GP > 1).
+      // ys = -z_i - Wn_i X_last = -X_i.
       if (!fetch(k_end)) return;
-      if (GP > 1)
-        rows_gemv<NB, 64>(ys, xs, Wn + static_cast<size_t>(i) * NB * NB, part * 64, nc, ps);
-      else
-        tile_gemv<NB, false>(ys, xs, Wn + static_cast<size_t>(i) * NB * NB, nc, ps);
+      tile_gemv<NB, false>(ys, xs, Wn + static_cast<size_t>(i) * NB * NB, nc, ps);
     }
   } else {
     diag_solve<NB, TRANS>(ys, Rd, xinv, ps, nc, wave, rr, half);
@@ -476,6 +467,112 @@ __global__ __launch_bounds__(TR_THREADS) void trsm_wave_kernel(const double* til
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   if (tid == 0) __hip_atomic_store(flags + i * GP + part, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// The solve of trsm_wave_kernel with the inverses and two coupling tiles per
+// row, at NB >= 128: GP = NB / 64 workgroups per tile row, part g owning
+// rows 64 g .. 64 g + 63 of the row.  With Wn_i = -op(R_ii)^{-1} N_i (the
+// row solved just before) and Wn2_i = -op(R_ii)^{-1} N2_i (the one before
+// it):  X_i = op(R_ii)^{-1} w_i + Wn2_i X_{i+-2} + Wn_i X_{i+-1},  w_i = Y_i
+// - sum of op(R)_ik X_k over the rows solved earlier still.  Each part
+// forms its rows of w_i as those rows arrive (reading its 64 rows of each
+// tile), publishes them (wbuf, wflags), gathers the whole w_i from the
+// other parts and applies its rows of the inverse: all of this a step
+// before X_{i+-1} is known.  After X_{i+-2} comes one 64-row product with
+// Wn2_i, and after X_{i+-1} one with Wn_i: the only product on the solve's
+// chain reads a quarter of a tile at NB = 256.  Y is solved in place: a
+// part reads only its own rows of Y_i, which no other workgroup writes
+// before every part of the row has published its partial sum.
+template <int NB, bool TRANS, int GP>
+__global__ __launch_bounds__(TR_THREADS) void trsm_part_kernel(const double* tiles, const double* Rt,
+                                                               const double* Rinv, const double* Wn, const double* Wn2,
+                                                               int p, int q, double* Y, int64_t ldy, int nc,
+                                                               int32_t* flags,
+                                                               int32_t* wflags, double* wbuf, int32_t epoch,
+                                                               int64_t spin_ticks, int32_t* err) {
+  static_assert(GP >= 2 && NB / GP == 64, "parts of 64 rows");
+  __shared__ double ys[NB * TR_COLS];
+  __shared__ double xs[NB * TR_COLS];
+  __shared__ double ps[TR_THREADS * TR_COLS];
+  __shared__ int s_abort;
+  const int blk = static_cast<int>(blockIdx.x) / GP, part = static_cast<int>(blockIdx.x) % GP;
+  const int i = TRANS ? blk : q - 1 - blk;
+  const int tid = threadIdx.x, rlo = part * 64;
+  const int64_t r0 = static_cast<int64_t>(i) * NB;
+  for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
+    const int c = e / NB, r = e % NB;
+    ys[e] = (c < nc && r >= rlo && r < rlo + 64) ? Y[c * ldy + r0 + r] : 0.0;
+  }
+  if (tid == 0) s_abort = 0;
+  __syncthreads();
+  // Wait until every part of row k has set its flag in fl, then xs = the
+  // NB x nc block at src (ld lds); false when the wait failed.
+  auto gather = [&](const int32_t* fl, int k, const double* src, int64_t lds) {
+    if (tid == 0) {
+      const uint64_t t0 = wall_clock64();
+      for (int g = 0; g < GP && !s_abort; ++g) {
+        while (__hip_atomic_load(const_cast<int32_t*>(fl) + k * GP + g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) !=
+               epoch) {
+          if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+              static_cast<int64_t>(wall_clock64() - t0) > spin_ticks) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_abort = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+    }
+    __syncthreads();
+    if (__builtin_amdgcn_readfirstlane(s_abort)) return false;
+    for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) {
+      const int c = e / NB, r = e % NB;
+      xs[e] = c < nc ? ld_coh(src + c * lds + r) : 0.0;
+    }
+    __syncthreads();
+    return true;
+  };
+  auto row_x = [&](int k) { return gather(flags, k, Y + static_cast<int64_t>(k) * NB, ldy); };
+  // Stores this part's rows of ys (times sign) at dst (ld ldd), then sets
+  // its flag in fl.
+  auto publish = [&](double* dst, int64_t ldd, double sign, int32_t* fl) {
+    for (int e = tid; e < 64 * TR_COLS; e += TR_THREADS) {
+      const int c = e / 64, r = rlo + e % 64;
+      if (c < nc) st_coh(dst + c * ldd + r, sign * ys[c * NB + r]);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(fl + i * GP + part, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  };
+  // 1. This part's rows of w_i.
+  const int near2 = TRANS ? i - 2 : i + 2;  // rows coupled through Wn2 / Wn
+  const int near1 = TRANS ? i - 1 : i + 1;
+  const int k_first = TRANS ? 0 : q - 1;
+  for (int k = k_first; TRANS ? (k < near2) : (k > near2); k += TRANS ? 1 : -1) {
+    if (!row_x(k)) return;
+    const double* R = TRANS ? Rt + (static_cast<size_t>(k) * q + i) * NB * NB
+                            : tiles + (static_cast<size_t>(k) * p + i) * NB * NB;
+    rows_gemv<NB, 64>(ys, xs, R, rlo, nc, ps);
+  }
+  // 2. The whole w_i from every part, then ys = -(this part's rows of
+  // op(R_ii)^{-1} w_i).
+  double* wrow = wbuf + static_cast<int64_t>(i) * NB;
+  const int64_t ldw = static_cast<int64_t>(q) * NB;
+  publish(wrow, ldw, 1.0, wflags);
+  if (!gather(wflags, i, wrow, ldw)) return;
+  for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) ys[e] = 0.0;
+  __syncthreads();
+  rows_gemv<NB, 64>(ys, xs, Rinv + static_cast<size_t>(i) * NB * NB, rlo, nc, ps);
+  // 3. ys -= Wn2_i X_near2 and Wn_i X_near1 (this part's rows): ys = -X_i.
+  if (TRANS ? near2 >= 0 : near2 < q) {
+    if (!row_x(near2)) return;
+    rows_gemv<NB, 64>(ys, xs, Wn2 + static_cast<size_t>(i) * NB * NB, rlo, nc, ps);
+  }
+  if (TRANS ? near1 >= 0 : near1 < q) {
+    if (!row_x(near1)) return;
+    rows_gemv<NB, 64>(ys, xs, Wn + static_cast<size_t>(i) * NB * NB, rlo, nc, ps);
+  }
+  publish(Y + r0, ldy, -1.0, flags);
 }
 
 // Tile transposes for the R^T solve: block (a, b), a >= b, writes
@@ -639,51 +736,53 @@ template <bool TRANS>
 static hipError_t trsm_launch(const double* tiles, const double* Rt, const double* Rinv, const double* Wn, int p, int q,
                               int nb, double* Y, int64_t ldy, int64_t nrhs, int32_t* flags, int32_t* epoch,
                               int32_t* err, int64_t spin_ticks, hipStream_t s) {
-  // Parts per tile row: NB / 64 workgroups with the coupling tiles at
-  // NB >= 128, else one; then the right-hand sides are read from a copy.
-  const int gp = (Rinv && Wn && nb >= 128) ? nb / 64 : 1;
+  // Parts per tile row: NB / 64 workgroups with the inverses and coupling
+  // tiles at NB >= 128 (trsm_part_kernel, which exchanges partial sums
+  // through wbuf, n x TR_COLS), else one (trsm_wave_kernel).
+  const int gp = (Rinv && Wn && nb >= 128 && (!TRANS || Rt)) ? nb / 64 : 1;
   const int64_t n = static_cast<int64_t>(q) * nb;
-  double* Ycopy = nullptr;
+  double* wbuf = nullptr;
   if (gp > 1) {
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&Ycopy), static_cast<size_t>(n) * nrhs * sizeof(double), s);
-    if (e == hipSuccess)
-      e = hipMemcpy2DAsync(Ycopy, n * sizeof(double), Y, ldy * sizeof(double), n * sizeof(double), nrhs,
-                           hipMemcpyDeviceToDevice, s);
-    if (e != hipSuccess) {
-      if (Ycopy) (void)hipFreeAsync(Ycopy, s);
-      return e;
-    }
+    const hipError_t e =
+        hipMallocAsync(reinterpret_cast<void**>(&wbuf), static_cast<size_t>(n) * TR_COLS * sizeof(double), s);
+    if (e != hipSuccess) return e;
   }
-  for (int64_t c0 = 0; c0 < nrhs; c0 += TR_COLS) {
+  hipError_t status = hipSuccess;
+  for (int64_t c0 = 0; c0 < nrhs && status == hipSuccess; c0 += TR_COLS) {
     const int nc = static_cast<int>(nrhs - c0 < TR_COLS ? nrhs - c0 : TR_COLS);
     const int32_t ep = ++*epoch;
     double* Yc = Y + c0 * ldy;
-    const double* Yi = gp > 1 ? Ycopy + c0 * n : Yc;
-    const int64_t ldi = gp > 1 ? n : ldy;
     switch (nb * 4 + (Rinv ? 2 : 0) + (gp > 1 ? 1 : 0)) {
-#define TQR_TRSM(NBV, INVV, GPV)                                                                                  \
-  case NBV * 4 + INVV * 2 + (GPV > 1 ? 1 : 0):                                                                   \
-    hipLaunchKernelGGL((trsm_wave_kernel<NBV, TRANS, INVV, GPV>), dim3(q * GPV), dim3(TR_THREADS), 0, s, tiles, Rt, \
-                       Rinv, Wn, p, q, Yi, ldi, Yc, ldy, nc, flags, ep, spin_ticks, err);                        \
+#define TQR_TRSM(NBV, INVV)                                                                                       \
+  case NBV * 4 + INVV * 2:                                                                                        \
+    hipLaunchKernelGGL((trsm_wave_kernel<NBV, TRANS, INVV>), dim3(q), dim3(TR_THREADS), 0, s, tiles, Rt, Rinv, Wn, \
+                       p, q, Yc, ldy, nc, flags, ep, spin_ticks, err);                                           \
     break;
-      TQR_TRSM(32, 0, 1)
-      TQR_TRSM(32, 1, 1)
-      TQR_TRSM(64, 0, 1)
-      TQR_TRSM(64, 1, 1)
-      TQR_TRSM(128, 0, 1)
-      TQR_TRSM(128, 1, 1)
-      TQR_TRSM(128, 1, 2)
-      TQR_TRSM(256, 0, 1)
-      TQR_TRSM(256, 1, 1)
-      TQR_TRSM(256, 1, 4)
+      TQR_TRSM(32, 0)
+      TQR_TRSM(32, 1)
+      TQR_TRSM(64, 0)
+      TQR_TRSM(64, 1)
+      TQR_TRSM(128, 0)
+      TQR_TRSM(128, 1)
+      TQR_TRSM(256, 0)
+      TQR_TRSM(256, 1)
 #undef TQR_TRSM
+#define TQR_TRSM_PART(NBV, GPV)                                                                                \
+  case NBV * 4 + 2 + 1:                                                                                        \
+    hipLaunchKernelGGL((trsm_part_kernel<NBV, TRANS, GPV>), dim3(q * GPV), dim3(TR_THREADS), 0, s, tiles, Rt,   \
+                       Rinv, Wn, Wn + static_cast<size_t>(q) * NBV * NBV, p, q, Yc, ldy, nc, flags, flags + 4 * q, \
+                       wbuf, ep, spin_ticks, err);                                                             \
+    break;
+      TQR_TRSM_PART(128, 2)
+      TQR_TRSM_PART(256, 4)
+#undef TQR_TRSM_PART
       default:
-        if (Ycopy) (void)hipFreeAsync(Ycopy, s);
-        return hipErrorInvalidValue;
+        status = hipErrorInvalidValue;
     }
   }
-  if (Ycopy) (void)hipFreeAsync(Ycopy, s);
-  return hipGetLastError();
+  if (status == hipSuccess) status = hipGetLastError();
+  if (wbuf) (void)hipFreeAsync(wbuf, s);
+  return status;
 }
 
 hipError_t launch_trsm_upper(const double* tiles, const double* Rinv, const double* Wn, int p, int q, int nb, double* Y,
@@ -700,26 +799,33 @@ hipError_t launch_trsm_upper_t(const double* tiles, const double* Rt, const doub
 
 hipError_t launch_coupling(const double* tiles, const double* Rt, int p, int q, int nb, int trans, double* Wn,
                            hipStream_t s) {
-  if (q < 2) return hipSuccess;
   if (nb % TR_COLS != 0) return hipErrorInvalidValue;
-  const dim3 grid(static_cast<unsigned>(q - 1), static_cast<unsigned>(nb / TR_COLS));
-  switch (nb * 2 + (trans ? 1 : 0)) {
-#define TQR_CPL(NBV, TV)                                                                              \
-  case NBV * 2 + TV:                                                                                  \
-    hipLaunchKernelGGL((coupling_kernel<NBV, TV != 0>), grid, dim3(TR_THREADS), 0, s, tiles, Rt, p, q, Wn); \
+  // Distance 1 into tiles 0 .. q - 1 of Wn; at nb >= 128 also distance 2
+  // into tiles q .. 2q - 1 (the solves there couple two rows).
+  const int maxd = nb >= 128 ? 2 : 1;
+  for (int dist = 1; dist <= maxd && dist < q; ++dist) {
+    const dim3 grid(static_cast<unsigned>(q - dist), static_cast<unsigned>(nb / TR_COLS));
+    double* out = Wn + static_cast<size_t>(dist - 1) * q * nb * nb;
+    switch (nb * 2 + (trans ? 1 : 0)) {
+#define TQR_CPL(NBV, TV)                                                                                       \
+  case NBV * 2 + TV:                                                                                           \
+    hipLaunchKernelGGL((coupling_kernel<NBV, TV != 0>), grid, dim3(TR_THREADS), 0, s, tiles, Rt, p, q, dist, out); \
     break;
-    TQR_CPL(32, 0)
-    TQR_CPL(32, 1)
-    TQR_CPL(64, 0)
-    TQR_CPL(64, 1)
-    TQR_CPL(128, 0)
-    TQR_CPL(128, 1)
-    TQR_CPL(256, 0)
-    TQR_CPL(256, 1)
+      TQR_CPL(32, 0)
+      TQR_CPL(32, 1)
+      TQR_CPL(64, 0)
+      TQR_CPL(64, 1)
+      TQR_CPL(128, 0)
+      TQR_CPL(128, 1)
+      TQR_CPL(256, 0)
+      TQR_CPL(256, 1)
 #undef TQR_CPL
-    default: return hipErrorInvalidValue;
+      default: return hipErrorInvalidValue;
+    }
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
   }
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t launch_transpose_r(const double* tiles, const double* Rinv, int p, int q, int nb, double* Rt,
