@@ -333,7 +333,7 @@ const double* diag_inverses(const tqr_factors* F, hipStream_t s, hipError_t* e) 
     }
   }
   *e = tqr::launch_trinv(F->tiles, F->p, F->q, F->nb, F->rinv, s);
-  if (*e == hipSuccess) *e = tqr::launch_coupling(F->tiles, nullptr, F->p, F->q, F->nb, 0, F->wn, s);
+  if (*e == hipSuccess) *e = tqr::launch_coupling(F->tiles, nullptr, F->rinv, F->p, F->q, F->nb, 0, F->wn, s);
   F->rinv_ok = *e == hipSuccess;
   return F->rinv;
 }
@@ -378,7 +378,7 @@ hipError_t solve_rt(const tqr_factors* F, double* X, int64_t ldx, int64_t nrhs, 
       }
     }
     e = tqr::launch_transpose_r(F->tiles, ri, F->p, F->q, F->nb, F->rt, F->rinvt, s);
-    if (e == hipSuccess) e = tqr::launch_coupling(F->tiles, F->rt, F->p, F->q, F->nb, 1, F->wnt, s);
+    if (e == hipSuccess) e = tqr::launch_coupling(F->tiles, F->rt, F->rinvt, F->p, F->q, F->nb, 1, F->wnt, s);
     if (e != hipSuccess) return e;
     F->rt_ok = true;
   }

@@ -117,9 +117,11 @@ hipError_t launch_trsm_upper_t(const double* tiles, const double* Rt, const doub
                                int32_t* err, int64_t spin_ticks, hipStream_t s);
 // Wn = coupling tiles -op(R_ii)^{-1} N_i of the solve with R (trans 0: N_i
 // = R_{i,i+d}) or R^T (trans 1: N_i = tile (i, i-d) of Rt): tiles 0 .. q - 1
-// for d = 1 and, at nb >= 128, tiles q .. 2q - 1 for d = 2 (2q tiles).
-hipError_t launch_coupling(const double* tiles, const double* Rt, int p, int q, int nb, int trans, double* Wn,
-                           hipStream_t s);
+// for d = 1 and, at nb >= 128, tiles q .. 2q - 1 for d = 2 (2q tiles).  Inv:
+// the diagonal-tile inverses of launch_trinv (trans 0) or their transposes
+// from launch_transpose_r (trans 1).
+hipError_t launch_coupling(const double* tiles, const double* Rt, const double* Inv, int p, int q, int nb, int trans,
+                           double* Wn, hipStream_t s);
 // Rt (q x q tile grid, tiles (i, k) with k <= i) = tiles of R^T, and RinvT
 // (q tiles) = transposes of the diagonal-tile inverses Rinv.
 hipError_t launch_transpose_r(const double* tiles, const double* Rinv, int p, int q, int nb, double* Rt,

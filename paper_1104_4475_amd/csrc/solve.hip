@@ -324,30 +324,41 @@ __global__ __launch_bounds__(TR_THREADS) void trinv_kernel(const double* tiles, 
 }
 
 // Coupling tiles of the triangular solves: block (i, c) writes columns
-// 16 c .. 16 c + 15 of Wn_i = -op(R_ii)^{-1} N_i into tile i of Wn, where
+// 16 c .. 16 c + 15 of Wn_i = -inv(op(R_ii)) N_i into tile i of Wn, where
 // N_i is the tile coupling row i to the row solved dist rows before it: for
 // R (back substitution) N_i = R_{i,i+dist}, i < q - dist; for R^T (forward)
-// N_i = (R^T)_{i,i-dist}, tile (i, i - dist) of Rt, i >= dist.  By
-// diag_solve on the columns of N_i.
+// N_i = (R^T)_{i,i-dist}, tile (i, i - dist) of Rt, i >= dist.  Inv holds
+// the inverses of the diagonal tiles (of R, or their transposes for R^T),
+// so the tile is one product: the 16 columns of N_i in LDS, thread t forms
+// row t % NB of TR_COLS / (TR_THREADS / NB) of them, reading the inverse's
+// rows coalesced.
 template <int NB, bool TRANS>
-__global__ __launch_bounds__(TR_THREADS) void coupling_kernel(const double* tiles, const double* Rt, int p, int q,
-                                                              int dist, double* Wn) {
-  __shared__ double ys[NB * TR_COLS];
-  __shared__ double ps[TR_THREADS * TR_COLS];
+__global__ __launch_bounds__(TR_THREADS) void coupling_kernel(const double* tiles, const double* Rt,
+                                                              const double* Inv, int p, int q, int dist, double* Wn) {
+  constexpr int CG = TR_THREADS / NB;  // column groups
+  constexpr int CPT = TR_COLS / CG;    // columns per thread
+  static_assert(CG >= 1 && CPT >= 1 && CPT * CG == TR_COLS, "column split");
+  __shared__ double ns[TR_COLS * NB];
   const int i = TRANS ? static_cast<int>(blockIdx.x) + dist : static_cast<int>(blockIdx.x);
   const int c0 = blockIdx.y * TR_COLS;
-  const int tid = threadIdx.x, lane = tid & 63, rr = lane & 31, half = lane >> 5;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int tid = threadIdx.x, r = tid % NB, cg = tid / NB;
   const double* N = TRANS ? Rt + (static_cast<size_t>(i - dist) * q + i) * NB * NB
                           : tiles + (static_cast<size_t>(i + dist) * p + i) * NB * NB;
-  for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) ys[e] = N[static_cast<size_t>(c0) * NB + e];
-  const double* Rd = tiles + (static_cast<size_t>(i) * p + i) * NB * NB;
-  double xinv[32];
-  block_inverse<NB, TRANS>(Rd, wave, rr, half, xinv, ps + wave * 32 * 32);
+  for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) ns[e] = N[static_cast<size_t>(c0) * NB + e];
   __syncthreads();
-  diag_solve<NB, TRANS>(ys, Rd, xinv, ps, TR_COLS, wave, rr, half);
+  const double* M = Inv + static_cast<size_t>(i) * NB * NB;
+  double acc[CPT];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) acc[c] = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < NB; ++k) {
+    const double a = M[static_cast<size_t>(k) * NB + r];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) acc[c] += a * ns[(cg * CPT + c) * NB + k];
+  }
   double* out = Wn + static_cast<size_t>(i) * NB * NB + static_cast<size_t>(c0) * NB;
-  for (int e = tid; e < NB * TR_COLS; e += TR_THREADS) out[e] = -ys[e];
+#pragma unroll
+  for (int c = 0; c < CPT; ++c) out[static_cast<size_t>(cg * CPT + c) * NB + r] = -acc[c];
 }
 
 // X = R^{-1} Y (TRANS = false) or X = R^{-T} Y (TRANS = true) in place in Y
@@ -797,8 +808,8 @@ hipError_t launch_trsm_upper_t(const double* tiles, const double* Rt, const doub
   return trsm_launch<true>(tiles, Rt, Rinv, Wn, p, q, nb, Y, ldy, nrhs, flags, epoch, err, spin_ticks, s);
 }
 
-hipError_t launch_coupling(const double* tiles, const double* Rt, int p, int q, int nb, int trans, double* Wn,
-                           hipStream_t s) {
+hipError_t launch_coupling(const double* tiles, const double* Rt, const double* Inv, int p, int q, int nb, int trans,
+                           double* Wn, hipStream_t s) {
   if (nb % TR_COLS != 0) return hipErrorInvalidValue;
   // Distance 1 into tiles 0 .. q - 1 of Wn; at nb >= 128 also distance 2
   // into tiles q .. 2q - 1 (the solves there couple two rows).
@@ -809,7 +820,8 @@ hipError_t launch_coupling(const double* tiles, const double* Rt, int p, int q, 
     switch (nb * 2 + (trans ? 1 : 0)) {
 #define TQR_CPL(NBV, TV)                                                                                       \
   case NBV * 2 + TV:                                                                                           \
-    hipLaunchKernelGGL((coupling_kernel<NBV, TV != 0>), grid, dim3(TR_THREADS), 0, s, tiles, Rt, p, q, dist, out); \
+    hipLaunchKernelGGL((coupling_kernel<NBV, TV != 0>), grid, dim3(TR_THREADS), 0, s, tiles, Rt, Inv, p, q, dist, \
+                       out);                                                                                   \
     break;
       TQR_CPL(32, 0)
       TQR_CPL(32, 1)
