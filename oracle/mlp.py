@@ -9,10 +9,10 @@ and picks the argmin.
 Network: 13 inputs -> 64 -> 64 -> 1, ReLU hidden units, linear output, mean
 squared error loss, Adam (Kingma & Ba 2015, with bias correction).
 
-Features (13): log2 p, log2 q, log2 nb; one-hot of six algorithm classes
-(TS-FlatTree, TT-FlatTree, BinaryTree, Fibonacci, Greedy, PlasmaTree);
-log2 BS for PlasmaTree (0 otherwise); one-hot of three update precisions
-(FP64, FP32, BF16).
+Features (13): log2 p, log2 q, log2 nb; one-hot of five trees (FlatTree,
+BinaryTree, Fibonacci, Greedy, PlasmaTree); the kernel family (1 for TS
+kernels, 0 for TT); log2 BS for PlasmaTree (0 otherwise); one-hot of three
+update precisions (FP64, FP32, BF16).
 
 Parity: gradients pinned by central finite differences; the Adam step by its
 closed form on the first iteration (tests/test_oracle_mlp.py).
@@ -21,15 +21,17 @@ closed form on the first iteration (tests/test_oracle_mlp.py).
 import numpy as np
 
 N_IN, N_HID = 13, 64
-ALGO_TS_FLAT, ALGO_TT_FLAT, ALGO_BINARY, ALGO_FIB, ALGO_GREEDY, ALGO_PLASMA = range(6)
+ALGO_FLAT, ALGO_BINARY, ALGO_FIB, ALGO_GREEDY, ALGO_PLASMA = range(5)
+KERN_TT, KERN_TS = 0, 1
 
 
-def features(p, q, nb, algo, bs, prec):
+def features(p, q, nb, algo, kern, bs, prec):
     x = np.zeros(N_IN)
     x[0] = np.log2(p)
     x[1] = np.log2(q)
     x[2] = np.log2(nb)
     x[3 + algo] = 1.0
+    x[8] = float(kern)
     x[9] = np.log2(bs) if algo == ALGO_PLASMA else 0.0
     x[10 + prec] = 1.0
     return x

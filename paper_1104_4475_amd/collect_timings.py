@@ -1,10 +1,10 @@
 """Collect the selector's timing data on the current GPU.
 
   python -m paper_1104_4475_amd.collect_timings corpus OUT.csv --count 5000 --seed 11
-      random candidates (training corpus), columns p,q,nb,algo,bs,prec,ms
+      random candidates (training corpus), columns p,q,nb,algo,kern,bs,prec,ms
   python -m paper_1104_4475_amd.collect_timings heldout OUT.csv --count 200 --seed 12 [--first i --last j]
       exhaustive autotuner tables of held-out shapes, columns
-      shape,m,n,prec,nb,algo,bs,ms
+      shape,m,n,prec,nb,algo,kern,bs,ms
 
 Times are the executor kernel's duration (HIP events) of one factorization
 after one warm-up run on the same handle.
@@ -41,12 +41,12 @@ def main(argv=None):
     with open(a.out, "a", newline="") as fh:
         w = csv.writer(fh)
         if new:
-            w.writerow(["shape", "m", "n", "prec", "nb", "algo", "bs", "ms"])
+            w.writerow(["shape", "m", "n", "prec", "nb", "algo", "kern", "bs", "ms"])
         for s in range(a.first, last):
             m, n, prec = shapes[s]
             table = selector.exhaustive(m, n, prec, timer)
-            for (nb, algo, bs), ms in table.items():
-                w.writerow([s, m, n, prec, nb, algo, bs, "%.5f" % ms])
+            for (nb, algo, kern, bs), ms in table.items():
+                w.writerow([s, m, n, prec, nb, algo, kern, bs, "%.5f" % ms])
             fh.flush()
             log("shape %d: %d x %d prec %d, %d candidates" % (s, m, n, prec, len(table)))
     return 0

@@ -1,17 +1,20 @@
-"""Autotuner and learned selector of the reduction tree, PlasmaTree domain
-size and tile size.
+"""Autotuner and learned selector of the reduction tree, kernel family,
+PlasmaTree domain size and tile size.
 
 The paper tunes PlasmaTree's domain size BS by exhaustive search over
 measured runs (Sec. 4).  Here the exhaustive autotuner times every candidate
-(tree, BS, nb) of a shape on the GPU; the learned selector instead predicts
-log(makespan) of every candidate with a small multilayer perceptron
-(13 -> 64 -> 64 -> 1, trained on timings of the GPU executor) and picks the
-argmin, so a shape can be tuned without running its candidates.  The
-network's forward pass, gradient and Adam step are the library's HIP kernels
-(tiledqr_mlp_*); this module only encodes features and drives the loops.
+(nb, tree, kernel family, BS) of a shape on the GPU; the learned selector
+instead predicts log(makespan) of every candidate with a small multilayer
+perceptron (13 -> 64 -> 64 -> 1, trained on timings of the GPU executor) and
+picks the argmin, so a shape can be tuned without running its candidates.
+The network's forward pass, gradient and Adam step are the library's HIP
+kernels (tiledqr_mlp_*); this module only encodes features and drives the
+loops.
 
-Algorithm classes (feature one-hot order): TS-FlatTree, TT-FlatTree
-(Sameh-Kuck), BinaryTree, Fibonacci, Greedy, PlasmaTree (TT, with BS).
+Trees (feature one-hot order): FlatTree, BinaryTree, Fibonacci, Greedy,
+PlasmaTree (with BS).  Kernel family: TT, or TS (TS kernels where the tree
+allows them: FlatTree with TS kernels is Sameh-Kuck's TS scheme, the other
+trees take TS kernels inside their flat chains and TT at the merges).
 """
 
 import csv
@@ -26,45 +29,50 @@ from . import _lib
 from ._lib import check
 
 N_IN = 13
-ALGOS = ["ts-flat", "tt-flat", "binary", "fibonacci", "greedy", "plasma"]
-ALGO_TREE = [(_lib.TREE_FLAT, _lib.KERN_TS), (_lib.TREE_SAMEH_KUCK, _lib.KERN_TT), (_lib.TREE_BINARY, _lib.KERN_TT),
-             (_lib.TREE_FIBONACCI, _lib.KERN_TT), (_lib.TREE_GREEDY, _lib.KERN_TT), (_lib.TREE_PLASMA, _lib.KERN_TT)]
+ALGOS = ["flat", "binary", "fibonacci", "greedy", "plasma"]
+ALGO_TREE = [_lib.TREE_FLAT, _lib.TREE_BINARY, _lib.TREE_FIBONACCI, _lib.TREE_GREEDY, _lib.TREE_PLASMA]
+KERNS = [_lib.KERN_TT, _lib.KERN_TS]  # feature 8: 0 = TT, 1 = TS
+PLASMA = 4
 PRECS = ["f64", "f32", "bf16"]
 NBS = (64, 128, 256)
-CORPUS_FIELDS = ["p", "q", "nb", "algo", "bs", "prec", "ms"]
+MAX_TILES = 64  # candidates keep p <= MAX_TILES (the host plan of larger grids takes seconds)
+CORPUS_FIELDS = ["p", "q", "nb", "algo", "kern", "bs", "prec", "ms"]
 
 
-def features(p, q, nb, algo, bs, prec):
-    """13 features of a candidate: log2 p, log2 q, log2 nb, one-hot
-    algorithm class (6), log2 BS for PlasmaTree else 0, one-hot update
-    precision (3)."""
+def features(p, q, nb, algo, kern, bs, prec):
+    """13 features of a candidate: log2 p, log2 q, log2 nb, one-hot tree
+    (5), kernel family (1 = TS), log2 BS for PlasmaTree else 0, one-hot
+    update precision (3)."""
     x = np.zeros(N_IN, dtype=np.float32)
     x[0] = math.log2(p)
     x[1] = math.log2(q)
     x[2] = math.log2(nb)
     x[3 + algo] = 1.0
-    x[9] = math.log2(bs) if algo == 5 else 0.0
+    x[8] = float(kern)
+    x[9] = math.log2(bs) if algo == PLASMA else 0.0
     x[10 + prec] = 1.0
     return x
 
 
-def candidates(m, n, nbs=NBS):
-    """Every (nb, algo, bs) for an m x n matrix: tile sizes dividing both
-    dimensions with p >= q, the five fixed trees, and PlasmaTree with every
-    power-of-two BS up to p."""
+def candidates(m, n, nbs=NBS, max_tiles=MAX_TILES):
+    """Every (nb, tree, family, bs) for an m x n matrix: tile sizes dividing
+    both dimensions with q <= p <= max_tiles, the four fixed trees and
+    PlasmaTree with every power-of-two BS up to p, each with TT and with TS
+    kernels."""
     out = []
     for nb in nbs:
         if m % nb or n % nb:
             continue
         p, q = m // nb, n // nb
-        if p < q:
+        if p < q or p > max_tiles:
             continue
-        for algo in range(5):
-            out.append((nb, algo, 1))
-        bs = 1
-        while bs <= p:
-            out.append((nb, 5, bs))
-            bs *= 2
+        for kern in (0, 1):
+            for algo in range(PLASMA):
+                out.append((nb, algo, kern, 1))
+            bs = 1
+            while bs <= p:
+                out.append((nb, PLASMA, kern, bs))
+                bs *= 2
     return out
 
 
@@ -92,11 +100,10 @@ class Timer:
             self._mats[key] = self.torch.randn((n, m), generator=g, dtype=self.torch.float64, device="cuda").t()
         return self._mats[key]
 
-    def time(self, m, n, nb, algo, bs, prec, reps=1):
+    def time(self, m, n, nb, algo, kern, bs, prec, reps=1):
         from .api import factor
         A = self.matrix(m, n)
-        tree, kern = ALGO_TREE[algo]
-        F = factor(A, nb, tree, bs, kern, prec)
+        F = factor(A, nb, ALGO_TREE[algo], bs, KERNS[kern], prec)
         F.sync()
         best = math.inf
         for _ in range(reps):
@@ -108,9 +115,9 @@ class Timer:
 
 
 def collect_corpus(path, count, seed=0, flop_cap=6e11, log=None):
-    """Time `count` random candidates (p log-uniform in [1, 128], q
-    log-uniform in [1, p], nb in {64, 128, 256}, algorithm and BS uniform,
-    precision uniform) and append them to a CSV file."""
+    """Time `count` random candidates (p log-uniform in [1, MAX_TILES], q
+    log-uniform in [1, p], nb in {64, 128, 256}, tree, family and BS
+    uniform, precision uniform) and append them to a CSV file."""
     rng = np.random.default_rng(seed)
     timer = Timer(seed)
     new = not os.path.exists(path)
@@ -120,17 +127,18 @@ def collect_corpus(path, count, seed=0, flop_cap=6e11, log=None):
             w.writerow(CORPUS_FIELDS)
         done = 0
         while done < count:
-            p = int(round(2 ** rng.uniform(0, 7)))
+            p = int(round(2 ** rng.uniform(0, math.log2(MAX_TILES))))
             q = int(round(2 ** rng.uniform(0, math.log2(p)))) if p > 1 else 1
             q = max(1, min(q, p))
             nb = int(rng.choice(NBS))
             if flops(p * nb, q * nb) > flop_cap:
                 continue
-            algo = int(rng.integers(0, 6))
-            bs = int(2 ** rng.integers(0, int(math.log2(p)) + 1)) if algo == 5 else 1
+            algo = int(rng.integers(0, len(ALGOS)))
+            kern = int(rng.integers(0, 2))
+            bs = int(2 ** rng.integers(0, int(math.log2(p)) + 1)) if algo == PLASMA else 1
             prec = int(rng.integers(0, 3))
-            ms = timer.time(p * nb, q * nb, nb, algo, bs, prec)
-            w.writerow([p, q, nb, algo, bs, prec, "%.5f" % ms])
+            ms = timer.time(p * nb, q * nb, nb, algo, kern, bs, prec)
+            w.writerow([p, q, nb, algo, kern, bs, prec, "%.5f" % ms])
             fh.flush()
             done += 1
             if log and done % 100 == 0:
@@ -138,11 +146,12 @@ def collect_corpus(path, count, seed=0, flop_cap=6e11, log=None):
 
 
 def exhaustive(m, n, prec, timer, nbs=NBS):
-    """The exhaustive autotuner: {(nb, algo, bs): ms} for every candidate."""
-    return {c: timer.time(m, n, c[0], c[1], c[2], prec) for c in candidates(m, n, nbs)}
+    """The exhaustive autotuner: {(nb, algo, kern, bs): ms} for every
+    candidate."""
+    return {c: timer.time(m, n, c[0], c[1], c[2], c[3], prec) for c in candidates(m, n, nbs)}
 
 
-def heldout_shapes(count, seed, step=512, mmax=4096):
+def heldout_shapes(count, seed, step=512, mmax=8192):
     """Held-out (m, n, precision) triples: m, n multiples of step with
     n <= m <= mmax."""
     rng = np.random.default_rng(seed)
@@ -227,8 +236,8 @@ class MakespanModel:
 
 
 def corpus_arrays(rows):
-    X = np.stack([features(int(r["p"]), int(r["q"]), int(r["nb"]), int(r["algo"]), int(r["bs"]), int(r["prec"]))
-                  for r in rows])
+    X = np.stack([features(int(r["p"]), int(r["q"]), int(r["nb"]), int(r["algo"]), int(r["kern"]), int(r["bs"]),
+                           int(r["prec"])) for r in rows])
     t = np.log(np.array([float(r["ms"]) for r in rows], dtype=np.float64)).astype(np.float32)
     return X, t
 
@@ -241,7 +250,7 @@ class Selector:
 
     def choose(self, m, n, prec, nbs=NBS):
         cands = candidates(m, n, nbs)
-        X = np.stack([features(m // nb, n // nb, nb, algo, bs, prec) for nb, algo, bs in cands])
+        X = np.stack([features(m // nb, n // nb, nb, algo, kern, bs, prec) for nb, algo, kern, bs in cands])
         y = self.model.predict(X).cpu().numpy()
         return cands[int(np.argmin(y))]
 
@@ -256,8 +265,8 @@ def default_choice(m, n):
     """The choice without a selector: Greedy with TT kernels at the largest
     tile size that divides the matrix."""
     for nb in sorted(NBS, reverse=True):
-        if m % nb == 0 and n % nb == 0 and m // nb >= n // nb:
-            return (nb, 4, 1)
+        if m % nb == 0 and n % nb == 0 and n // nb <= m // nb <= MAX_TILES:
+            return (nb, 3, 0, 1)
     raise ValueError("no tile size divides %d x %d" % (m, n))
 
 

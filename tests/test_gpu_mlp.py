@@ -130,7 +130,7 @@ def _heldout_tables(path):
     tables = {}
     for r in selector.load_csv(path):
         key = (int(r["shape"]), int(r["m"]), int(r["n"]), int(r["prec"]))
-        tables.setdefault(key, {})[(int(r["nb"]), int(r["algo"]), int(r["bs"]))] = float(r["ms"])
+        tables.setdefault(key, {})[(int(r["nb"]), int(r["algo"]), int(r["kern"]), int(r["bs"]))] = float(r["ms"])
     return tables
 
 

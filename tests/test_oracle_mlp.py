@@ -65,8 +65,22 @@ def test_training_reduces_loss():
 
 
 def test_features_layout():
-    x = mlp.features(64, 8, 256, mlp.ALGO_PLASMA, 4, 2)
+    x = mlp.features(64, 8, 256, mlp.ALGO_PLASMA, mlp.KERN_TS, 4, 2)
     assert x.shape == (13,)
     assert list(x[:3]) == [6.0, 3.0, 8.0]
-    assert x[3 + mlp.ALGO_PLASMA] == 1.0 and x[9] == 2.0 and x[12] == 1.0
-    assert x.sum() == 6 + 3 + 8 + 1 + 2 + 1
+    assert x[3 + mlp.ALGO_PLASMA] == 1.0 and x[8] == 1.0 and x[9] == 2.0 and x[12] == 1.0
+    assert x.sum() == 6 + 3 + 8 + 1 + 1 + 2 + 1
+    y = mlp.features(64, 8, 256, mlp.ALGO_GREEDY, mlp.KERN_TT, 1, 0)
+    assert y[3 + mlp.ALGO_GREEDY] == 1.0 and y[8] == 0.0 and y[9] == 0.0 and y[10] == 1.0
+
+
+def test_selector_features_match_the_oracle():
+    """The selector's feature encoding is the oracle's, for every candidate
+    of a few shapes."""
+    from paper_1104_4475_amd import selector
+    for m, n in ((2048, 512), (4096, 4096), (8192, 1024)):
+        cands = selector.candidates(m, n)
+        assert cands and {c[1] for c in cands} == set(range(5)) and {c[2] for c in cands} == {0, 1}
+        for nb, algo, kern, bs in cands:
+            assert np.array_equal(selector.features(m // nb, n // nb, nb, algo, kern, bs, 1),
+                                  mlp.features(m // nb, n // nb, nb, algo, kern, bs, 1).astype(np.float32))
