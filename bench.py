@@ -56,9 +56,9 @@ TILE_RW = (2.0, 2.5, 4.0, 5.0, 2.0, 4.5)
 # (calibrated by a plain copy; profiles/hbm_traffic_square10240_nb256.md),
 # keyed by (workload, update precision, tree, BS, kernels, nb) and valid for
 # the executor sources with the given SHA-256 prefix only.
-TRAFFIC = {("square", "f32", "plasma", 16, "ts", 256): (63.627e9, "8a444c1abb382bf3"),
-           ("square", "bf16", "plasma", 16, "ts", 256): (64.678e9, "8a444c1abb382bf3"),
-           ("square", "f64", "plasma", 16, "ts", 256): (90.318e9, "8a444c1abb382bf3")}
+TRAFFIC = {("square", "f32", "flat", 1, "ts", 256): (62.22e9, "e7553df0970b304b"),
+           ("square", "bf16", "flat", 1, "ts", 256): (58.01e9, "e7553df0970b304b"),
+           ("square", "f64", "flat", 1, "ts", 256): (84.12e9, "e7553df0970b304b")}
 
 
 def executor_source_hash():
