@@ -65,7 +65,7 @@ def executor_source_hash():
     import hashlib
     h = hashlib.sha256()
     here = os.path.dirname(os.path.abspath(__file__))
-    for f in ("kernels.hip", "device.hpp"):
+    for f in ("kernels.hip", "device.hpp", "hip_prims.hpp"):
         with open(os.path.join(here, "paper_1104_4475_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

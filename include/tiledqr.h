@@ -298,6 +298,17 @@ int tiledqr_lstsq_qtb(const tqr_factors* F, const double* A0, int64_t lda,
  * tiledqr_batch_sync: waits for the last run; TQR_EEXEC if its executor
  *   stopped on a wait time limit.
  * tiledqr_batch_time: milliseconds of the last run's graph (HIP events).
+ * tiledqr_batch_set_trace: with tracing on, every later run records, for
+ *   each subtask of the merged dispatch order, the same four ticks as
+ *   tiledqr_set_trace (ticket, ready, end, workgroup).  The captured graph
+ *   is not rebuilt: the kernel reads the trace buffer's address from device
+ *   memory at its start.  Synchronizes the last run's stream.  Errors:
+ *   TQR_EINVAL, TQR_ENOMEM, TQR_EHIP.
+ * tiledqr_batch_get_trace: 11 int64 per subtask to out (host): the ten
+ *   columns of tiledqr_get_trace (tiles of the subtask's own problem), then
+ *   the problem index; out may be NULL to query *n; *ticks_per_second (may
+ *   be NULL) gets the clock rate.  Synchronizes the last run's stream.
+ *   Errors: TQR_EINVAL (tracing off), TQR_EHIP.
  * tiledqr_batch_get: borrowed handle of problem i (valid until the batch is
  *   destroyed; not to be passed to tiledqr_destroy), usable with
  *   tiledqr_apply_q, tiledqr_get_r, tiledqr_lstsq and the other handle
@@ -308,6 +319,8 @@ int tiledqr_batch_create(int32_t nprob, const tqr_opts* opts, const int64_t* lda
 int tiledqr_batch_run(tqr_batch* batch, const double* const* A, void* stream);
 int tiledqr_batch_sync(tqr_batch* batch);
 int tiledqr_batch_time(tqr_batch* batch, float* ms);
+int tiledqr_batch_set_trace(tqr_batch* batch, int enable);
+int tiledqr_batch_get_trace(tqr_batch* batch, int64_t* out, int64_t* n, double* ticks_per_second);
 int tiledqr_batch_get(tqr_batch* batch, int32_t i, tqr_factors** F);
 int tiledqr_batch_destroy(tqr_batch* batch);
 

@@ -85,6 +85,8 @@ _sigs = {
     "tiledqr_batch_run": (ctypes.c_int, [_vp, _P(_vp), _vp]),
     "tiledqr_batch_sync": (ctypes.c_int, [_vp]),
     "tiledqr_batch_time": (ctypes.c_int, [_vp, _P(ctypes.c_float)]),
+    "tiledqr_batch_set_trace": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "tiledqr_batch_get_trace": (ctypes.c_int, [_vp, _P(_i64), _P(_i64), _P(ctypes.c_double)]),
     "tiledqr_batch_get": (ctypes.c_int, [_vp, _i32, _P(_vp)]),
     "tiledqr_batch_destroy": (ctypes.c_int, [_vp]),
     "tiledqr_mlp_nparam": (ctypes.c_int, []),

@@ -247,6 +247,23 @@ class Batch:
         check(_lib.tiledqr_batch_time(self.handle, ctypes.byref(ms)), "tiledqr_batch_time")
         return ms.value
 
+    def set_trace(self, enable=True):
+        check(_lib.tiledqr_batch_set_trace(self.handle, 1 if enable else 0), "tiledqr_batch_set_trace")
+
+    def trace(self):
+        """Per subtask of the merged dispatch order: int64 array (n, 11) =
+        kind, i, piv, k, j, slab, ticket, ready, end, workgroup (ticks),
+        problem; and the tick rate in Hz."""
+        import numpy as np
+        n = ctypes.c_int64()
+        rate = ctypes.c_double()
+        check(_lib.tiledqr_batch_get_trace(self.handle, None, ctypes.byref(n), ctypes.byref(rate)),
+              "tiledqr_batch_get_trace")
+        out = np.zeros((max(1, n.value), 11), dtype=np.int64)
+        check(_lib.tiledqr_batch_get_trace(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                           ctypes.byref(n), ctypes.byref(rate)), "tiledqr_batch_get_trace")
+        return out[:n.value], rate.value
+
     def factors(self, i):
         """Borrowed Factors of problem i (valid while the batch lives)."""
         h = ctypes.c_void_p()

@@ -246,6 +246,8 @@ struct tqr_batch {
   double** aptr_dev = nullptr;
   double** aptr_host = nullptr;  // pinned staging of the A pointers
   int32_t* ctl = nullptr;        // ticket, err, epoch
+  int64_t** trace_slot = nullptr;  // device word: the trace buffer, or null
+  int64_t* trace = nullptr;      // 4 int64 per subtask while tracing
   int64_t ntiles = 0;
   int grid = 1;
   hipStream_t cap = nullptr;
@@ -262,6 +264,8 @@ struct tqr_batch {
     if (ev0) (void)hipEventDestroy(ev0);
     if (ev1) (void)hipEventDestroy(ev1);
     exec.release();
+    if (trace_slot) (void)hipFree(trace_slot);
+    if (trace) (void)hipFree(trace);
     if (prob) (void)hipFree(prob);
     if (prob_of) (void)hipFree(prob_of);
     if (tile_start) (void)hipFree(tile_start);
@@ -1157,7 +1161,7 @@ int tiledqr_batch_create(int32_t nprob, const tqr_opts* opts, const int64_t* lda
     tqr::SubTask st = plans[i].sub[r];
     st.dep_begin = static_cast<int32_t>(merged.deps.size());
     for (int32_t e = plans[i].sub[r].dep_begin; e < plans[i].sub[r].dep_end; ++e)
-      merged.deps.push_back(gpos[i][plans[i].deps[e]]);
+      merged.deps.push_back(gpos[i][tqr::dep_index(plans[i].deps[e])] | tqr::dep_bits(plans[i].deps[e]));
     st.dep_end = static_cast<int32_t>(merged.deps.size());
     merged.sub[g] = st;
     prob_of[g] = i;
@@ -1171,6 +1175,7 @@ int tiledqr_batch_create(int32_t nprob, const tqr_opts* opts, const int64_t* lda
       !hip_ok(hipMalloc(&b->lda_dev, nprob * sizeof(int64_t))) ||
       !hip_ok(hipMalloc(&b->aptr_dev, nprob * sizeof(double*))) ||
       !hip_ok(hipMalloc(&b->ctl, 3 * sizeof(int32_t))) ||
+      !hip_ok(hipMalloc(&b->trace_slot, sizeof(int64_t*))) ||
       !hip_ok(hipHostMalloc(&b->aptr_host, nprob * sizeof(double*))))
     return TQR_ENOMEM;
   HIP_TRY(hipMemcpy(b->prob, desc.data(), nprob * sizeof(tqr::ProbDesc), hipMemcpyHostToDevice));
@@ -1178,6 +1183,7 @@ int tiledqr_batch_create(int32_t nprob, const tqr_opts* opts, const int64_t* lda
   HIP_TRY(hipMemcpy(b->tile_start, tile_start.data(), (nprob + 1) * sizeof(int64_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(b->lda_dev, lda, nprob * sizeof(int64_t), hipMemcpyHostToDevice));
   HIP_TRY(hipMemset(b->ctl, 0, 3 * sizeof(int32_t)));
+  HIP_TRY(hipMemset(b->trace_slot, 0, sizeof(int64_t*)));
   HIP_TRY(hipMemset(b->aptr_dev, 0, nprob * sizeof(double*)));
   b->grid = device_cus() * tqr::batched_occupancy(b->upd);
   // The whole run (pack every problem, reset the executor, execute) as one
@@ -1194,6 +1200,7 @@ int tiledqr_batch_create(int32_t nprob, const tqr_opts* opts, const int64_t* lda
   a.nsub = b->exec.nsub;
   a.upd = b->upd;
   a.spin_ticks = 4 * wall_ticks_per_second();
+  a.trace = b->trace_slot;
   HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
   hipError_t e1 = tqr::launch_pack_batched(b->aptr_dev, b->lda_dev, b->prob, b->tile_start, nprob, b->ntiles, 64,
                                            b->cap);
@@ -1249,6 +1256,54 @@ int tiledqr_batch_time(tqr_batch* b, float* ms) {
   if (!b || !ms || !b->ran) return TQR_EINVAL;
   HIP_TRY(hipEventSynchronize(b->ev1));
   HIP_TRY(hipEventElapsedTime(ms, b->ev0, b->ev1));
+  return TQR_OK;
+}
+
+int tiledqr_batch_set_trace(tqr_batch* b, int enable) {
+  if (!b) return TQR_EINVAL;
+  if (b->stream) HIP_TRY(hipStreamSynchronize(b->stream));
+  if (enable && !b->trace) {
+    const size_t bytes = 4 * sizeof(int64_t) * std::max<int32_t>(1, b->exec.nsub);
+    if (!hip_ok(hipMalloc(&b->trace, bytes))) return TQR_ENOMEM;
+    HIP_TRY(hipMemset(b->trace, 0, bytes));
+    HIP_TRY(hipMemcpy(b->trace_slot, &b->trace, sizeof(int64_t*), hipMemcpyHostToDevice));
+  } else if (!enable && b->trace) {
+    int64_t* none = nullptr;
+    HIP_TRY(hipMemcpy(b->trace_slot, &none, sizeof(int64_t*), hipMemcpyHostToDevice));
+    HIP_TRY(hipFree(b->trace));
+    b->trace = nullptr;
+  }
+  return TQR_OK;
+}
+
+int tiledqr_batch_get_trace(tqr_batch* b, int64_t* out, int64_t* n, double* ticks_per_second) {
+  if (!b || !n) return TQR_EINVAL;
+  *n = b->exec.nsub;
+  if (ticks_per_second) *ticks_per_second = static_cast<double>(wall_ticks_per_second());
+  if (!out) return TQR_OK;
+  if (!b->trace) return TQR_EINVAL;
+  if (b->stream) HIP_TRY(hipStreamSynchronize(b->stream));
+  const int32_t ns = b->exec.nsub;
+  std::vector<int64_t> t(4 * static_cast<size_t>(ns));
+  std::vector<DevSub> sub(ns);
+  std::vector<int32_t> prob(ns);
+  HIP_TRY(hipMemcpy(t.data(), b->trace, t.size() * sizeof(int64_t), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(sub.data(), b->exec.sub, sub.size() * sizeof(DevSub), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(prob.data(), b->prob_of, prob.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+  for (int32_t s = 0; s < ns; ++s) {
+    int64_t* o = out + 11 * static_cast<int64_t>(s);
+    o[0] = sub[s].kind;
+    o[1] = sub[s].i;
+    o[2] = sub[s].piv;
+    o[3] = sub[s].k;
+    o[4] = sub[s].j;
+    o[5] = sub[s].slab;
+    o[6] = t[4 * s];
+    o[7] = t[4 * s + 1];
+    o[8] = t[4 * s + 2];
+    o[9] = t[4 * s + 3];
+    o[10] = prob[s];
+  }
   return TQR_OK;
 }
 

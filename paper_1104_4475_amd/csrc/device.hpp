@@ -85,6 +85,7 @@ struct BatchArgs {
   int32_t nsub;
   int32_t upd;
   int64_t spin_ticks;
+  int64_t* const* trace;  // device word holding the trace buffer (4 int64 per subtask), or null there
 };
 
 // Kernel launchers (defined in kernels.hip).

@@ -7,8 +7,12 @@
       mean measured duration from the executor trace); --upd selects the
       update precision (0 FP64, 1 FP32, 2 BF16), --ts adds every tree with
       TS kernels at its leaves
-  python -m paper_1104_4475_amd.measure batched  [--count 512]
-      the batched launch of tall-skinny problems, FP64 and FP32 updates
+  python -m paper_1104_4475_amd.measure batched  [--count 512 --tree 5 --bs 16 --kern 2]
+      the batched launch of tall-skinny problems, FP64 and FP32 updates,
+      with a per-kind breakdown of one traced run of each (default tree:
+      PlasmaTree BS=16 with TS kernels)
+  python -m paper_1104_4475_amd.measure batched-trees  [--count 512]
+      the same batch under each tree and kernel family of BATCH_TREES
 """
 
 import argparse
@@ -16,7 +20,7 @@ import sys
 
 import numpy as np
 
-from . import _lib
+from . import _lib, trace
 from .api import Batch, factor
 
 KIND = ["GEQRT", "UNMQR", "TSQRT", "TSMQR", "TTQRT", "TTMQR"]
@@ -83,7 +87,40 @@ def trees(m, n, nb, reps=3, upd=0, ts=False):
         del F
 
 
-def batched(count, seed=6):
+BATCH_TREES = [("Greedy, TT kernels", _lib.TREE_GREEDY, 1, _lib.KERN_TT),
+               ("Greedy, TS kernels", _lib.TREE_GREEDY, 1, _lib.KERN_TS),
+               ("PlasmaTree BS=4, TS", _lib.TREE_PLASMA, 4, _lib.KERN_TS),
+               ("PlasmaTree BS=8, TS", _lib.TREE_PLASMA, 8, _lib.KERN_TS),
+               ("PlasmaTree BS=16, TS", _lib.TREE_PLASMA, 16, _lib.KERN_TS),
+               ("PlasmaTree BS=16, TT", _lib.TREE_PLASMA, 16, _lib.KERN_TT),
+               ("FlatTree, TS", _lib.TREE_FLAT, 1, _lib.KERN_TS)]
+# The best tree above again with nb = 32 for every problem (instead of 64
+# for n = 64 and 128).
+BATCH_NB32 = ("PlasmaTree BS=16, TS, nb = 32 throughout", _lib.TREE_PLASMA, 16, _lib.KERN_TS)
+
+
+def batched_trees(count, seed=6, reps=3):
+    """Graph time of the batch for each tree and kernel family of
+    BATCH_TREES (FP64 updates)."""
+    shapes, mats = _batch_inputs(count, seed)
+    flops = sum(2.0 * m * n * n - 2.0 * n ** 3 / 3.0 for m, n, _ in shapes)
+    print("| tree | problems | graph time (ms) | GFLOP/s |")
+    print("|---|---|---|---|")
+    for name, tree, bs, kern in BATCH_TREES + [BATCH_NB32]:
+        nbs = [32 if name == BATCH_NB32[0] else nb for _, _, nb in shapes]
+        B = Batch([(m, n) for m, n, _ in shapes], nbs, tree=tree, bs=bs, kernels=kern)
+        ts = []
+        for _ in range(reps + 1):
+            B.run(mats)
+            B.sync()
+            ts.append(B.time_ms())
+        t = min(ts[1:])
+        print("| %s | %d | %.2f | %.0f |" % (name, count, t, flops / t / 1e6))
+        sys.stdout.flush()
+        del B
+
+
+def _batch_inputs(count, seed):
     import torch
     rng = np.random.default_rng(seed)
     shapes = []
@@ -97,11 +134,17 @@ def batched(count, seed=6):
         g = torch.Generator(device="cuda")
         g.manual_seed(1000 + i)
         mats.append(torch.randn((n, m), generator=g, dtype=torch.float64, device="cuda").t())
+    return shapes, mats
+
+
+def batched(count, seed=6, tree=_lib.TREE_PLASMA, bs=16, kern=_lib.KERN_TS):
+    shapes, mats = _batch_inputs(count, seed)
     flops = sum(2.0 * m * n * n - 2.0 * n ** 3 / 3.0 for m, n, _ in shapes)
     print("| updates | problems | total flops | graph time (ms) | GFLOP/s |")
     print("|---|---|---|---|---|")
+    summaries = []
     for upd, name in ((0, "FP64"), (1, "FP32")):
-        B = Batch([(m, n) for m, n, _ in shapes], [nb for _, _, nb in shapes], upd=upd)
+        B = Batch([(m, n) for m, n, _ in shapes], [nb for _, _, nb in shapes], tree=tree, bs=bs, kernels=kern, upd=upd)
         ts = []
         for _ in range(4):
             B.run(mats)
@@ -110,23 +153,48 @@ def batched(count, seed=6):
         t = min(ts[1:])
         print("| %s | %d | %.3e | %.2f | %.0f |" % (name, count, flops, t, flops / t / 1e6))
         sys.stdout.flush()
+        # one traced run for the per-kind breakdown (printed after the table)
+        B.set_trace(True)
+        B.run(mats)
+        B.sync()
+        tr, rate = B.trace()
+        summaries.append((name, B.time_ms(), trace.summarize(tr, rate)))
         del B
+    for name, ms, s in summaries:
+        print()
+        print("%s updates, traced run (%.2f ms graph): %d subtasks on %d workgroups, executor makespan %.2f ms, "
+              "workgroups busy %.1f%%, waiting for predecessors %.1f%%"
+              % (name, ms, s["subtasks"], s["workgroups"], s["makespan_us"] / 1e3, 100 * s["utilization"],
+                 100 * s["wait_us"] / max(1e-9, s["workgroups"] * s["makespan_us"])))
+        print()
+        print("| kind | subtasks | mean (us) | max (us) | total (ms) | share of busy time | mean wait (us) |")
+        print("|---|---|---|---|---|---|---|")
+        for k, v in sorted(s["kinds"].items(), key=lambda kv: -kv[1]["total_us"]):
+            print("| %s | %d | %.2f | %.2f | %.2f | %.1f%% | %.2f |" % (
+                k, v["count"], v["mean_us"], v["max_us"], v["total_us"] / 1e3, 100 * v["total_us"] / s["busy_us"],
+                v["mean_wait_us"]))
+        sys.stdout.flush()
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["trees", "batched"])
+    ap.add_argument("what", choices=["trees", "batched", "batched-trees"])
     ap.add_argument("--m", type=int, default=16384)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--nb", type=int, default=256)
     ap.add_argument("--count", type=int, default=512)
     ap.add_argument("--upd", type=int, default=0)
     ap.add_argument("--ts", action="store_true")
+    ap.add_argument("--tree", type=int, default=_lib.TREE_PLASMA)
+    ap.add_argument("--bs", type=int, default=16)
+    ap.add_argument("--kern", type=int, default=_lib.KERN_TS)
     a = ap.parse_args(argv)
     if a.what == "trees":
         trees(a.m, a.n, a.nb, upd=a.upd, ts=a.ts)
+    elif a.what == "batched-trees":
+        batched_trees(a.count)
     else:
-        batched(a.count)
+        batched(a.count, tree=a.tree, bs=a.bs, kern=a.kern)
     return 0
 
 

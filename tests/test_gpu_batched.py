@@ -117,3 +117,48 @@ def test_full_batch_512(torch_cuda, upd):
         cn = torch.linalg.norm(mats[i], dim=0)
         rel = ((torch.linalg.norm(R, dim=0) - cn).abs() / cn).max().item()
         assert rel <= tol, (i, rel)
+
+
+def test_batch_trace_respects_each_problems_dag(torch_cuda):
+    """Tracing a batch (switched on after the graph was captured): every
+    subtask of the merged order is traced once with its problem index, the
+    subtasks of problem i are those of its own executor plan, and each became
+    ready only after all its predecessors in that plan ended.  Switching the
+    trace off again leaves the results unchanged."""
+    import paper_1104_4475_amd as tqr
+    from paper_1104_4475_amd import _lib
+    torch = torch_cuda
+    _say("batched trace")
+    shapes = SMALL
+    B = tqr.Batch([(m, n) for m, n, _ in shapes], [nb for _, _, nb in shapes])
+    mats = [_dev(torch, m, n, 700 + i) for i, (m, n, nb) in enumerate(shapes)]
+    B.run(mats)
+    B.sync()
+    B.set_trace(True)
+    B.run(mats)
+    B.sync()
+    tr, rate = B.trace()
+    assert rate > 0 and tr.shape[1] == 11
+    ticket, ready, end = tr[:, 6], tr[:, 7], tr[:, 8]
+    assert np.all(ticket > 0) and np.all(ready >= ticket) and np.all(end >= ready)
+    assert np.array_equal(np.sort(np.unique(tr[:, 10])), np.arange(len(shapes)))
+    total = 0
+    for i in range(len(shapes)):
+        rows = np.nonzero(tr[:, 10] == i)[0]
+        sub, deps = B.factors(i).exec_plan()
+        assert len(rows) == len(sub), i
+        total += len(sub)
+        where = {tuple(int(x) for x in tr[r, :6]): r for r in rows}
+        assert len(where) == len(rows)
+        pos = [where[tuple(int(x) for x in sub[t, :6])] for t in range(len(sub))]
+        for t in range(len(sub)):
+            e = deps[sub[t, 6]:sub[t, 7]]
+            assert np.all((e & ~_lib.DEP_INDEX) == 0)  # nb <= 64: whole-task waits only
+            for d in e:
+                assert end[pos[d]] <= ready[pos[t]], (i, t, int(d))
+    assert total == len(tr)
+    B.set_trace(False)
+    B.run(mats)
+    B.sync()
+    for i, ((m, n, nb), A) in enumerate(zip(shapes, mats)):
+        assert _same_as_single(torch, tqr, B.factors(i), A, nb, tqr.TREE_GREEDY, 0), i
