@@ -195,10 +195,13 @@ def factor(A, nb, tree=_lib.TREE_GREEDY, bs=1, kernels=_lib.KERN_DEFAULT, upd=_l
 
 
 def _batch_opts(shapes, nbs, tree, bs, kernels, upd):
+    """Per-problem options; a PlasmaTree or Hadri domain size larger than a
+    problem's tile rows is capped at them."""
     k = len(shapes)
     opts = (_lib.Opts * k)()
     for i, ((m, n), nb) in enumerate(zip(shapes, nbs)):
-        opts[i] = _lib.Opts(m, n, nb, 0, tree, bs, kernels, upd)
+        b = min(bs, m // nb) if tree in (_lib.TREE_PLASMA, _lib.TREE_HADRI) else bs
+        opts[i] = _lib.Opts(m, n, nb, 0, tree, b, kernels, upd)
     return opts
 
 
@@ -270,6 +273,46 @@ class Batch:
         check(_lib.tiledqr_batch_get(self.handle, i, ctypes.byref(h)), "tiledqr_batch_get")
         m, n = self.shapes[i]
         return Factors(h, m, n, self.nbs[i], self.opts[i], owner=self)
+
+
+# Candidates of the batch autotuner: (tree, BS, kernel family); BS is capped
+# at each problem's tile rows.
+BATCH_CANDIDATES = [(_lib.TREE_PLASMA, 16, _lib.KERN_TS), (_lib.TREE_PLASMA, 8, _lib.KERN_TS),
+                    (_lib.TREE_PLASMA, 4, _lib.KERN_TS), (_lib.TREE_GREEDY, 1, _lib.KERN_TS),
+                    (_lib.TREE_GREEDY, 1, _lib.KERN_TT), (_lib.TREE_FLAT, 1, _lib.KERN_TS)]
+
+
+def batch_nb_rules(shapes):
+    """Tile-size choices of the batch autotuner, one nb per problem: the
+    largest of 64 and 32 dividing m and n, and 32 throughout."""
+    big = [64 if m % 64 == 0 and n % 64 == 0 else 32 for m, n in shapes]
+    return {"nb 64 where it divides": big, "nb 32": [32] * len(shapes)}
+
+
+def tune_batch(mats, candidates=None, upd=_lib.UPD_F64, reps=2):
+    """Exhaustive autotuner of a batched launch: times the replayed graph for
+    every candidate (tree, BS, kernel family) under every tile-size rule of
+    batch_nb_rules (best of reps runs after one warm-up) and returns
+    (best, table): best = (ms, rule, tree, bs, kernels, nbs), table = list of
+    (ms, rule, tree, bs, kernels).  mats: column-major float64 CUDA tensors."""
+    shapes = [tuple(A.shape) for A in mats]
+    table, best = [], None
+    for rule, nbs in batch_nb_rules(shapes).items():
+        for tree, bs, kern in (candidates or BATCH_CANDIDATES):
+            if any(m % nb or n % nb for (m, n), nb in zip(shapes, nbs)):
+                continue
+            B = Batch(shapes, nbs, tree=tree, bs=bs, kernels=kern, upd=upd, lds=[_ld(A) for A in mats])
+            ms = []
+            for _ in range(reps + 1):
+                B.run(mats)
+                B.sync()
+                ms.append(B.time_ms())
+            del B
+            t = min(ms[1:])
+            table.append((t, rule, tree, bs, kern))
+            if best is None or t < best[0]:
+                best = (t, rule, tree, bs, kern, nbs)
+    return best, table
 
 
 def factor_batched(mats, nbs, tree=_lib.TREE_GREEDY, bs=1, kernels=_lib.KERN_DEFAULT, upd=_lib.UPD_F64):

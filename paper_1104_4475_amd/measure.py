@@ -13,6 +13,8 @@
       PlasmaTree BS=16 with TS kernels)
   python -m paper_1104_4475_amd.measure batched-trees  [--count 512]
       the same batch under each tree and kernel family of BATCH_TREES
+  python -m paper_1104_4475_amd.measure batched-tune  [--count 512]
+      the batch autotuner (trees x tile-size rules) on the same batch
 """
 
 import argparse
@@ -99,6 +101,22 @@ BATCH_TREES = [("Greedy, TT kernels", _lib.TREE_GREEDY, 1, _lib.KERN_TT),
 BATCH_NB32 = ("PlasmaTree BS=16, TS, nb = 32 throughout", _lib.TREE_PLASMA, 16, _lib.KERN_TS)
 
 
+def batched_tune(count, seed=6):
+    """The batch autotuner (api.tune_batch) on the batch: every candidate
+    tree and tile-size rule, FP64 updates; prints the table and the pick."""
+    from .api import tune_batch
+    _, mats = _batch_inputs(count, seed)
+    names = {v: k for k, v in vars(_lib).items() if k.startswith("TREE_")}
+    best, table = tune_batch(mats)
+    print("| tile sizes | tree | BS | kernels | graph time (ms) |")
+    print("|---|---|---|---|---|")
+    for ms, rule, tree, bs, kern in sorted(table):
+        print("| %s | %s | %d | %s | %.2f |" % (rule, names.get(tree, tree), bs, "TS" if kern == _lib.KERN_TS else "TT", ms))
+    print()
+    print("pick: %s, %s BS=%d, %s kernels, %.2f ms" % (best[1], names.get(best[2], best[2]), best[3],
+                                                       "TS" if best[4] == _lib.KERN_TS else "TT", best[0]))
+
+
 def batched_trees(count, seed=6, reps=3):
     """Graph time of the batch for each tree and kernel family of
     BATCH_TREES (FP64 updates)."""
@@ -178,7 +196,7 @@ def batched(count, seed=6, tree=_lib.TREE_PLASMA, bs=16, kern=_lib.KERN_TS):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["trees", "batched", "batched-trees"])
+    ap.add_argument("what", choices=["trees", "batched", "batched-trees", "batched-tune"])
     ap.add_argument("--m", type=int, default=16384)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--nb", type=int, default=256)
@@ -193,6 +211,8 @@ def main(argv=None):
         trees(a.m, a.n, a.nb, upd=a.upd, ts=a.ts)
     elif a.what == "batched-trees":
         batched_trees(a.count)
+    elif a.what == "batched-tune":
+        batched_tune(a.count)
     else:
         batched(a.count, tree=a.tree, bs=a.bs, kern=a.kern)
     return 0

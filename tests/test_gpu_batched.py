@@ -162,3 +162,32 @@ def test_batch_trace_respects_each_problems_dag(torch_cuda):
     B.sync()
     for i, ((m, n, nb), A) in enumerate(zip(shapes, mats)):
         assert _same_as_single(torch, tqr, B.factors(i), A, nb, tqr.TREE_GREEDY, 0), i
+
+
+def test_batch_autotuner_picks_its_fastest_and_runs_it(torch_cuda):
+    """The batch autotuner times every candidate (tree, BS, kernel family)
+    under every tile-size rule; its pick is the fastest entry of its own
+    table, and a batch built with the pick factors each problem bit for bit
+    as a single call with the same options."""
+    import paper_1104_4475_amd as tqr
+    from paper_1104_4475_amd.api import batch_nb_rules
+    torch = torch_cuda
+    _say("batch autotuner")
+    shapes = [(512, 64), (1024, 128), (256, 32), (768, 64), (2048, 128), (384, 32)]
+    mats = [_dev(torch, m, n, 900 + i) for i, (m, n) in enumerate(shapes)]
+    rules = batch_nb_rules(shapes)
+    assert rules["nb 32"] == [32] * len(shapes)
+    assert rules["nb 64 where it divides"] == [64, 64, 32, 64, 64, 32]
+    best, table = tqr.tune_batch(mats, reps=1)
+    assert len(table) == len(rules) * len(tqr.BATCH_CANDIDATES)
+    assert best[0] == min(t[0] for t in table)
+    ms, rule, tree, bs, kern, nbs = best
+    B = tqr.Batch(shapes, nbs, tree=tree, bs=bs, kernels=kern)
+    B.run(mats)
+    B.sync()
+    for i in (0, 1, 2):
+        m, n = shapes[i]
+        Fs = tqr.factor(mats[i], nbs[i], tree, min(bs, m // nbs[i]) if tree == tqr.TREE_PLASMA else bs, kern, 0)
+        Pb, Ps = B.factors(i).packed(), Fs.packed()
+        torch.cuda.synchronize()
+        assert bool(torch.equal(Pb, Ps)), (i, best)
