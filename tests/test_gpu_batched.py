@@ -93,24 +93,36 @@ def test_graph_replays(torch_cuda):
     assert B.time_ms() > 0
 
 
+# (tree, BS, kernel family): the default Greedy/TT and the batch
+# autotuner's pick, PlasmaTree BS=16 with TS kernels.
+FULL_TREES = [(4, 1, 1), (5, 16, 2)]
+
+
+@pytest.mark.parametrize("tree,bs,kern", FULL_TREES, ids=["greedy_tt", "plasma16_ts"])
 @pytest.mark.parametrize("upd", [0, 1])
-def test_full_batch_512(torch_cuda, upd):
+def test_full_batch_512(torch_cuda, upd, tree, bs, kern):
     """512 tall-skinny problems: m uniform in [1024, 16384] rounded to nb,
     n in {32, 64, 128}, nb = 32 for n = 32 else 64.  Sampled problems are
     bit-exact with single calls; every problem's R has the column norms of
     A (||R e_j|| = ||A e_j||, orthogonal invariance)."""
     import paper_1104_4475_amd as tqr
     torch = torch_cuda
-    _say("batched 512, upd %d" % upd)
+    _say("batched 512, upd %d, tree %d bs %d kernels %d" % (upd, tree, bs, kern))
     shapes = tqr_inputs.batched_shapes(512, tqr_inputs.SEED_BATCH)
     mats = [_dev(torch, m, n, 1000 + i) for i, (m, n, nb) in enumerate(shapes)]
-    B = tqr.Batch([(m, n) for m, n, _ in shapes], [nb for _, _, nb in shapes], upd=upd)
+    B = tqr.Batch([(m, n) for m, n, _ in shapes], [nb for _, _, nb in shapes], tree=tree, bs=bs, kernels=kern,
+                  upd=upd)
     B.run(mats)
     B.sync()
     _say("  batch run %.2f ms" % B.time_ms())
     for i in range(0, 512, 37):
         m, n, nb = shapes[i]
-        assert _same_as_single(torch, tqr, B.factors(i), mats[i], nb, tqr.TREE_GREEDY, upd), i
+        b = min(bs, m // nb) if tree == tqr.TREE_PLASMA else bs
+        Fs = tqr.factor(mats[i], nb, tree, b, kern, upd)
+        Pb, Ps = B.factors(i).packed(), Fs.packed()
+        tb, ts = B.factors(i).tau(), Fs.tau()
+        torch.cuda.synchronize()
+        assert bool(torch.equal(Pb, Ps)) and all(bool(torch.equal(x, y)) for x, y in zip(tb, ts)), i
     tol = 1e-13 if upd == 0 else 1e-5
     for i in range(512):
         R = B.factors(i).R()
