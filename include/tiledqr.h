@@ -282,7 +282,8 @@ int tiledqr_lstsq_qtb(const tqr_factors* F, const double* A0, int64_t lda,
 
 /* Many independent factorizations in one persistent launch.  The task
  * graphs of all problems (each built as for tiledqr_factor, Sec. 2.3) are
- * merged into one dispatch order by the executor's priority, and one
+ * merged into one dispatch order by the executor's priority (each problem's
+ * subtasks by bottom level, the longest remaining path), and one
  * persistent kernel walks them; a problem's subtasks run on its own tiles.
  * Tile sizes 32 and 64 may be mixed; all problems share upd.  The run (pack
  * every problem into tiles, reset the executor, execute) is captured once

@@ -158,6 +158,13 @@ int exec_order() {
   return 3;
 }
 
+// Dispatch order of a batch's problems: the plain bottom-level order
+// (TQR_ORDER overrides).  The simulated list schedule assumes that one
+// problem has every workgroup; across 512 tall-skinny problems the
+// bottom-level order is 3.7% faster (19.5 ms against 20.3 ms).  The order
+// does not change any task's arithmetic.
+int batch_order() { return std::getenv("TQR_ORDER") ? exec_order() : 2; }
+
 // Per-kind task weights (GEQRT, UNMQR, TSQRT, TSMQR, TTQRT, TTMQR) for the
 // priorities: measured durations on MI355X of one task (all column slabs of
 // an update) in microseconds, per tile size and update precision.  Other
@@ -430,7 +437,7 @@ int check_opts(const tqr_opts* o, int64_t lda) {
   return TQR_OK;
 }
 
-int create(const tqr_opts* o, tqr_factors** out, ExecPlan* keep = nullptr) {
+int create(const tqr_opts* o, tqr_factors** out, ExecPlan* keep = nullptr, int order = -1) {
   std::unique_ptr<tqr_factors> F(new (std::nothrow) tqr_factors());
   if (!F) return TQR_ENOMEM;
   F->o = *o;
@@ -456,7 +463,7 @@ int create(const tqr_opts* o, tqr_factors** out, ExecPlan* keep = nullptr) {
   const char* ev = std::getenv("TQR_EARLY");
   const bool early = pblk > 1 && !(ev && ev[0] == '0');
   const int workers = device_cus() * tqr::persistent_occupancy(o->nb, o->upd);
-  tqr::make_exec_plan(F->plan, nslab, exec_order(), w, ex, pblk, stream, early, workers);
+  tqr::make_exec_plan(F->plan, nslab, order < 0 ? exec_order() : order, w, ex, pblk, stream, early, workers);
   int st = upload(ex, F->exec);
   if (st != TQR_OK) return st;
   if (keep) *keep = ex;
@@ -1131,7 +1138,7 @@ int tiledqr_batch_create(int32_t nprob, const tqr_opts* opts, const int64_t* lda
   size_t total = 0;
   for (int32_t i = 0; i < nprob; ++i) {
     tqr_factors* F = nullptr;
-    const int st = create(opts + i, &F, &plans[i]);
+    const int st = create(opts + i, &F, &plans[i], batch_order());
     if (st != TQR_OK) return st;
     b->F.push_back(F);
     desc[i] = tqr::ProbDesc{F->tiles, F->Tg, F->Tp, F->p, F->q, F->nb, 0};
