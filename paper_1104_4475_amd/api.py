@@ -195,20 +195,25 @@ def factor(A, nb, tree=_lib.TREE_GREEDY, bs=1, kernels=_lib.KERN_DEFAULT, upd=_l
 
 
 def _batch_opts(shapes, nbs, tree, bs, kernels, upd):
-    """Per-problem options; a PlasmaTree or Hadri domain size larger than a
+    """Per-problem options (tree, bs and kernels: one value for every
+    problem, or a list); a PlasmaTree or Hadri domain size larger than a
     problem's tile rows is capped at them."""
     k = len(shapes)
+    per = lambda v, i: v[i] if isinstance(v, (list, tuple)) else v  # noqa: E731
     opts = (_lib.Opts * k)()
     for i, ((m, n), nb) in enumerate(zip(shapes, nbs)):
-        b = min(bs, m // nb) if tree in (_lib.TREE_PLASMA, _lib.TREE_HADRI) else bs
-        opts[i] = _lib.Opts(m, n, nb, 0, tree, b, kernels, upd)
+        t, b = per(tree, i), per(bs, i)
+        if t in (_lib.TREE_PLASMA, _lib.TREE_HADRI):
+            b = min(b, m // nb)
+        opts[i] = _lib.Opts(m, n, nb, 0, t, b, per(kernels, i), upd)
     return opts
 
 
 class Batch:
     """Many factorizations in one persistent launch, replayable as a HIP
     graph (tiledqr_batch_*).  shapes: list of (m, n); nbs: tile sizes (32
-    or 64); lds: leading dimensions the runs will use (default m)."""
+    or 64); tree, bs, kernels: one value for all problems or one per
+    problem; lds: leading dimensions the runs will use (default m)."""
 
     def __init__(self, shapes, nbs, tree=_lib.TREE_GREEDY, bs=1, kernels=_lib.KERN_DEFAULT, upd=_lib.UPD_F64,
                  lds=None):
