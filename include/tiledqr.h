@@ -278,6 +278,37 @@ int tiledqr_lstsq_qtb(const tqr_factors* F, const double* A0, int64_t lda,
                       double* X, int64_t ldx, const tqr_refine* r,
                       tqr_refine_info* info, void* stream);
 
+/* ---- double complex -------------------------------------------------------- */
+
+/* The tiled QR of a double-complex matrix (the paper's ZGEQRT family, Sec. 5)
+ * with the same trees, kernel families and task graphs as tiledqr_factor,
+ * on tiles of nb = 32 (other tile sizes: TQR_EUNSUPPORTED).  Each kernel uses
+ * LAPACK's complex elementary reflector H = I - tau u u^H with a real beta;
+ * R = H_l^H ... H_1^H A, so R's diagonal is real.
+ *
+ * tiledqr_zfactor: A is device memory, m x n column-major with interleaved
+ *   real and imaginary parts, lda in complex elements (>= m); opts as for
+ *   tiledqr_factor with nb = 32 and upd = TQR_UPD_F64 (else TQR_EINVAL).
+ *   Copies A into tiles and enqueues the factorization on stream; the
+ *   handle owns its storage.  Errors: TQR_EINVAL, TQR_EUNSUPPORTED,
+ *   TQR_ENOMEM, TQR_EHIP.
+ * tiledqr_zget_packed: the factored matrix in A's layout (R on and above
+ *   the diagonal of the top n rows, the reflectors elsewhere, as LAPACK's
+ *   zgeqrf would leave a tile), to device memory out (ld >= m, complex
+ *   elements).  Enqueued on stream.
+ * tiledqr_zget_tau: the tau of the GEQRT sets (taug) and of the TS/TT sets
+ *   (taup), 32 complex values per tile, tile (r, c) at (c p + r) 32 complex
+ *   elements; device memory, p q 32 complex elements each.
+ * tiledqr_zsync: waits for the factorization; TQR_EEXEC if its executor
+ *   stopped on a wait time limit.
+ * tiledqr_zdestroy: releases the handle (NULL accepted). */
+typedef struct tqr_zfactors tqr_zfactors;
+int tiledqr_zfactor(const tqr_opts* opts, const double* A, int64_t lda, tqr_zfactors** F, void* stream);
+int tiledqr_zget_packed(const tqr_zfactors* F, double* out, int64_t ld, void* stream);
+int tiledqr_zget_tau(const tqr_zfactors* F, double* taug, double* taup, void* stream);
+int tiledqr_zsync(tqr_zfactors* F);
+int tiledqr_zdestroy(tqr_zfactors* F);
+
 /* ---- batched ------------------------------------------------------------ */
 
 /* Many independent factorizations in one persistent launch.  The task

@@ -20,4 +20,4 @@ from ._lib import (  # noqa: F401
     tiledqr_batch_get, tiledqr_batch_destroy, tiledqr_elim_list, tiledqr_schedule, tiledqr_task_preds,
     tiledqr_strerror, elim_list, schedule, task_preds,
 )
-from .api import BATCH_CANDIDATES, Batch, Factors, factor, factor_batched, colmajor, tune_batch  # noqa: F401
+from .api import BATCH_CANDIDATES, Batch, Factors, ZFactors, colmajor, factor, factor_batched, tune_batch, zfactor  # noqa: F401

@@ -280,6 +280,57 @@ class Batch:
         return Factors(h, m, n, self.nbs[i], self.opts[i], owner=self)
 
 
+class ZFactors:
+    """Handle of a double-complex tiled QR (tiledqr_zfactor, nb = 32)."""
+
+    def __init__(self, handle, m, n):
+        self.handle, self.m, self.n = handle, m, n
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            destroy = getattr(_lib, "tiledqr_zdestroy", None)
+            if destroy is not None:
+                destroy(h)
+            self.handle = None
+
+    def sync(self):
+        check(_lib.tiledqr_zsync(self.handle), "tiledqr_zsync")
+
+    def packed(self):
+        """The factored matrix (R and the reflectors) as an m x n complex128
+        column-major CUDA tensor."""
+        import torch
+        out = torch.empty((self.n, self.m), dtype=torch.complex128, device="cuda").t()
+        check(_lib.tiledqr_zget_packed(self.handle, out.data_ptr(), self.m, _stream()), "tiledqr_zget_packed")
+        return out
+
+    def tau(self):
+        """(taug, taup): complex128 CUDA tensors of p q 32 entries."""
+        import torch
+        k = (self.m // 32) * (self.n // 32) * 32
+        tg = torch.empty(k, dtype=torch.complex128, device="cuda")
+        tp = torch.empty(k, dtype=torch.complex128, device="cuda")
+        check(_lib.tiledqr_zget_tau(self.handle, tg.data_ptr(), tp.data_ptr(), _stream()), "tiledqr_zget_tau")
+        return tg, tp
+
+
+def zfactor(A, nb=32, tree=_lib.TREE_GREEDY, bs=1, kernels=_lib.KERN_DEFAULT):
+    """Tiled QR of a complex128 CUDA matrix (tiledqr_zfactor; nb = 32)."""
+    import torch
+    if A.dtype != torch.complex128:
+        raise ValueError("zfactor takes a complex128 matrix")
+    A = A if A.stride(0) == 1 else A.t().contiguous().t()
+    m, n = A.shape
+    opts = _lib.Opts(m, n, nb, 0, tree, bs, kernels, _lib.UPD_F64)
+    h = ctypes.c_void_p()
+    check(_lib.tiledqr_zfactor(ctypes.byref(opts), A.data_ptr(), _ld(A), ctypes.byref(h), _stream()),
+          "tiledqr_zfactor")
+    F = ZFactors(h, m, n)
+    F._A = A  # the copy into tiles runs on the stream
+    return F
+
+
 # Candidates of the batch autotuner: (tree, BS, kernel family); BS is capped
 # at each problem's tile rows.
 BATCH_CANDIDATES = [(_lib.TREE_PLASMA, 16, _lib.KERN_TS), (_lib.TREE_PLASMA, 8, _lib.KERN_TS),

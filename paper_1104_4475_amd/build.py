@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtiledqr.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-SOURCES = ["api.cpp", "plan.cpp", "kernels.hip", "layout.hip", "solve.hip", "mlp.hip"]
+SOURCES = ["api.cpp", "plan.cpp", "kernels.hip", "layout.hip", "solve.hip", "mlp.hip", "zkernels.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-mcode-object-version=5",

@@ -240,6 +240,26 @@ struct tqr_factors {
   }
 };
 
+// Double-complex factorization (nb = 32): tiles, tau of the GEQRT and TS/TT
+// sets, the executor's subtask table and its ticket / error words.
+struct tqr_zfactors {
+  tqr_opts o{};
+  int p = 0, q = 0, grid = 1;
+  DevPlan exec;
+  double* tiles = nullptr;
+  double* taug = nullptr;
+  double* taup = nullptr;
+  int32_t* ctl = nullptr;
+  hipStream_t stream = nullptr;
+
+  ~tqr_zfactors() {
+    exec.release();
+    for (void* ptr : {static_cast<void*>(tiles), static_cast<void*>(taug), static_cast<void*>(taup),
+                      static_cast<void*>(ctl)})
+      if (ptr) (void)hipFree(ptr);
+  }
+};
+
 struct tqr_batch {
   int32_t nprob = 0;
   int32_t upd = 0;
@@ -890,6 +910,77 @@ int tiledqr_lstsq_qtb(const tqr_factors* F, const double* A0, int64_t lda, const
                       tqr_refine_info* info, void* stream) {
   if (!F || !QtB || ldq < F->o.n) return TQR_EINVAL;
   return lstsq_impl(F, A0, lda, B, ldb, QtB, ldq, nrhs, X, ldx, r, info, stream);
+}
+
+int tiledqr_zfactor(const tqr_opts* o, const double* A, int64_t lda, tqr_zfactors** out, void* stream) {
+  if (!out) return TQR_EINVAL;
+  *out = nullptr;
+  const int st0 = check_opts(o, lda);
+  if (st0 != TQR_OK) return st0;
+  if (o->nb != 32) return TQR_EUNSUPPORTED;
+  if (o->upd != TQR_UPD_F64 || !A) return TQR_EINVAL;
+  std::unique_ptr<tqr_zfactors> F(new (std::nothrow) tqr_zfactors());
+  if (!F) return TQR_ENOMEM;
+  F->o = *o;
+  F->o.ib = tqr::IB;
+  F->p = static_cast<int>(o->m / 32);
+  F->q = static_cast<int>(o->n / 32);
+  Plan plan;
+  if (!tqr::make_plan(F->p, F->q, o->tree, o->bs, o->kernels, plan)) return TQR_EINVAL;
+  double w[6];
+  exec_weights(32, TQR_UPD_F64, w);
+  F->grid = device_cus() * tqr::zqr_occupancy();
+  ExecPlan ex;
+  tqr::make_exec_plan(plan, 1, exec_order(), w, ex, 1, false, false, F->grid);
+  int st = upload(ex, F->exec);
+  if (st != TQR_OK) return st;
+  const size_t ntile = static_cast<size_t>(F->p) * F->q;
+  if (!hip_ok(hipMalloc(&F->tiles, ntile * 32 * 32 * 16)) || !hip_ok(hipMalloc(&F->taug, ntile * 32 * 16)) ||
+      !hip_ok(hipMalloc(&F->taup, ntile * 32 * 16)) || !hip_ok(hipMalloc(&F->ctl, 2 * sizeof(int32_t))))
+    return TQR_ENOMEM;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemsetAsync(F->taug, 0, ntile * 32 * 16, s));
+  HIP_TRY(hipMemsetAsync(F->taup, 0, ntile * 32 * 16, s));
+  F->stream = s;
+  HIP_TRY(tqr::launch_zpack(const_cast<double*>(A), lda, F->tiles, F->p, F->q, false, s));
+  if (F->exec.nsub > 0) {
+    const int epoch = ++F->exec.epoch;
+    HIP_TRY(tqr::launch_zqr(F->tiles, F->taug, F->taup, F->exec.sub, F->exec.deps, F->exec.flags, F->ctl,
+                            F->exec.nsub, epoch, F->p, 4 * wall_ticks_per_second(),
+                            std::max(1, std::min(F->exec.nsub, F->grid)), s));
+  }
+  *out = F.release();
+  return TQR_OK;
+}
+
+int tiledqr_zget_packed(const tqr_zfactors* F, double* out, int64_t ld, void* stream) {
+  if (!F || !out || ld < F->o.m) return TQR_EINVAL;
+  HIP_TRY(tqr::launch_zpack(out, ld, F->tiles, F->p, F->q, true, static_cast<hipStream_t>(stream)));
+  return TQR_OK;
+}
+
+int tiledqr_zget_tau(const tqr_zfactors* F, double* taug, double* taup, void* stream) {
+  if (!F || !taug || !taup) return TQR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t bytes = static_cast<size_t>(F->p) * F->q * 32 * 16;
+  HIP_TRY(hipMemcpyAsync(taug, F->taug, bytes, hipMemcpyDeviceToDevice, s));
+  HIP_TRY(hipMemcpyAsync(taup, F->taup, bytes, hipMemcpyDeviceToDevice, s));
+  return TQR_OK;
+}
+
+int tiledqr_zsync(tqr_zfactors* F) {
+  if (!F) return TQR_EINVAL;
+  HIP_TRY(hipStreamSynchronize(F->stream));
+  int32_t err = 0;
+  HIP_TRY(hipMemcpy(&err, F->ctl + 1, sizeof(int32_t), hipMemcpyDeviceToHost));
+  return err ? TQR_EEXEC : TQR_OK;
+}
+
+int tiledqr_zdestroy(tqr_zfactors* F) {
+  if (!F) return TQR_OK;
+  (void)hipStreamSynchronize(F->stream);
+  delete F;
+  return TQR_OK;
 }
 
 int tiledqr_refactor_qtb(tqr_factors* F, const double* A, int64_t lda, double* B, int64_t ldb, int64_t nrhs,

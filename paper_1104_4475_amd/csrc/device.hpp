@@ -145,6 +145,15 @@ int persistent_occupancy(int nb, int upd);
 hipError_t launch_batch_reset(int32_t* ctl, hipStream_t s);
 hipError_t launch_batched(const BatchArgs& b, int grid, hipStream_t s);
 int batched_occupancy(int upd);
+// Double-complex factorization at nb = 32 (zkernels.hip): tiles and tau in
+// interleaved complex layout, the executor's subtask table and flags; ctl
+// holds the ticket and the error word (reset by the launch).  zpack copies
+// a column-major complex matrix into tiles (unpack: back).
+hipError_t launch_zqr(double* tiles, double* taug, double* taup, const DevSub* sub, const int32_t* deps,
+                      int32_t* flags, int32_t* ctl, int32_t nsub, int32_t epoch, int32_t p, int64_t spin_ticks,
+                      int grid, hipStream_t s);
+hipError_t launch_zpack(double* A, int64_t lda, double* tiles, int p, int q, bool unpack, hipStream_t s);
+int zqr_occupancy();
 // All problems' column-major A (device pointer array Aptr, leading
 // dimensions lda) into their tiles; tile_start[i] is the first global tile
 // of problem i (nprob + 1 entries).

@@ -1,0 +1,101 @@
+"""GPU: the double-complex tiled QR (tiledqr_zfactor, nb = 32) against the
+double-complex oracle (oracle.ztiled) on the same seeded inputs: the packed
+factors (R and the reflectors) elementwise within 50 n eps ||A||_F, R's
+diagonal exactly real, and the tau of every panel set (the tau of a short
+reflector moves by |d alpha| / ||x||, hence its looser absolute bound)."""
+
+import sys
+
+import numpy as np
+import pytest
+
+import tqr_inputs
+from oracle import dag, trees, ztiled
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+def _cplx(m, n, seed):
+    return tqr_inputs.gaussian(m, n, seed) + 1j * tqr_inputs.gaussian(m, n, seed + 7919)
+
+
+def _gpu(torch, A):
+    return torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t()
+
+
+CASES = [
+    # (m, n, tree, bs, kernels)
+    (256, 128, trees.GREEDY, 1, dag.KERN_TT),
+    (256, 128, trees.FLAT, 1, dag.KERN_TS),
+    (320, 192, trees.FIBONACCI, 1, dag.KERN_TT),
+    (512, 256, trees.PLASMA, 4, dag.KERN_TS),
+    (256, 256, trees.BINARY, 1, dag.KERN_TT),
+    (1024, 64, trees.GREEDY, 1, dag.KERN_TS),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: "%dx%d_t%d_bs%d_k%d" % c)
+def test_complex_factors_match_oracle(torch_cuda, case):
+    import paper_1104_4475_amd as tqr
+    torch = torch_cuda
+    m, n, tree, bs, kern = case
+    _say("complex %s" % (case,))
+    A = _cplx(m, n, 61)
+    F = tqr.zfactor(_gpu(torch, A), 32, tree, bs, kern)
+    F.sync()
+    P = F.packed().cpu().numpy()
+    O = ztiled.ztiled_qr(A, 32, tree, bs, kern)
+    err = np.max(np.abs(P - O.A))
+    assert err <= 50 * n * EPS * np.linalg.norm(A), err
+    assert np.all(np.diag(P[:n, :n]).imag == 0.0)
+    tg, tp = (t.cpu().numpy().reshape(n // 32, m // 32, 32) for t in F.tau())
+    for (i, k), t in O.tau_g.items():
+        assert np.max(np.abs(tg[k - 1, i - 1] - t)) <= 1e-12, ("taug", i, k)
+    for (i, k), t in O.tau_p.items():
+        assert np.max(np.abs(tp[k - 1, i - 1] - t)) <= 1e-12, ("taup", i, k)
+
+
+def test_complex_real_input_stays_real_and_diagonal_matrix(torch_cuda):
+    import paper_1104_4475_amd as tqr
+    torch = torch_cuda
+    _say("complex special cases")
+    A = tqr_inputs.gaussian(128, 64, 62).astype(np.complex128)
+    F = tqr.zfactor(_gpu(torch, A), 32, tqr.TREE_GREEDY, 1, tqr.KERN_TT)
+    F.sync()
+    P = F.packed().cpu().numpy()
+    assert np.all(P.imag == 0.0)
+    # diag(d): R = diag(-sign(Re d) |d|), the reflectors below are zero
+    rng = np.random.default_rng(5)
+    d = rng.standard_normal(64) + 1j * rng.standard_normal(64)
+    d[3] = 2.0
+    D = np.diag(d)
+    F = tqr.zfactor(_gpu(torch, D), 32, tqr.TREE_FLAT, 1, tqr.KERN_TS)
+    F.sync()
+    R = F.packed().cpu().numpy()
+    beta = -np.where(d.real >= 0.0, 1.0, -1.0) * np.abs(d)
+    beta[3] = 2.0
+    assert np.max(np.abs(np.diag(R) - beta)) <= 4 * EPS * np.abs(d).max()
+    assert np.max(np.abs(R - np.diag(np.diag(R)))) == 0.0
+
+
+def test_complex_tile_size_other_than_32_is_unsupported(torch_cuda):
+    import paper_1104_4475_amd as tqr
+    from paper_1104_4475_amd import _lib
+    torch = torch_cuda
+    A = _gpu(torch, _cplx(128, 64, 63))
+    with pytest.raises(_lib.TiledQRError) as e:
+        tqr.zfactor(A, 64)
+    assert e.value.status == _lib.TQR_EUNSUPPORTED
