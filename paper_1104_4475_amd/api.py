@@ -297,6 +297,12 @@ class ZFactors:
     def sync(self):
         check(_lib.tiledqr_zsync(self.handle), "tiledqr_zsync")
 
+    def refactor(self, A):
+        """Factor a new complex128 matrix of the same shape into the handle."""
+        A = A if A.stride(0) == 1 else A.t().contiguous().t()
+        self._A = A
+        check(_lib.tiledqr_zrefactor(self.handle, A.data_ptr(), _ld(A), _stream()), "tiledqr_zrefactor")
+
     def packed(self):
         """The factored matrix (R and the reflectors) as an m x n complex128
         column-major CUDA tensor."""

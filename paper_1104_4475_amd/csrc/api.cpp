@@ -912,6 +912,8 @@ int tiledqr_lstsq_qtb(const tqr_factors* F, const double* A0, int64_t lda, const
   return lstsq_impl(F, A0, lda, B, ldb, QtB, ldq, nrhs, X, ldx, r, info, stream);
 }
 
+int tiledqr_zrefactor(tqr_zfactors* F, const double* A, int64_t lda, void* stream);
+
 int tiledqr_zfactor(const tqr_opts* o, const double* A, int64_t lda, tqr_zfactors** out, void* stream) {
   if (!out) return TQR_EINVAL;
   *out = nullptr;
@@ -942,6 +944,16 @@ int tiledqr_zfactor(const tqr_opts* o, const double* A, int64_t lda, tqr_zfactor
   HIP_TRY(hipMemsetAsync(F->taug, 0, ntile * 32 * 16, s));
   HIP_TRY(hipMemsetAsync(F->taup, 0, ntile * 32 * 16, s));
   F->stream = s;
+  st = tiledqr_zrefactor(F.get(), A, lda, stream);
+  if (st != TQR_OK) return st;
+  *out = F.release();
+  return TQR_OK;
+}
+
+int tiledqr_zrefactor(tqr_zfactors* F, const double* A, int64_t lda, void* stream) {
+  if (!F || !A || lda < F->o.m) return TQR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  F->stream = s;
   HIP_TRY(tqr::launch_zpack(const_cast<double*>(A), lda, F->tiles, F->p, F->q, false, s));
   if (F->exec.nsub > 0) {
     const int epoch = ++F->exec.epoch;
@@ -949,7 +961,6 @@ int tiledqr_zfactor(const tqr_opts* o, const double* A, int64_t lda, tqr_zfactor
                             F->exec.nsub, epoch, F->p, 4 * wall_ticks_per_second(),
                             std::max(1, std::min(F->exec.nsub, F->grid)), s));
   }
-  *out = F.release();
   return TQR_OK;
 }
 

@@ -15,6 +15,8 @@
       the same batch under each tree and kernel family of BATCH_TREES
   python -m paper_1104_4475_amd.measure batched-tune  [--count 512]
       the batch autotuner (trees x tile-size rules) on the same batch
+  python -m paper_1104_4475_amd.measure complex
+      the double-complex tiled QR (nb = 32) of square matrices, three trees
 """
 
 import argparse
@@ -194,9 +196,41 @@ def batched(count, seed=6, tree=_lib.TREE_PLASMA, bs=16, kern=_lib.KERN_TS):
         sys.stdout.flush()
 
 
+def complex_qr(sizes=(2048, 4096, 8192), reps=3):
+    """Double-complex tiled QR (nb = 32) of square N(0,1) + i N(0,1)
+    matrices: pack + factorization time (HIP events, best of reps after one
+    warm-up) for three trees; complex flops = 4 (2 m n^2 - 2 n^3 / 3)."""
+    import torch
+    from .api import zfactor
+    cases = [("Greedy, TT", _lib.TREE_GREEDY, 1, _lib.KERN_TT), ("FlatTree, TS", _lib.TREE_FLAT, 1, _lib.KERN_TS),
+             ("PlasmaTree BS=16, TS", _lib.TREE_PLASMA, 16, _lib.KERN_TS)]
+    print("| n | tree | time (ms) | GFLOP/s (real flops) |")
+    print("|---|---|---|---|")
+    for n in sizes:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(3)
+        A = torch.complex(torch.randn((n, n), generator=g, dtype=torch.float64, device="cuda"),
+                          torch.randn((n, n), generator=g, dtype=torch.float64, device="cuda")).t()
+        flops = 4.0 * (2.0 * n ** 3 - 2.0 * n ** 3 / 3.0)
+        for name, tree, bs, kern in cases:
+            F = zfactor(A, 32, tree, bs, kern)
+            F.sync()
+            best = float("inf")
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                F.refactor(A)
+                e1.record()
+                F.sync()
+                best = min(best, e0.elapsed_time(e1))
+            print("| %d | %s | %.2f | %.0f |" % (n, name, best, flops / best / 1e6))
+            sys.stdout.flush()
+            del F
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["trees", "batched", "batched-trees", "batched-tune"])
+    ap.add_argument("what", choices=["trees", "batched", "batched-trees", "batched-tune", "complex"])
     ap.add_argument("--m", type=int, default=16384)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--nb", type=int, default=256)
@@ -213,6 +247,8 @@ def main(argv=None):
         batched_trees(a.count)
     elif a.what == "batched-tune":
         batched_tune(a.count)
+    elif a.what == "complex":
+        complex_qr()
     else:
         batched(a.count, tree=a.tree, bs=a.bs, kern=a.kern)
     return 0

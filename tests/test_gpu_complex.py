@@ -66,6 +66,12 @@ def test_complex_factors_match_oracle(torch_cuda, case):
         assert np.max(np.abs(tg[k - 1, i - 1] - t)) <= 1e-12, ("taug", i, k)
     for (i, k), t in O.tau_p.items():
         assert np.max(np.abs(tp[k - 1, i - 1] - t)) <= 1e-12, ("taup", i, k)
+    # the handle refactors a second matrix into the same storage
+    A2 = _cplx(m, n, 64)
+    F.refactor(_gpu(torch, A2))
+    F.sync()
+    O2 = ztiled.ztiled_qr(A2, 32, tree, bs, kern)
+    assert np.max(np.abs(F.packed().cpu().numpy() - O2.A)) <= 50 * n * EPS * np.linalg.norm(A2)
 
 
 def test_complex_real_input_stays_real_and_diagonal_matrix(torch_cuda):
