@@ -295,6 +295,11 @@ int tiledqr_lstsq_qtb(const tqr_factors* F, const double* A0, int64_t lda,
  * tiledqr_zrefactor: factors a new matrix of the same shape and options
  *   into the handle's storage (no allocation or planning).  Errors:
  *   TQR_EINVAL, TQR_EHIP.
+ * tiledqr_zapply_q: B <- Q^H B (trans 'C') or Q B ('N'); B is device
+ *   memory, m x nrhs column-major complex (ldb >= m complex elements,
+ *   1 <= nrhs <= 4096).  Enqueued on stream (a device scratch copy of B in
+ *   row tiles is allocated and freed on it).  Errors: TQR_EINVAL,
+ *   TQR_ENOMEM, TQR_EHIP.
  * tiledqr_zget_packed: the factored matrix in A's layout (R on and above
  *   the diagonal of the top n rows, the reflectors elsewhere, as LAPACK's
  *   zgeqrf would leave a tile), to device memory out (ld >= m, complex
@@ -308,6 +313,7 @@ int tiledqr_lstsq_qtb(const tqr_factors* F, const double* A0, int64_t lda,
 typedef struct tqr_zfactors tqr_zfactors;
 int tiledqr_zfactor(const tqr_opts* opts, const double* A, int64_t lda, tqr_zfactors** F, void* stream);
 int tiledqr_zrefactor(tqr_zfactors* F, const double* A, int64_t lda, void* stream);
+int tiledqr_zapply_q(tqr_zfactors* F, char trans, double* B, int64_t ldb, int64_t nrhs, void* stream);
 int tiledqr_zget_packed(const tqr_zfactors* F, double* out, int64_t ld, void* stream);
 int tiledqr_zget_tau(const tqr_zfactors* F, double* taug, double* taup, void* stream);
 int tiledqr_zsync(tqr_zfactors* F);

@@ -303,6 +303,15 @@ class ZFactors:
         self._A = A
         check(_lib.tiledqr_zrefactor(self.handle, A.data_ptr(), _ld(A), _stream()), "tiledqr_zrefactor")
 
+    def apply_q(self, B, trans="C"):
+        """Return Q^H B (trans 'C') or Q B ('N') for a complex128 CUDA B with
+        m rows (tiledqr_zapply_q); B is not modified."""
+        B = B if B.dim() == 2 else B[:, None]
+        X = B.t().contiguous().t().clone()
+        check(_lib.tiledqr_zapply_q(self.handle, trans.encode(), X.data_ptr(), _ld(X), X.shape[1], _stream()),
+              "tiledqr_zapply_q")
+        return X
+
     def packed(self):
         """The factored matrix (R and the reflectors) as an m x n complex128
         column-major CUDA tensor."""

@@ -245,7 +245,9 @@ struct tqr_factors {
 struct tqr_zfactors {
   tqr_opts o{};
   int p = 0, q = 0, grid = 1;
+  Plan plan;
   DevPlan exec;
+  std::map<int, DevPlan> apply;  // Q application plans by trans * 1024 + slabs
   double* tiles = nullptr;
   double* taug = nullptr;
   double* taup = nullptr;
@@ -254,6 +256,7 @@ struct tqr_zfactors {
 
   ~tqr_zfactors() {
     exec.release();
+    for (auto& kv : apply) kv.second.release();
     for (void* ptr : {static_cast<void*>(tiles), static_cast<void*>(taug), static_cast<void*>(taup),
                       static_cast<void*>(ctl)})
       if (ptr) (void)hipFree(ptr);
@@ -927,13 +930,12 @@ int tiledqr_zfactor(const tqr_opts* o, const double* A, int64_t lda, tqr_zfactor
   F->o.ib = tqr::IB;
   F->p = static_cast<int>(o->m / 32);
   F->q = static_cast<int>(o->n / 32);
-  Plan plan;
-  if (!tqr::make_plan(F->p, F->q, o->tree, o->bs, o->kernels, plan)) return TQR_EINVAL;
+  if (!tqr::make_plan(F->p, F->q, o->tree, o->bs, o->kernels, F->plan)) return TQR_EINVAL;
   double w[6];
   exec_weights(32, TQR_UPD_F64, w);
   F->grid = device_cus() * tqr::zqr_occupancy();
   ExecPlan ex;
-  tqr::make_exec_plan(plan, 1, exec_order(), w, ex, 1, false, false, F->grid);
+  tqr::make_exec_plan(F->plan, 1, exec_order(), w, ex, 1, false, false, F->grid);
   int st = upload(ex, F->exec);
   if (st != TQR_OK) return st;
   const size_t ntile = static_cast<size_t>(F->p) * F->q;
@@ -962,6 +964,36 @@ int tiledqr_zrefactor(tqr_zfactors* F, const double* A, int64_t lda, void* strea
                             std::max(1, std::min(F->exec.nsub, F->grid)), s));
   }
   return TQR_OK;
+}
+
+int tiledqr_zapply_q(tqr_zfactors* F, char trans, double* B, int64_t ldb, int64_t nrhs, void* stream) {
+  if (!F || !B || nrhs < 1 || ldb < F->o.m || (trans != 'C' && trans != 'N')) return TQR_EINVAL;
+  if (nrhs > 4096) return TQR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int tr = trans == 'C' ? 1 : 0;
+  const int ncolB = static_cast<int>((nrhs + 31) / 32 * 32), nslab = ncolB / 32;
+  const int key = tr * 1024 + nslab;
+  auto it = F->apply.find(key);
+  if (it == F->apply.end()) {
+    ExecPlan ex;
+    tqr::make_apply_plan(F->plan, tr, nslab, ex);
+    DevPlan d;
+    const int st = upload(ex, d);
+    if (st != TQR_OK) return st;
+    it = F->apply.emplace(key, d).first;
+  }
+  DevPlan& d = it->second;
+  double* Bt = nullptr;
+  const size_t bytes = static_cast<size_t>(F->p) * 32 * ncolB * 16;
+  if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Bt), bytes, s))) return TQR_ENOMEM;
+  F->stream = s;
+  hipError_t e = tqr::launch_zpack_b(B, ldb, nrhs, Bt, F->p, ncolB, false, s);
+  if (e == hipSuccess && d.nsub > 0)
+    e = tqr::launch_zqr(F->tiles, F->taug, F->taup, d.sub, d.deps, d.flags, F->ctl, d.nsub, ++d.epoch, F->p,
+                        4 * wall_ticks_per_second(), std::max(1, std::min(d.nsub, F->grid)), s, Bt, ncolB, tr);
+  if (e == hipSuccess) e = tqr::launch_zpack_b(B, ldb, nrhs, Bt, F->p, ncolB, true, s);
+  (void)hipFreeAsync(Bt, s);
+  return hip_ok(e) ? TQR_OK : TQR_EHIP;
 }
 
 int tiledqr_zget_packed(const tqr_zfactors* F, double* out, int64_t ld, void* stream) {

@@ -151,8 +151,11 @@ int batched_occupancy(int upd);
 // a column-major complex matrix into tiles (unpack: back).
 hipError_t launch_zqr(double* tiles, double* taug, double* taup, const DevSub* sub, const int32_t* deps,
                       int32_t* flags, int32_t* ctl, int32_t nsub, int32_t epoch, int32_t p, int64_t spin_ticks,
-                      int grid, hipStream_t s);
+                      int grid, hipStream_t s, double* B = nullptr, int32_t ncolB = 0, int32_t transB = 1);
 hipError_t launch_zpack(double* A, int64_t lda, double* tiles, int p, int q, bool unpack, hipStream_t s);
+// m x nrhs complex B to and from p row tiles of 32 x ncolB (zero padded).
+hipError_t launch_zpack_b(double* Bm, int64_t ldb, int64_t nrhs, double* Bt, int p, int ncolB, bool unpack,
+                          hipStream_t s);
 int zqr_occupancy();
 // All problems' column-major A (device pointer array Aptr, leading
 // dimensions lda) into their tiles; tile_start[i] is the first global tile

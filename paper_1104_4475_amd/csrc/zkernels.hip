@@ -24,8 +24,10 @@
 // finished column's lanes keep the column as it was when its reflector was
 // generated; v is that column times its scale, written at the end.
 //
-// The executor walks the same subtask table as the real executor (one
-// subtask per task at this tile size) with a ticket loop of its own:
+// The executor walks the same subtask tables as the real executor (one
+// subtask per task at this tile size; the Q application plans with one
+// 32-column slab of the right-hand side per subtask) with a ticket loop of
+// its own:
 // subtasks are taken in dispatch order and wait for their predecessors'
 // completion flags (epoch-tagged, so no reset between runs).
 #include <hip/hip_runtime.h>
@@ -266,8 +268,9 @@ __device__ void zpair_task(double* R1, double* A2, double* tau, double* L) {
 // KIND 0: reflectors of a ZGEQRT tile (unit diagonal, rows below it); 1: of
 // a ZTSQRT tile (every row); 2: of a ZTTQRT tile (upper triangle).  C1 (pair
 // kinds: the pivot row's tile, row j touched by reflector j only), C2: the
-// target tile.  Q^H is applied: reflector 0 first, with conj(tau).
-template <int KIND>
+// target tile.  CONJ: Q^H, reflector 0 first with conj(tau); else Q, the
+// last reflector first with tau.
+template <int KIND, bool CONJ>
 __device__ void zupdate_task(const double* V, const double* tau, double* C1, double* C2, double* L) {
   constexpr bool PAIR = KIND != 0;
   const ZPos P;
@@ -278,7 +281,8 @@ __device__ void zupdate_task(const double* V, const double* tau, double* C1, dou
   cd a[ZRPL];
   zload_col(a, C2, c, r0);
 #pragma unroll 1
-  for (int q = 0; q < ZNCH; ++q) {
+  for (int qq = 0; qq < ZNCH; ++qq) {
+    const int q = CONJ ? qq : ZNCH - 1 - qq;
     if (P.wave == 0) {
       if (lane < ZNB) {
 #pragma unroll
@@ -298,11 +302,13 @@ __device__ void zupdate_task(const double* V, const double* tau, double* C1, dou
     }
     __syncthreads();
 #pragma unroll 1
-    for (int i = 0; i < 8; ++i) {
+    for (int ii = 0; ii < 8; ++ii) {
+      const int i = CONJ ? ii : 7 - ii;
       const double* vb = vs + 2 * i * ZNB;
       const cd dot = zdot(vb, a, r0);
       const cd top = PAIR ? lds_cd(c1s + 2 * (i * ZNB + c)) : cd{0.0, 0.0};
-      const cd w = cmul(cconj(lds_cd(tsc + 2 * i)), cd{top.re + dot.re, top.im + dot.im});
+      const cd t = lds_cd(tsc + 2 * i);
+      const cd w = cmul(CONJ ? cconj(t) : t, cd{top.re + dot.re, top.im + dot.im});
       zupdate(vb, a, r0, w);
       if (PAIR && h == 0) lds_st(c1s + 2 * (i * ZNB + c), cd{top.re - w.re, top.im - w.im});
     }
@@ -326,6 +332,9 @@ struct ZArgs {
   int32_t* err;
   int32_t nsub, epoch, p;
   int64_t spin_ticks;
+  double* B;       // Q application: p row tiles of 32 x ncolB complex (ld 32)
+  int32_t ncolB;   // columns of the row tiles, a multiple of 32 (one 32-column slab per subtask)
+  int32_t transB;  // 1: Q^H B, 0: Q B
 };
 
 __device__ __forceinline__ double* ztile(const ZArgs& a, int r, int c) {
@@ -379,15 +388,40 @@ __global__ __launch_bounds__(ZTHREADS) void exec_zqr(ZArgs a) {
     const int k = __builtin_amdgcn_readfirstlane(s.k), j = __builtin_amdgcn_readfirstlane(s.j);
     switch (kind) {
       case D_GEQRT: zgeqrt_task(ztile(a, i, k), ztau(a.taug, a, i, k), L); break;
-      case D_UNMQR: zupdate_task<0>(ztile(a, i, k), ztau(a.taug, a, i, k), nullptr, ztile(a, i, j), L); break;
+      case D_UNMQR: zupdate_task<0, true>(ztile(a, i, k), ztau(a.taug, a, i, k), nullptr, ztile(a, i, j), L); break;
       case D_TSQRT: zpair_task<0>(ztile(a, piv, k), ztile(a, i, k), ztau(a.taup, a, i, k), L); break;
       case D_TTQRT: zpair_task<1>(ztile(a, piv, k), ztile(a, i, k), ztau(a.taup, a, i, k), L); break;
       case D_TSMQR:
-        zupdate_task<1>(ztile(a, i, k), ztau(a.taup, a, i, k), ztile(a, piv, j), ztile(a, i, j), L);
+        zupdate_task<1, true>(ztile(a, i, k), ztau(a.taup, a, i, k), ztile(a, piv, j), ztile(a, i, j), L);
         break;
       case D_TTMQR:
-        zupdate_task<2>(ztile(a, i, k), ztau(a.taup, a, i, k), ztile(a, piv, j), ztile(a, i, j), L);
+        zupdate_task<2, true>(ztile(a, i, k), ztau(a.taup, a, i, k), ztile(a, piv, j), ztile(a, i, j), L);
         break;
+      case D_APPLY_GE:
+      case D_APPLY_TS:
+      case D_APPLY_TT: {
+        const size_t off = 2 * static_cast<size_t>(__builtin_amdgcn_readfirstlane(s.slab)) * ZNB * ZNB;
+        double* Bi = a.B + 2 * static_cast<size_t>(i) * ZNB * a.ncolB + off;
+        double* Bp = a.B + 2 * static_cast<size_t>(piv) * ZNB * a.ncolB + off;
+        const double* V = ztile(a, i, k);
+        if (kind == D_APPLY_GE) {
+          if (a.transB)
+            zupdate_task<0, true>(V, ztau(a.taug, a, i, k), nullptr, Bi, L);
+          else
+            zupdate_task<0, false>(V, ztau(a.taug, a, i, k), nullptr, Bi, L);
+        } else if (kind == D_APPLY_TS) {
+          if (a.transB)
+            zupdate_task<1, true>(V, ztau(a.taup, a, i, k), Bp, Bi, L);
+          else
+            zupdate_task<1, false>(V, ztau(a.taup, a, i, k), Bp, Bi, L);
+        } else {
+          if (a.transB)
+            zupdate_task<2, true>(V, ztau(a.taup, a, i, k), Bp, Bi, L);
+          else
+            zupdate_task<2, false>(V, ztau(a.taup, a, i, k), Bp, Bi, L);
+        }
+        break;
+      }
       default: break;
     }
     // publish once every lane's stores are complete
@@ -423,13 +457,50 @@ __global__ void zpack_kernel(double* A, int64_t lda, double* tiles, int p, int q
   }
 }
 
+// m x nrhs column-major complex B (ldb) to and from p row tiles of 32 x
+// ncolB (ld 32; columns nrhs .. ncolB - 1 zero when packing).
+__global__ void zpack_b_kernel(double* Bm, int64_t ldb, int64_t nrhs, double* Bt, int p, int ncolB, bool unpack) {
+  const int64_t total = static_cast<int64_t>(p) * ZNB * ncolB;
+  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
+       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    const int64_t t = e / (static_cast<int64_t>(ZNB) * ncolB), w = e % (static_cast<int64_t>(ZNB) * ncolB);
+    const int64_t col = w / ZNB, row = t * ZNB + w % ZNB;
+    double* T = Bt + 2 * e;
+    if (col >= nrhs) {
+      if (!unpack) {
+        T[0] = 0.0;
+        T[1] = 0.0;
+      }
+      continue;
+    }
+    double* M = Bm + 2 * (col * ldb + row);
+    if (unpack) {
+      M[0] = T[0];
+      M[1] = T[1];
+    } else {
+      T[0] = M[0];
+      T[1] = M[1];
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t launch_zpack_b(double* Bm, int64_t ldb, int64_t nrhs, double* Bt, int p, int ncolB, bool unpack,
+                          hipStream_t s) {
+  const int64_t total = static_cast<int64_t>(p) * ZNB * ncolB;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(zpack_b_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, Bm, ldb, nrhs, Bt, p,
+                     ncolB, unpack);
+  return hipGetLastError();
+}
 
 hipError_t launch_zqr(double* tiles, double* taug, double* taup, const DevSub* sub, const int32_t* deps,
                       int32_t* flags, int32_t* ctl, int32_t nsub, int32_t epoch, int32_t p, int64_t spin_ticks,
-                      int grid, hipStream_t s) {
+                      int grid, hipStream_t s, double* B, int32_t ncolB, int32_t transB) {
   hipLaunchKernelGGL(zreset_kernel, dim3(1), dim3(1), 0, s, ctl, ctl + 1);
-  ZArgs a{tiles, taug, taup, sub, deps, flags, ctl, ctl + 1, nsub, epoch, p, spin_ticks};
+  ZArgs a{tiles, taug, taup, sub, deps, flags, ctl, ctl + 1, nsub, epoch, p, spin_ticks, B, ncolB, transB};
   hipLaunchKernelGGL(exec_zqr, dim3(grid), dim3(ZTHREADS), 0, s, a);
   return hipGetLastError();
 }

@@ -105,3 +105,31 @@ def test_complex_tile_size_other_than_32_is_unsupported(torch_cuda):
     with pytest.raises(_lib.TiledQRError) as e:
         tqr.zfactor(A, 64)
     assert e.value.status == _lib.TQR_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("case", [(256, 128, trees.GREEDY, 1, dag.KERN_TT), (320, 192, trees.FLAT, 1, dag.KERN_TS),
+                                  (512, 256, trees.PLASMA, 4, dag.KERN_TS)],
+                         ids=lambda c: "%dx%d_t%d_bs%d_k%d" % c)
+def test_complex_apply_q_residual_and_orthogonality(torch_cuda, case):
+    """Q^H B and Q B against the complex oracle (5 and 40 right-hand
+    sides: one and two 32-column slabs), and the GPU's own Q: ||A - QR||_F /
+    ||A||_F and ||Q^H Q - I||_F within 50 n eps."""
+    import paper_1104_4475_amd as tqr
+    torch = torch_cuda
+    m, n, tree, bs, kern = case
+    _say("complex apply_q %s" % (case,))
+    A = _cplx(m, n, 65)
+    F = tqr.zfactor(_gpu(torch, A), 32, tree, bs, kern)
+    O = ztiled.ztiled_qr(A, 32, tree, bs, kern)
+    for nrhs in (5, 40):
+        B = _cplx(m, nrhs, 66 + nrhs)
+        for trans in ("C", "N"):
+            got = F.apply_q(_gpu(torch, B), trans).cpu().numpy()
+            want = ztiled.zapply_q(O, B, trans)
+            assert np.max(np.abs(got - want)) <= 50 * n * EPS * np.linalg.norm(B), (nrhs, trans)
+    E = np.zeros((m, n), dtype=np.complex128)
+    E[:n, :n] = np.eye(n)
+    Q = F.apply_q(_gpu(torch, E), "N").cpu().numpy()
+    R = np.triu(F.packed().cpu().numpy()[:n, :n])
+    assert np.linalg.norm(A - Q @ R) / np.linalg.norm(A) <= 50 * n * EPS
+    assert np.linalg.norm(Q.conj().T @ Q - np.eye(n)) <= 50 * n * EPS
