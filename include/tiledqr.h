@@ -300,6 +300,12 @@ int tiledqr_lstsq_qtb(const tqr_factors* F, const double* A0, int64_t lda,
  *   1 <= nrhs <= 4096).  Enqueued on stream (a device scratch copy of B in
  *   row tiles is allocated and freed on it).  Errors: TQR_EINVAL,
  *   TQR_ENOMEM, TQR_EHIP.
+ * tiledqr_zsolve_r: X <- R^{-1} X (X: device, n x nrhs complex, ldx >= n);
+ *   back substitution, n <= 4096 (else TQR_EINVAL).  Enqueued on stream.
+ * tiledqr_zlstsq: X (n x nrhs, ldx) = argmin ||B - A X||_2 column by column,
+ *   X = R^{-1} (Q^H B)(1:n) (Sec. 1); B (m x nrhs, ldb) is not modified.
+ *   n <= 4096.  Enqueued on stream (scratch allocated and freed on it).
+ *   Errors: TQR_EINVAL, TQR_ENOMEM, TQR_EHIP.
  * tiledqr_zget_packed: the factored matrix in A's layout (R on and above
  *   the diagonal of the top n rows, the reflectors elsewhere, as LAPACK's
  *   zgeqrf would leave a tile), to device memory out (ld >= m, complex
@@ -314,6 +320,9 @@ typedef struct tqr_zfactors tqr_zfactors;
 int tiledqr_zfactor(const tqr_opts* opts, const double* A, int64_t lda, tqr_zfactors** F, void* stream);
 int tiledqr_zrefactor(tqr_zfactors* F, const double* A, int64_t lda, void* stream);
 int tiledqr_zapply_q(tqr_zfactors* F, char trans, double* B, int64_t ldb, int64_t nrhs, void* stream);
+int tiledqr_zsolve_r(const tqr_zfactors* F, double* X, int64_t ldx, int64_t nrhs, void* stream);
+int tiledqr_zlstsq(tqr_zfactors* F, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
+                   void* stream);
 int tiledqr_zget_packed(const tqr_zfactors* F, double* out, int64_t ld, void* stream);
 int tiledqr_zget_tau(const tqr_zfactors* F, double* taug, double* taup, void* stream);
 int tiledqr_zsync(tqr_zfactors* F);

@@ -84,6 +84,8 @@ _sigs = {
     "tiledqr_zfactor": (ctypes.c_int, [_P(Opts), _vp, _i64, _P(_vp), _vp]),
     "tiledqr_zrefactor": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
     "tiledqr_zapply_q": (ctypes.c_int, [_vp, ctypes.c_char, _vp, _i64, _i64, _vp]),
+    "tiledqr_zsolve_r": (ctypes.c_int, [_vp, _vp, _i64, _i64, _vp]),
+    "tiledqr_zlstsq": (ctypes.c_int, [_vp, _vp, _i64, _i64, _vp, _i64, _vp]),
     "tiledqr_zget_packed": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
     "tiledqr_zget_tau": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "tiledqr_zsync": (ctypes.c_int, [_vp]),

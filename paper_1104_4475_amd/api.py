@@ -312,6 +312,24 @@ class ZFactors:
               "tiledqr_zapply_q")
         return X
 
+    def lstsq(self, B):
+        """Least-squares solution X (n x nrhs, complex128 CUDA) of A X ~ B
+        (tiledqr_zlstsq)."""
+        import torch
+        B = B if B.dim() == 2 else B[:, None]
+        B = B.t().contiguous().t()
+        X = torch.empty((B.shape[1], self.n), dtype=torch.complex128, device="cuda").t()
+        check(_lib.tiledqr_zlstsq(self.handle, B.data_ptr(), _ld(B), B.shape[1], X.data_ptr(), _ld(X), _stream()),
+              "tiledqr_zlstsq")
+        torch.cuda.current_stream().synchronize()
+        return X
+
+    def solve_r(self, X):
+        """R^{-1} X for a complex128 CUDA X with n rows (tiledqr_zsolve_r)."""
+        X = (X if X.dim() == 2 else X[:, None]).t().contiguous().t().clone()
+        check(_lib.tiledqr_zsolve_r(self.handle, X.data_ptr(), _ld(X), X.shape[1], _stream()), "tiledqr_zsolve_r")
+        return X
+
     def packed(self):
         """The factored matrix (R and the reflectors) as an m x n complex128
         column-major CUDA tensor."""

@@ -996,6 +996,34 @@ int tiledqr_zapply_q(tqr_zfactors* F, char trans, double* B, int64_t ldb, int64_
   return hip_ok(e) ? TQR_OK : TQR_EHIP;
 }
 
+int tiledqr_zsolve_r(const tqr_zfactors* F, double* X, int64_t ldx, int64_t nrhs, void* stream) {
+  if (!F || !X || ldx < F->o.n || nrhs < 1 || F->o.n > 4096) return TQR_EINVAL;
+  HIP_TRY(tqr::launch_zsolve_r(F->tiles, F->p, static_cast<int>(F->o.n), X, ldx, nrhs,
+                               static_cast<hipStream_t>(stream)));
+  return TQR_OK;
+}
+
+int tiledqr_zlstsq(tqr_zfactors* F, const double* B, int64_t ldb, int64_t nrhs, double* X, int64_t ldx,
+                   void* stream) {
+  if (!F || !B || !X || nrhs < 1 || ldb < F->o.m || ldx < F->o.n || F->o.n > 4096) return TQR_EINVAL;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int64_t m = F->o.m, n = F->o.n;
+  double* W = nullptr;
+  if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&W), static_cast<size_t>(m) * nrhs * 16, s))) return TQR_ENOMEM;
+  auto done = [&](int code) {
+    (void)hipFreeAsync(W, s);
+    return code;
+  };
+  if (!hip_ok(hipMemcpy2DAsync(W, m * 16, B, ldb * 16, m * 16, nrhs, hipMemcpyDeviceToDevice, s)))
+    return done(TQR_EHIP);
+  const int st = tiledqr_zapply_q(F, 'C', W, m, nrhs, stream);
+  if (st != TQR_OK) return done(st);
+  if (!hip_ok(hipMemcpy2DAsync(X, ldx * 16, W, m * 16, n * 16, nrhs, hipMemcpyDeviceToDevice, s)) ||
+      !hip_ok(tqr::launch_zsolve_r(F->tiles, F->p, static_cast<int>(n), X, ldx, nrhs, s)))
+    return done(TQR_EHIP);
+  return done(TQR_OK);
+}
+
 int tiledqr_zget_packed(const tqr_zfactors* F, double* out, int64_t ld, void* stream) {
   if (!F || !out || ld < F->o.m) return TQR_EINVAL;
   HIP_TRY(tqr::launch_zpack(out, ld, F->tiles, F->p, F->q, true, static_cast<hipStream_t>(stream)));

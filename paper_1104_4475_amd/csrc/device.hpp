@@ -153,6 +153,9 @@ hipError_t launch_zqr(double* tiles, double* taug, double* taup, const DevSub* s
                       int32_t* flags, int32_t* ctl, int32_t nsub, int32_t epoch, int32_t p, int64_t spin_ticks,
                       int grid, hipStream_t s, double* B = nullptr, int32_t ncolB = 0, int32_t transB = 1);
 hipError_t launch_zpack(double* A, int64_t lda, double* tiles, int p, int q, bool unpack, hipStream_t s);
+// X <- R^{-1} X (n x nrhs complex, ldx) for the complex R in the tiles of a
+// p-row grid; n <= 4096 (else hipErrorInvalidValue).
+hipError_t launch_zsolve_r(const double* tiles, int p, int n, double* X, int64_t ldx, int64_t nrhs, hipStream_t s);
 // m x nrhs complex B to and from p row tiles of 32 x ncolB (zero padded).
 hipError_t launch_zpack_b(double* Bm, int64_t ldb, int64_t nrhs, double* Bt, int p, int ncolB, bool unpack,
                           hipStream_t s);

@@ -484,7 +484,47 @@ __global__ void zpack_b_kernel(double* Bm, int64_t ldb, int64_t nrhs, double* Bt
   }
 }
 
+// X <- R^{-1} X for the upper triangular n x n complex R held in the tiles
+// (top q tile rows): one workgroup per right-hand side, the column in LDS,
+// back substitution with the column of R below the pivot applied by all
+// threads (n <= ZSOLVE_MAX).
+constexpr int ZSOLVE_MAX = 4096;
+__global__ __launch_bounds__(256) void zsolve_r_kernel(const double* tiles, int p, int n, double* X, int64_t ldx) {
+  __shared__ __attribute__((aligned(16))) double xs[2 * ZSOLVE_MAX];
+  double* x = X + 2 * static_cast<int64_t>(blockIdx.x) * ldx;
+  for (int r = threadIdx.x; r < n; r += blockDim.x) lds_st(xs + 2 * r, cd{x[2 * r], x[2 * r + 1]});
+  __syncthreads();
+  for (int i = n - 1; i >= 0; --i) {
+    const int ti = i / ZNB, ci = i % ZNB;
+    const double* colt = tiles;  // column i of R: tiles (tr, ti), tr <= ti
+    const cd rii = zld(colt + 2 * ((static_cast<size_t>(ti) * p + ti) * ZNB * ZNB + ci * ZNB + ci));
+    const cd bi = lds_cd(xs + 2 * i);
+    const double den = rii.re * rii.re + rii.im * rii.im;
+    const cd xi = cd{(bi.re * rii.re + bi.im * rii.im) / den, (bi.im * rii.re - bi.re * rii.im) / den};
+    __syncthreads();
+    if (threadIdx.x == 0) lds_st(xs + 2 * i, xi);
+    for (int r = threadIdx.x; r < i; r += blockDim.x) {
+      const cd rri = zld(colt + 2 * ((static_cast<size_t>(ti) * p + r / ZNB) * ZNB * ZNB + ci * ZNB + r % ZNB));
+      cd b = lds_cd(xs + 2 * r);
+      csub_mul(b, xi, rri);
+      lds_st(xs + 2 * r, b);
+    }
+    __syncthreads();
+  }
+  for (int r = threadIdx.x; r < n; r += blockDim.x) {
+    const cd v = lds_cd(xs + 2 * r);
+    x[2 * r] = v.re;
+    x[2 * r + 1] = v.im;
+  }
+}
+
 }  // namespace
+
+hipError_t launch_zsolve_r(const double* tiles, int p, int n, double* X, int64_t ldx, int64_t nrhs, hipStream_t s) {
+  if (n > ZSOLVE_MAX || nrhs < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(zsolve_r_kernel, dim3(static_cast<unsigned>(nrhs)), dim3(256), 0, s, tiles, p, n, X, ldx);
+  return hipGetLastError();
+}
 
 hipError_t launch_zpack_b(double* Bm, int64_t ldb, int64_t nrhs, double* Bt, int p, int ncolB, bool unpack,
                           hipStream_t s) {

@@ -133,3 +133,29 @@ def test_complex_apply_q_residual_and_orthogonality(torch_cuda, case):
     R = np.triu(F.packed().cpu().numpy()[:n, :n])
     assert np.linalg.norm(A - Q @ R) / np.linalg.norm(A) <= 50 * n * EPS
     assert np.linalg.norm(Q.conj().T @ Q - np.eye(n)) <= 50 * n * EPS
+
+
+@pytest.mark.parametrize("case", [(256, 128, trees.GREEDY, 1, dag.KERN_TT), (512, 256, trees.FLAT, 1, dag.KERN_TS),
+                                  (320, 320, trees.FIBONACCI, 1, dag.KERN_TT)],
+                         ids=lambda c: "%dx%d_t%d_bs%d_k%d" % c)
+def test_complex_least_squares_matches_lapack(torch_cuda, case):
+    """X = R^{-1} (Q^H B)(1:n) against LAPACK's complex least squares
+    (numpy.linalg.lstsq) within 10 kappa n eps relative, and R^{-1} X
+    against a dense triangular solve of the GPU's own R."""
+    import paper_1104_4475_amd as tqr
+    from scipy.linalg import solve_triangular
+    torch = torch_cuda
+    m, n, tree, bs, kern = case
+    _say("complex lstsq %s" % (case,))
+    A = _cplx(m, n, 71)
+    B = _cplx(m, 3, 72)
+    F = tqr.zfactor(_gpu(torch, A), 32, tree, bs, kern)
+    X = F.lstsq(_gpu(torch, B)).cpu().numpy()
+    Xn = np.linalg.lstsq(A, B, rcond=None)[0]
+    kappa = np.linalg.cond(A)
+    assert np.linalg.norm(X - Xn) / np.linalg.norm(Xn) <= 10 * kappa * n * EPS
+    R = np.triu(F.packed().cpu().numpy()[:n, :n])
+    Y = _cplx(n, 2, 73)
+    got = F.solve_r(_gpu(torch, Y)).cpu().numpy()
+    want = solve_triangular(R, Y, lower=False)
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) <= 10 * np.linalg.cond(R) * n * EPS
