@@ -1147,33 +1147,27 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
       !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&D), nx_bytes, s)) ||
       !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Xp), nx_bytes, s)) ||
       !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&Xb), nx_bytes, s)) ||
-      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&nrm), 4 * nrhs * sizeof(double), s)))
+      !hip_ok(hipMallocAsync(reinterpret_cast<void**>(&nrm), (4 * nrhs + 1) * sizeof(double), s)))
     return fail(TQR_ENOMEM);
   // Corrections: semi-normal (method 3, and method 0 while each one cuts
   // the backward error at least fourfold) or, after that, classical with Q
   // (square) or the augmented system (tall).
   bool semi = r->method == 0 || r->method == 3;
-  // nrm: ||r||^2, ||x||^2, ||b||^2 (once), ||A^T r||^2 (tall) per column.
-  if (!hip_ok(hipMemsetAsync(nrm, 0, 4 * nrhs * sizeof(double), s))) return fail(TQR_EHIP);
-  std::vector<double> colA(static_cast<size_t>(n));
-  {
-    double* ca = nullptr;
-    if (!hip_ok(hipMallocAsync(reinterpret_cast<void**>(&ca), n * sizeof(double), s))) return fail(TQR_ENOMEM);
-    (void)hipMemsetAsync(ca, 0, n * sizeof(double), s);
-    bool ok = hip_ok(tqr::launch_colnorms2(A0, lda, m, n, ca, s)) &&
-              hip_ok(hipMemcpyAsync(colA.data(), ca, n * sizeof(double), hipMemcpyDeviceToHost, s)) &&
-              hip_ok(tqr::launch_colnorms2(B, ldb, m, nrhs, nrm + 2 * nrhs, s));
-    (void)hipFreeAsync(ca, s);
-    if (!ok) return fail(TQR_EHIP);
-  }
-  std::vector<double> h(4 * nrhs);
+  // nrm: ||r||^2, ||x||^2, ||b||^2 (once), ||A^T r||^2 (tall) per column,
+  // then ||A||_F^2 (from the first residual, which reads all of A).
+  if (!hip_ok(hipMemsetAsync(nrm, 0, (4 * nrhs + 1) * sizeof(double), s)) ||
+      !hip_ok(tqr::launch_colnorms2(B, ldb, m, nrhs, nrm + 2 * nrhs, s)))
+    return fail(TQR_EHIP);
+  std::vector<double> h(4 * nrhs + 1);
+  double fa = 0.0;
   double best = INFINITY, eta = INFINITY;
   std::vector<double> hist;
   int it = 0, nsemi = 0;
   bool conv = false;
   for (;; ++it) {
     // residual and norms (tall: also A^T r into D, used by the correction)
-    if (!hip_ok(tqr::launch_residual(A0, lda, m, n, X, ldx, B, ldb, nrhs, Rv, m, s))) return fail(TQR_EHIP);
+    if (!hip_ok(tqr::launch_residual(A0, lda, m, n, X, ldx, B, ldb, nrhs, Rv, m, s, it == 0 ? nrm + 4 * nrhs : nullptr)))
+      return fail(TQR_EHIP);
     if (!hip_ok(hipMemsetAsync(nrm, 0, 2 * nrhs * sizeof(double), s))) return fail(TQR_EHIP);
     if (!hip_ok(tqr::launch_colnorms2(Rv, m, m, nrhs, nrm, s)) ||
         !hip_ok(tqr::launch_colnorms2(X, ldx, n, nrhs, nrm + nrhs, s)))
@@ -1183,14 +1177,12 @@ int lstsq_impl(const tqr_factors* F, const double* A0, int64_t lda, const double
                  !hip_ok(tqr::launch_colnorms2(D, n, n, nrhs, nrm + 3 * nrhs, s))))
       return fail(TQR_EHIP);
     int32_t serr = 0;
-    if (!hip_ok(hipMemcpyAsync(h.data(), nrm, 4 * nrhs * sizeof(double), hipMemcpyDeviceToHost, s)) ||
+    if (!hip_ok(hipMemcpyAsync(h.data(), nrm, (4 * nrhs + 1) * sizeof(double), hipMemcpyDeviceToHost, s)) ||
         !hip_ok(hipMemcpyAsync(&serr, F->ctl + 2, sizeof(int32_t), hipMemcpyDeviceToHost, s)) ||
         !hip_ok(hipStreamSynchronize(s)))
       return fail(TQR_EHIP);
     if (serr) return fail(TQR_EEXEC);
-    double fa = 0.0;
-    for (double v : colA) fa += v;
-    fa = std::sqrt(fa);
+    if (it == 0) fa = std::sqrt(h[4 * nrhs]);
     eta = 0.0;
     for (int64_t c = 0; c < nrhs; ++c) {
       const double nr = std::sqrt(h[c]);

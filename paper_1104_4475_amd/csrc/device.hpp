@@ -133,8 +133,10 @@ hipError_t launch_trinv(const double* tiles, int p, int q, int nb, double* Rinv,
 // out (n x nrhs, ldo) = sign * A^T Y for A m x n (lda), Y m x nrhs (ldy).
 hipError_t launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* Y, int64_t ldy,
                          int64_t nrhs, double* out, int64_t ldo, double sign, hipStream_t s);
+// Rv = B - A X; with fro2, ||A||_F^2 is added to *fro2 (zeroed by the caller).
 hipError_t launch_residual(const double* A, int64_t lda, int64_t m, int64_t n, const double* X, int64_t ldx,
-                           const double* B, int64_t ldb, int64_t nrhs, double* Rv, int64_t ldr, hipStream_t s);
+                           const double* B, int64_t ldb, int64_t nrhs, double* Rv, int64_t ldr, hipStream_t s,
+                           double* fro2 = nullptr);
 hipError_t launch_colnorms2(const double* M, int64_t ld, int64_t rows, int64_t cols, double* out, hipStream_t s);
 // X += alpha D (rows x cols); D -> copy of S.
 hipError_t launch_axpy_cols(double* X, int64_t ldx, const double* D, int64_t ldd, int64_t rows, int64_t cols,

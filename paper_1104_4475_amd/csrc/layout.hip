@@ -7,15 +7,30 @@ namespace tqr {
 
 // ---- layout conversions ------------------------------------------------------
 
-// Column-major A (lda) -> tiles.  One thread per element of the tile matrix.
-__global__ void pack_kernel(const double* A, int64_t lda, double* tiles, int p, int q, int nb) {
-  const int64_t m = static_cast<int64_t>(p) * nb;
-  const int64_t total = m * q * nb;
-  for (int64_t e = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; e < total;
-       e += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-    const int64_t col = e / m, row = e - col * m;
-    const int64_t r = row / nb, c = col / nb;
-    tiles[(c * p + r) * nb * nb + (col - c * nb) * nb + (row - r * nb)] = A[col * lda + row];
+// Column-major A (lda) -> tiles.  A column's rows in one tile row are a
+// contiguous run both in A and in the tile, so block (g, y) copies the runs
+// of columns g * 1024 / nb .. (1024 doubles) for tile rows y, y + gridDim.y,
+// ...: four doubles per thread, each load instruction 64 consecutive
+// doubles, all loads issued before the stores.  nb is a power of two <= 1024.
+__global__ __launch_bounds__(256) void pack_kernel(const double* A, int64_t lda, double* tiles, int p, int q, int nb) {
+  const int lg = __builtin_ctz(nb);
+  const int64_t n = static_cast<int64_t>(q) << lg;
+  const int64_t col0 = static_cast<int64_t>(blockIdx.x) * (1024 >> lg);
+  for (int r = blockIdx.y; r < p; r += gridDim.y) {
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      const int64_t col = col0 + (e >> lg);
+      v[k] = col < n ? A[col * lda + (static_cast<int64_t>(r) << lg) + (e & (nb - 1))] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = threadIdx.x + 256 * k;
+      const int64_t col = col0 + (e >> lg);
+      if (col < n)
+        tiles[(((col >> lg) * p + r) << (2 * lg)) + ((col & (nb - 1)) << lg) + (e & (nb - 1))] = v[k];
+    }
   }
 }
 
@@ -104,8 +119,11 @@ static int grid_for(int64_t total) {
 }
 
 hipError_t launch_pack(const double* A, int64_t lda, double* tiles, int p, int q, int nb, hipStream_t s) {
-  const int64_t total = static_cast<int64_t>(p) * nb * q * nb;
-  hipLaunchKernelGGL(pack_kernel, dim3(grid_for(total)), dim3(256), 0, s, A, lda, tiles, p, q, nb);
+  if (nb <= 0 || nb > 1024 || (nb & (nb - 1)) != 0) return hipErrorInvalidValue;
+  if (p <= 0 || q <= 0) return hipSuccess;
+  const int64_t groups = (static_cast<int64_t>(q) * nb + (1024 / nb) - 1) / (1024 / nb);
+  const dim3 grid(static_cast<unsigned>(groups), static_cast<unsigned>(p < 65535 ? p : 65535));
+  hipLaunchKernelGGL(pack_kernel, grid, dim3(256), 0, s, A, lda, tiles, p, q, nb);
   return hipGetLastError();
 }
 hipError_t launch_unpack(const double* tiles, double* out, int64_t ld, int p, int q, int nb, int rows, int cols,

@@ -620,80 +620,121 @@ __global__ __launch_bounds__(256) void transpose_tiles_kernel(const double* src,
 }
 
 // out[c * ldo + j] = sign * sum_r A[j * lda + r] Y[c * ldy + r] for j < n,
-// c < nrhs: one wave per column j (read once per 4 right-hand sides), lanes
-// over rows.
+// c < nrhs: one wave per GV_COLS consecutive columns (each load of Y serves
+// all of them; the last wave's missing columns re-read column n - 1 and are
+// not written), lanes over rows, eight rows per lane per pass with every
+// load issued before the products, up to four right-hand sides per pass.
+constexpr int GV_COLS = 4;
 __global__ __launch_bounds__(256) void gemv_t_kernel(const double* A, int64_t lda, int64_t m, int64_t n,
                                                      const double* Y, int64_t ldy, int64_t nrhs, double* out,
                                                      int64_t ldo, double sign) {
-  const int64_t j = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int64_t j0 = ((static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) >> 6) * GV_COLS;
   const int lane = threadIdx.x & 63;
-  if (j >= n) return;
-  const double* a = A + j * lda;
-  for (int64_t c0 = 0; c0 < nrhs; c0 += 4) {
-    double s[4] = {0.0, 0.0, 0.0, 0.0};
-    int64_t r = lane;
-    // Eight rows per lane per pass, loads issued before the products.
-    for (; r + 7 * 64 < m; r += 8 * 64) {
-      double v[8];
+  if (j0 >= n) return;
+  const double* a[GV_COLS];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = a[r + 64 * u];
+  for (int q = 0; q < GV_COLS; ++q) a[q] = A + (j0 + q < n ? j0 + q : n - 1) * lda;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += 4) {
+    double s[GV_COLS][4] = {};
+    int64_t r = lane;
+    for (; r + 7 * 64 < m; r += 8 * 64) {
+      double v[GV_COLS][8];
+#pragma unroll
+      for (int q = 0; q < GV_COLS; ++q)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[q][u] = a[q][r + 64 * u];
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
         if (c0 + h >= nrhs) continue;
         const double* y = Y + (c0 + h) * ldy + r;
+        double yv[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s[h] += v[u] * y[64 * u];
+        for (int u = 0; u < 8; ++u) yv[u] = y[64 * u];
+#pragma unroll
+        for (int q = 0; q < GV_COLS; ++q)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) s[q][h] += v[q][u] * yv[u];
       }
     }
     for (; r < m; r += 64) {
-      const double v = a[r];
 #pragma unroll
-      for (int h = 0; h < 4; ++h)
-        if (c0 + h < nrhs) s[h] += v * Y[(c0 + h) * ldy + r];
+      for (int h = 0; h < 4; ++h) {
+        if (c0 + h >= nrhs) continue;
+        const double yv = Y[(c0 + h) * ldy + r];
+#pragma unroll
+        for (int q = 0; q < GV_COLS; ++q) s[q][h] += a[q][r] * yv;
+      }
     }
 #pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      double t = s[h];
-      for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
-      if (lane == 0 && c0 + h < nrhs) out[(c0 + h) * ldo + j] = sign * t;
-    }
+    for (int q = 0; q < GV_COLS; ++q)
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        double t = s[q][h];
+        for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off, 64);
+        if (lane == 0 && c0 + h < nrhs && j0 + q < n) out[(c0 + h) * ldo + j0 + q] = sign * t;
+      }
   }
 }
 
 // Rv = B - A X for m x n A; grid (row blocks, column chunks), partial sums
-// subtracted with FP64 atomics (Rv must hold B on entry).
-constexpr int RES_CHUNK = 256;
+// subtracted with FP64 atomics (Rv must hold B on entry).  The chunk's rows
+// of X (four right-hand sides per pass) are staged once per workgroup in
+// LDS, interleaved by right-hand side, and each thread streams its row of
+// A sixteen columns at a time.  With fro2, the sum of squares of the
+// elements of A read (each once, in the first pass) is added to *fro2: one
+// atomic per workgroup.
+constexpr int RES_CHUNK = 512;
+constexpr int RES_STEP = 16;
 __global__ __launch_bounds__(256) void residual_kernel(const double* A, int64_t lda, int64_t m, int64_t n,
                                                        const double* X, int64_t ldx, int64_t nrhs, double* Rv,
-                                                       int64_t ldr) {
+                                                       int64_t ldr, double* fro2) {
+  __shared__ __attribute__((aligned(16))) double xs[4 * RES_CHUNK];
+  __shared__ double red[4];
+  double sq = 0.0;
   const int64_t row = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   const int64_t c0 = static_cast<int64_t>(blockIdx.y) * RES_CHUNK;
-  const int64_t c1 = (c0 + RES_CHUNK < n) ? c0 + RES_CHUNK : n;
-  if (row >= m) return;
+  const int nc = static_cast<int>((c0 + RES_CHUNK < n) ? RES_CHUNK : n - c0);
+  const double* arow = A + c0 * lda + (row < m ? row : 0);
   for (int64_t h0 = 0; h0 < nrhs; h0 += 4) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 4 * RES_CHUNK; e += blockDim.x) {
+      const int c = e >> 2, h = e & 3;
+      xs[e] = (c < nc && h0 + h < nrhs) ? X[(h0 + h) * ldx + c0 + c] : 0.0;
+    }
+    __syncthreads();
+    if (row >= m) continue;
     double s[4] = {0.0, 0.0, 0.0, 0.0};
-    int64_t c = c0;
-    // Eight columns per pass, loads issued before the products.
-    for (; c + 8 <= c1; c += 8) {
-      double a[8];
+    int c = 0;
+    for (; c + RES_STEP <= nc; c += RES_STEP) {
+      double a[RES_STEP];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) a[u] = A[(c + u) * lda + row];
+      for (int u = 0; u < RES_STEP; ++u) a[u] = arow[(c + u) * lda];
 #pragma unroll
-      for (int h = 0; h < 4; ++h) {
-        if (h0 + h >= nrhs) continue;
+      for (int u = 0; u < RES_STEP; ++u) {
+        const double* x = xs + 4 * (c + u);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) s[h] += a[u] * X[(h0 + h) * ldx + c + u];
+        for (int h = 0; h < 4; ++h) s[h] += a[u] * x[h];
+      }
+      if (fro2 && h0 == 0) {
+#pragma unroll
+        for (int u = 0; u < RES_STEP; ++u) sq += a[u] * a[u];
       }
     }
-    for (; c < c1; ++c) {
-      const double a = A[c * lda + row];
+    for (; c < nc; ++c) {
+      const double a = arow[c * lda];
 #pragma unroll
-      for (int h = 0; h < 4; ++h)
-        if (h0 + h < nrhs) s[h] += a * X[(h0 + h) * ldx + c];
+      for (int h = 0; h < 4; ++h) s[h] += a * xs[4 * c + h];
+      if (h0 == 0) sq += a * a;
     }
 #pragma unroll
     for (int h = 0; h < 4; ++h)
       if (h0 + h < nrhs) atomicAdd(Rv + (h0 + h) * ldr + row, -s[h]);
+  }
+  if (fro2) {
+    for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(fro2, red[0] + red[1] + red[2] + red[3]);
   }
 }
 
@@ -873,7 +914,7 @@ hipError_t launch_trinv(const double* tiles, int p, int q, int nb, double* Rinv,
 
 hipError_t launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, const double* Y, int64_t ldy,
                          int64_t nrhs, double* out, int64_t ldo, double sign, hipStream_t s) {
-  const int64_t threads = n * 64;
+  const int64_t threads = (n + GV_COLS - 1) / GV_COLS * 64;
   if (threads == 0 || nrhs == 0) return hipSuccess;
   hipLaunchKernelGGL(gemv_t_kernel, dim3(static_cast<unsigned>((threads + 255) / 256)), dim3(256), 0, s, A, lda, m,
                      n, Y, ldy, nrhs, out, ldo, sign);
@@ -881,10 +922,11 @@ hipError_t launch_gemv_t(const double* A, int64_t lda, int64_t m, int64_t n, con
 }
 
 hipError_t launch_residual(const double* A, int64_t lda, int64_t m, int64_t n, const double* X, int64_t ldx,
-                           const double* B, int64_t ldb, int64_t nrhs, double* Rv, int64_t ldr, hipStream_t s) {
+                           const double* B, int64_t ldb, int64_t nrhs, double* Rv, int64_t ldr, hipStream_t s,
+                           double* fro2) {
   hipLaunchKernelGGL(copy_cols_kernel, dim3(grid_of(m * nrhs)), dim3(256), 0, s, B, ldb, Rv, ldr, m, nrhs);
   const dim3 grid(static_cast<unsigned>((m + 255) / 256), static_cast<unsigned>((n + RES_CHUNK - 1) / RES_CHUNK));
-  hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, s, A, lda, m, n, X, ldx, nrhs, Rv, ldr);
+  hipLaunchKernelGGL(residual_kernel, grid, dim3(256), 0, s, A, lda, m, n, X, ldx, nrhs, Rv, ldr, fro2);
   return hipGetLastError();
 }
 
