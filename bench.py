@@ -56,9 +56,9 @@ TILE_RW = (2.0, 2.5, 4.0, 5.0, 2.0, 4.5)
 # (calibrated by a plain copy; profiles/hbm_traffic_square10240_nb256.md),
 # keyed by (workload, update precision, tree, BS, kernels, nb) and valid for
 # the executor sources with the given SHA-256 prefix only.
-TRAFFIC = {("square", "f32", "flat", 1, "ts", 256): (62.24e9, "f2c510bc3b5d986c"),
-           ("square", "bf16", "flat", 1, "ts", 256): (58.03e9, "f2c510bc3b5d986c"),
-           ("square", "f64", "flat", 1, "ts", 256): (84.33e9, "f2c510bc3b5d986c")}
+TRAFFIC = {("square", "f32", "flat", 1, "ts", 256): (62.21e9, "62c138673644114d"),
+           ("square", "bf16", "flat", 1, "ts", 256): (58.03e9, "62c138673644114d"),
+           ("square", "f64", "flat", 1, "ts", 256): (84.12e9, "62c138673644114d")}
 
 
 def executor_source_hash():
