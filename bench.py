@@ -359,6 +359,25 @@ def main():
                 del Ak, Bk
                 torch.cuda.empty_cache()
             line["kappa_sweep"] = sweep
+            # The tall workload (16384 x 2048 N(0,1), same nb and right-hand
+            # sides): Greedy with the TS-hybrid kernels, the fastest FP64 tree
+            # of its tree sweep, for FP64 and the mixed path beside it.
+            mt, nt = 16384, 2048
+            At = tqr_inputs.gaussian_device(mt, nt, tqr_inputs.SEED_C2, dev).t()
+            gt = torch.Generator(device=dev)
+            gt.manual_seed(tqr_inputs.SEED_C3_RHS)
+            Bt = (At @ torch.randn((nrhs, nt), generator=gt, dtype=torch.float64, device=dev).t()).t().contiguous().t()
+            Ft = flops(mt, nt)
+            tall = {"workload": "tall %dx%d N(0,1), nb %d, %d rhs, greedy ts" % (mt, nt, nb, nrhs)}
+            for u in ("f64", args.upd):
+                r = measure(u, u != "f64", ("greedy", 1, "ts"), At, Bt, args.steps, args.warmup)
+                tall[u] = {"ms_per_step": round(r["ms_per_step"], 3), "exec_ms": round(r["exec_ms"], 3),
+                           "gflops": round(Ft / (r["ms_per_step"] / 1e3) / 1e9, 2),
+                           "backward_err": r["backward_err"], "refine_iters": r["refine_iters"],
+                           "converged": r["converged"]}
+            tall["speedup_vs_fp64"] = round(tall["f64"]["ms_per_step"] / tall[args.upd]["ms_per_step"], 3)
+            line["tall"] = tall
+            del At, Bt
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(nb, TREES[tname], bs, KERNS[kname], args.kappa)
     print(json.dumps(line), flush=True)
