@@ -1215,15 +1215,17 @@ __device__ __forceinline__ void panel_factor(double* Ps, int ldp, int K, double*
 // T factor of the block (forward, columnwise, as LAPACK dlarft):
 // T[j][j] = tau_j and T[0:j, j] = -tau_j T[0:j, 0:j] (V^T v_j)[0:j].
 // Ps holds the block's reflectors explicitly (K rows); the Gram matrix
-// G = V^T V comes from FP64 MFMAs on waves 0..2 (upper 16 x 16 blocks).  The
-// two diagonal 16 x 16 blocks of T follow the recurrence on their own
-// reflectors (waves 0 and 1 side by side, one row of T per lane), and the
-// coupling block is T12 = -T11 (V1^T V2) T22, two 16 x 16 MFMA products.
+// G = V^T V comes from FP64 MFMAs (upper 16 x 16 blocks).  The two diagonal
+// 16 x 16 blocks of T follow the recurrence on their own reflectors (one
+// row of T per lane), and the coupling block is T12 = -T11 (V1^T V2) T22,
+// two 16 x 16 MFMA products.  The Gram blocks run on waves 0..2, the
+// diagonal blocks on waves 0 and 1 and the coupling block on wave 0, with a
+// barrier after each phase.
 template <int NB>
 __device__ __forceinline__ void build_t(const double* Ps, int ldp, int K, const double* tau, double* Gs, double* Ts) {
   const int lane = lane_id(), wave = wave_id(), g = lane >> 4, n = lane & 15;
-  if (wave < 3) {
-    const int ab = (wave == 2) ? 1 : 0, jb = (wave == 0) ? 0 : 1;
+  auto gram = [&](int gb) {
+    const int ab = (gb == 2) ? 1 : 0, jb = (gb == 0) ? 0 : 1;
     d4 a0 = zero4(), a1 = zero4();
     const double* pa = Ps + g + (ab * 16 + n) * ldp;
     const double* pb = Ps + g + (jb * 16 + n) * ldp;
@@ -1233,10 +1235,9 @@ __device__ __forceinline__ void build_t(const double* Ps, int ldp, int K, const 
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) Gs[(ab * 16 + 4 * i + g) + (jb * 16 + n) * IB] = a0[i] + a1[i];
-  }
-  __syncthreads();
-  if (wave < 2 && lane < 16) {
-    const int off = 16 * wave, a = lane;
+  };
+  auto tdiag = [&](int half, int a) {
+    const int off = 16 * half;
     double trow[16];
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
@@ -1248,13 +1249,12 @@ __device__ __forceinline__ void build_t(const double* Ps, int ldp, int K, const 
     }
 #pragma unroll
     for (int j = 0; j < 16; ++j) Ts[(off + a) + (off + j) * IB] = trow[j];
-    if (wave == 1) {
+    if (half == 1) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) Ts[(16 + a) + j * IB] = 0.0;  // T21 = 0
     }
-  }
-  __syncthreads();
-  if (wave == 0) {
+  };
+  auto t12 = [&]() {
     // P = G12 T22 (D layout: P[4 i + g][n] in p[i]), then T12 = -T11 P.
     d4 pm = zero4(), e = zero4();
 #pragma unroll
@@ -1264,7 +1264,12 @@ __device__ __forceinline__ void build_t(const double* Ps, int ldp, int K, const 
     for (int st = 0; st < 4; ++st) e = mfma(Ts[n + (4 * st + g) * IB], pm[st], e);
 #pragma unroll
     for (int i = 0; i < 4; ++i) Ts[(4 * i + g) + (16 + n) * IB] = -e[i];
-  }
+  };
+  if (wave < 3) gram(wave);
+  __syncthreads();
+  if (wave < 2 && lane < 16) tdiag(wave, lane);
+  __syncthreads();
+  if (wave == 0) t12();
   __syncthreads();
 }
 
