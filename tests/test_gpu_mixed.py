@@ -135,6 +135,33 @@ def test_mixed_refined_lstsq_matches_oracle(torch_cuda, upd, kappa, method):
     assert fwd <= 2 * (s[0] / s[-1]) * 1e-12 * np.linalg.norm(A) / s[0]
 
 
+def test_refinement_six_rhs_reported_error_matches_oracle(torch_cuda):
+    """Six right-hand sides (two passes of four through the residual and
+    A^T r kernels) on a 384 x 384 system (a column chunk shorter than the
+    residual kernel's).  With FP32 updates and a loose tolerance the solve
+    stops at its first iterate, whose backward error (about 1e-7) is far
+    above rounding level, so the reported error -- built from ||A||_F
+    accumulated inside the first residual -- equals the oracle's backward
+    error of the returned X to 1e-6 relative (a norm counted twice would be
+    off by sqrt(2)); refined to 1e-12 afterwards."""
+    import paper_1104_4475_amd as tqr
+    torch = torch_cuda
+    n, nb, nrhs = 384, 64, 6
+    _say("refinement with %d right-hand sides, n %d" % (nrhs, n))
+    A = tqr_inputs.conditioned(n, 1e2, 61, 62)
+    B = A @ np.random.default_rng(63).standard_normal((n, nrhs))
+    F = tqr.factor(_gpu(torch, A), nb, trees.GREEDY, 1, dag.KERN_DEFAULT, 1)
+    X, info = F.lstsq(_gpu(torch, B), A0=_gpu(torch, A), tol=1e-3, method=3, raise_on_noconv=True)
+    eta = max(tiled.backward_error(A, X.cpu().numpy(), B))
+    _say("  first iterate: reported %.6e, oracle %.6e" % (info["backward_err"], eta))
+    assert info["converged"] and eta > 1e-10
+    assert abs(info["backward_err"] - eta) <= 1e-6 * eta
+    X, info = F.lstsq(_gpu(torch, B), A0=_gpu(torch, A), tol=1e-12, method=0, raise_on_noconv=True)
+    eta = max(tiled.backward_error(A, X.cpu().numpy(), B))
+    _say("  refined: iters %d reported %.2e oracle %.2e" % (info["iters"], info["backward_err"], eta))
+    assert info["converged"] and eta <= 1e-12
+
+
 @pytest.mark.parametrize("upd", [1, 2])
 def test_mixed_full_size_square(torch_cuda, upd):
     """10240 x 10240 (40 x 40 tiles of 256), kappa 1e2, 4 right-hand sides:
