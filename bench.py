@@ -56,9 +56,9 @@ TILE_RW = (2.0, 2.5, 4.0, 5.0, 2.0, 4.5)
 # (calibrated by a plain copy; profiles/hbm_traffic_square10240_nb256.md),
 # keyed by (workload, update precision, tree, BS, kernels, nb) and valid for
 # the executor sources with the given SHA-256 prefix only.
-TRAFFIC = {("square", "f32", "flat", 1, "ts", 256): (60.70e9, "09be5b4dc7226389"),
-           ("square", "bf16", "flat", 1, "ts", 256): (58.31e9, "09be5b4dc7226389"),
-           ("square", "f64", "flat", 1, "ts", 256): (84.19e9, "09be5b4dc7226389")}
+TRAFFIC = {("square", "f32", "flat", 1, "ts", 256): (58.82e9, "ea5e686e0971b03b"),
+           ("square", "bf16", "flat", 1, "ts", 256): (57.61e9, "ea5e686e0971b03b"),
+           ("square", "f64", "flat", 1, "ts", 256): (84.06e9, "ea5e686e0971b03b")}
 
 
 def executor_source_hash():

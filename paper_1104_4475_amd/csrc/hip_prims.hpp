@@ -37,7 +37,25 @@ __device__ __forceinline__ f4 mfma32(float a, float b, f4 c) {
 __device__ __forceinline__ f4 mfmabf(bf8 a, bf8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
-__device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
+// The lane index, opaque to the optimizer: the empty asm statement keeps
+// lane-derived addresses from being hoisted out of the persistent task loops,
+// where they would stay live across every task and spill to scratch (they
+// are recomputed at each use instead).
+__device__ __forceinline__ int lane_id() {
+  int v = threadIdx.x & 63;
+  asm volatile("" : "+v"(v));
+  return v;
+}
+// The lane index for the FP64 update and prefetch helpers: plain at
+// NB >= 128, where the FP64 executor holds its addresses without spilling
+// and the opaque index would only add recomputation; opaque below.
+template <int NB>
+__device__ __forceinline__ int lane_nb() {
+  if constexpr (NB >= 128)
+    return threadIdx.x & 63;
+  else
+    return lane_id();
+}
 
 // Tile, T and right-hand-side data move with device-coherent (sc1) loads and
 // stores.  The eight XCDs have L2 caches that are not coherent with each

@@ -156,7 +156,7 @@ struct Prefetch {
 
 template <int NB, int MODE>
 __device__ __forceinline__ void prefetch_load(Prefetch<NB>& pf, const double* src, int K, int c0, const double* T) {
-  const int lane = lane_id(), wave = wave_id();
+  const int lane = lane_nb<NB>(), wave = wave_id();
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int m = wave + NWAVES * c;
@@ -176,7 +176,7 @@ __device__ __forceinline__ void prefetch_load(Prefetch<NB>& pf, const double* sr
 
 template <int NB>
 __device__ __forceinline__ void prefetch_store(const Prefetch<NB>& pf, double* Vs, int ldv, int K, double* Ts) {
-  const int lane = lane_id(), wave = wave_id();
+  const int lane = lane_nb<NB>(), wave = wave_id();
 #pragma unroll
   for (int c = 0; c < 4; ++c) {
     const int m = wave + NWAVES * c;
@@ -199,7 +199,7 @@ enum { V_UNM = 0, V_TS = 1, V_TT = 2 };
 // 16 rb + 4 i + g.  Load / store rows of blocks rb in [lo, hi).
 template <int NB>
 __device__ __forceinline__ void load_cols(d4 (&acc)[NB / 32], const double* C, int lo, int hi) {
-  const int lane = lane_id(), g = lane >> 4, h = wave_id() >> 2;
+  const int lane = lane_nb<NB>(), g = lane >> 4, h = wave_id() >> 2;
 #pragma unroll
   for (int j = 0; j < NB / 32; ++j) {
     const int rb = 2 * j + h;
@@ -213,7 +213,7 @@ __device__ __forceinline__ void load_cols(d4 (&acc)[NB / 32], const double* C, i
 }
 template <int NB>
 __device__ __forceinline__ void store_cols(const d4 (&acc)[NB / 32], double* C, int lo, int hi) {
-  const int lane = lane_id(), g = lane >> 4, h = wave_id() >> 2;
+  const int lane = lane_nb<NB>(), g = lane >> 4, h = wave_id() >> 2;
 #pragma unroll
   for (int j = 0; j < NB / 32; ++j) {
     const int rb = 2 * j + h;
@@ -261,7 +261,7 @@ __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); 
 template <int NB, int VAR>
 __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const double* Ts, int c0, d4 (&acc)[NB / 32],
                                             double* c1, const d4 (&c1v)[2], bool active, int trans, double* wx) {
-  const int lane = lane_id(), g = lane >> 4, n = lane & 15;
+  const int lane = lane_nb<NB>(), g = lane >> 4, n = lane & 15;
   const int h = wave_id() >> 2;
   const int rb_lo = (VAR == V_UNM) ? (c0 >> 4) : 0;
   const int rb_hi = (VAR == V_TT) ? ((c0 + IB) >> 4) : (NB >> 4);
@@ -1467,7 +1467,7 @@ __device__ __forceinline__ void unmqr_task(const double* V, const double* T, dou
   constexpr int ldv = Smem<NB>::LDP;
   double* Vs = sm + Smem<NB>::PS;
   double* Ts = sm + Smem<NB>::TS;
-  const int lane = lane_id(), gw = wave_id() & 3;
+  const int lane = lane_nb<NB>(), gw = wave_id() & 3;
   double* wx = sm + Smem<NB>::WX + gw * 16 * 64;
   const int mycol = col0 + gw * 16;
   const bool active = mycol < ncol;
@@ -1525,7 +1525,7 @@ constexpr int narrow_nj() { return (NB / 16 + NWAVES - 1) / NWAVES; }
 
 template <int NB>
 __device__ __forceinline__ void load_rows_narrow(d4 (&acc)[narrow_nj<NB>()], const double* Bc, int lo, int hi) {
-  const int lane = lane_id(), g = lane >> 4, wave = wave_id();
+  const int lane = lane_nb<NB>(), g = lane >> 4, wave = wave_id();
 #pragma unroll
   for (int j = 0; j < narrow_nj<NB>(); ++j) {
     const int rb = wave + NWAVES * j;
@@ -1539,7 +1539,7 @@ __device__ __forceinline__ void load_rows_narrow(d4 (&acc)[narrow_nj<NB>()], con
 }
 template <int NB>
 __device__ __forceinline__ void store_rows_narrow(const d4 (&acc)[narrow_nj<NB>()], double* Bc, int lo, int hi) {
-  const int lane = lane_id(), g = lane >> 4, wave = wave_id();
+  const int lane = lane_nb<NB>(), g = lane >> 4, wave = wave_id();
 #pragma unroll
   for (int j = 0; j < narrow_nj<NB>(); ++j) {
     const int rb = wave + NWAVES * j;
@@ -1555,7 +1555,7 @@ __device__ __forceinline__ void store_rows_narrow(const d4 (&acc)[narrow_nj<NB>(
 template <int NB, int VAR>
 __device__ __forceinline__ void apply_block_narrow(const double* Vs, int ldv, const double* Ts, int c0,
                                                    d4 (&acc)[narrow_nj<NB>()], double* c1, int trans, double* wx) {
-  const int lane = lane_id(), g = lane >> 4, n = lane & 15, wave = wave_id();
+  const int lane = lane_nb<NB>(), g = lane >> 4, n = lane & 15, wave = wave_id();
   const int rb_lo = (VAR == V_UNM) ? (c0 >> 4) : 0;
   const int rb_hi = (VAR == V_TT) ? ((c0 + IB) >> 4) : (NB >> 4);
   const int vbase = (VAR == V_UNM) ? c0 : 0;
@@ -1652,7 +1652,7 @@ __device__ __forceinline__ void apply_narrow_task(int kind, const double* V, con
   double* Vs = sm + Smem<NB>::PS;
   double* Ts = sm + Smem<NB>::TS;
   double* wx = sm + Smem<NB>::WX;
-  const int lane = lane_id();
+  const int lane = lane_nb<NB>();
   const bool ge = kind == D_APPLY_GE, tt = kind == D_APPLY_TT;
   double* c1 = ge ? nullptr : B1 + (lane & 15) * NB;
   double* Bc = B2 + (lane & 15) * NB;
@@ -1686,7 +1686,7 @@ __device__ __forceinline__ void pair_mqr_task(const double* V2, const double* T,
   constexpr int ldv = Smem<NB>::LDP;
   double* Vs = sm + Smem<NB>::PS;
   double* Ts = sm + Smem<NB>::TS;
-  const int lane = lane_id(), gw = wave_id() & 3;
+  const int lane = lane_nb<NB>(), gw = wave_id() & 3;
   double* wx = sm + Smem<NB>::WX + gw * 16 * 64;
   const int mycol = col0 + gw * 16;
   const bool active = mycol < ncol;
