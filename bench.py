@@ -56,9 +56,9 @@ TILE_RW = (2.0, 2.5, 4.0, 5.0, 2.0, 4.5)
 # (calibrated by a plain copy; profiles/hbm_traffic_square10240_nb256.md),
 # keyed by (workload, update precision, tree, BS, kernels, nb) and valid for
 # the executor sources with the given SHA-256 prefix only.
-TRAFFIC = {("square", "f32", "flat", 1, "ts", 256): (58.82e9, "ea5e686e0971b03b"),
-           ("square", "bf16", "flat", 1, "ts", 256): (57.61e9, "ea5e686e0971b03b"),
-           ("square", "f64", "flat", 1, "ts", 256): (84.06e9, "ea5e686e0971b03b")}
+TRAFFIC = {("square", "f32", "flat", 1, "ts", 256): (58.44e9, "2b079dbf6a3a457d"),
+           ("square", "bf16", "flat", 1, "ts", 256): (57.58e9, "2b079dbf6a3a457d"),
+           ("square", "f64", "flat", 1, "ts", 256): (84.43e9, "2b079dbf6a3a457d")}
 
 
 def executor_source_hash():

@@ -261,7 +261,7 @@ __device__ __forceinline__ void wait_vm() { __builtin_amdgcn_s_waitcnt(0x0F70); 
 template <int NB, int VAR>
 __device__ __forceinline__ void apply_block(const double* Vs, int ldv, const double* Ts, int c0, d4 (&acc)[NB / 32],
                                             double* c1, const d4 (&c1v)[2], bool active, int trans, double* wx) {
-  const int lane = lane_nb<NB>(), g = lane >> 4, n = lane & 15;
+  const int lane = lane_id(), g = lane >> 4, n = lane & 15;
   const int h = wave_id() >> 2;
   const int rb_lo = (VAR == V_UNM) ? (c0 >> 4) : 0;
   const int rb_hi = (VAR == V_TT) ? ((c0 + IB) >> 4) : (NB >> 4);
